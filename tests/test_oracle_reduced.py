@@ -1,0 +1,242 @@
+"""Pins for the oracle's reduced gradient, Gauss-Newton Hessian matvec, PCG
+and GN loop (Sec. 2.2, 2.3.2, Algorithms "outer iteration" and "inner
+iteration"): closed forms at v = 0 and at the inverse-crime point,
+symmetry and positivity, brute-force assembly on tiny grids, finite
+differences under refinement, and solver behaviour."""
+import numpy as np
+import pytest
+
+from oracle import core, prep, solver
+from paper_1808_04487_amd import synth
+
+
+def smooth_field(g, seed, amp=1.0):
+    x1, x2, x3 = g.coords()
+    r = np.random.default_rng(seed).uniform(0, 2 * np.pi, 6)
+    return amp * np.stack(np.broadcast_arrays(
+        np.cos(x1 + r[0]) * np.sin(x2 + r[1]) + 0 * x3,
+        np.cos(x2 + x3 + r[2]) + 0.5 * np.sin(x1 + r[3]) + 0 * x1,
+        np.sin(x3 - x1 + r[4]) * np.cos(x2 + r[5]) + 0 * x2))
+
+
+def problem(n, div_mode=core.DIV_NONE, reg=core.REG_H1, beta_v=1e-2, beta_w=0.0, order=3):
+    g = core.Grid(n)
+    mT = synth.trig_template(g.n)
+    vs = synth.trig_velocity(g.n)
+    mR = prep.transport(g, mT, vs, order=order)
+    p = core.Params(g.n, nt=4, order=order, reg=reg, div_mode=div_mode, beta_v=beta_v,
+                    beta_w=beta_w)
+    return g, core.Registration(p, mT, mR), vs
+
+
+@pytest.mark.parametrize("div_mode", [core.DIV_NONE, core.DIV_NEAR, core.DIV_LERAY])
+def test_closed_forms_at_zero_velocity(div_mode):
+    """At v = 0: X = Y = 0, m^j = mT, l^j = mR - mT, sum_j a_j = 1, so
+    g(0) = K[(mR - mT) grad mT] and H vt = beta_v A vt + K[(grad mT . vt) grad mT]."""
+    g, R, _ = problem((12, 16, 10), div_mode=div_mode, beta_w=1.0)
+    R.set_velocity(np.zeros((3,) + g.n))
+    bv, bw = R.p.beta_v, R.p.beta_w
+    gm = core.grad(g, R.mT)
+    expect_g = core.apply_K(g, (R.mR - R.mT) * gm, div_mode, bv, bw)
+    assert np.abs(R.gradient() - expect_g).max() < 1e-13
+    vt = smooth_field(g, 1)
+    expect_H = bv * core.apply_A(g, vt, R.p.reg) + core.apply_K(
+        g, np.sum(gm * vt, axis=0) * gm, div_mode, bv, bw)
+    assert np.abs(R.hessian_matvec(vt) - expect_H).max() < 1e-13
+
+
+@pytest.mark.parametrize("div_mode,reg", [(core.DIV_NONE, core.REG_H2),
+                                          (core.DIV_NEAR, core.REG_H1)])
+def test_inverse_crime_gradient(div_mode, reg):
+    """mR is the template transported by v* with the same scheme, so at v*
+    the mismatch vanishes, l = 0 and g(v*) = beta_v A v*."""
+    g, R, vs = problem((16, 16, 16), div_mode=div_mode, reg=reg, beta_w=1.0)
+    R.set_velocity(vs)
+    J, mism, regterm = R.objective()
+    assert mism == 0.0
+    expect = R.p.beta_v * core.apply_A(g, vs, reg)
+    assert np.abs(R.gradient() - expect).max() < 1e-15
+
+
+def test_hessian_symmetric_and_psd_at_zero_and_integer_shift():
+    """With K = I the GN Hessian is symmetric exactly when interpolation is a
+    permutation (v = 0 or an integer shift per step): the backward gather is
+    its transpose and the trapezoidal weights pair up."""
+    n = (10, 12, 8)
+    g = core.Grid(n)
+    rng = np.random.default_rng(2)
+    mT = core.gauss_smooth(g, rng.standard_normal(n), 1.0)
+    mR = core.gauss_smooth(g, rng.standard_normal(n), 1.0)
+    p = core.Params(n, reg=core.REG_H1, div_mode=core.DIV_NONE, beta_v=1e-3)
+    R = core.Registration(p, mT, mR)
+    s = (1, -1, 2)
+    vshift = np.stack([np.full(n, s[a] * g.h[a] * 4) for a in range(3)])
+    u, w = smooth_field(g, 3), smooth_field(g, 4)
+    for v in (np.zeros((3,) + n), vshift):
+        R.set_velocity(v)
+        Hu, Hw = R.hessian_matvec(u), R.hessian_matvec(w)
+        a, b = g.inner(Hu, w), g.inner(u, Hw)
+        assert abs(a - b) < 1e-12 * abs(a)
+        # data term equals |mt(1)|^2 >= 0
+        data = g.inner(Hu, u) - p.beta_v * g.inner(core.apply_A(g, u, p.reg), u)
+        mt = R.incremental_state(u)
+        assert abs(data - g.inner(mt, mt)) < 1e-12 * abs(data)
+
+
+def test_hessian_asymmetry_shrinks_with_refinement():
+    asym = []
+    for n in (16, 32):
+        g, R, vs = problem((n,) * 3)
+        R.set_velocity(0.5 * vs)
+        u, w = smooth_field(g, 5), smooth_field(g, 6)
+        a, b = g.inner(R.hessian_matvec(u), w), g.inner(u, R.hessian_matvec(w))
+        asym.append(abs(a - b) / abs(a))
+    assert asym[1] < asym[0]
+    assert asym[1] < 1e-3
+
+
+@pytest.mark.parametrize("div_mode", [core.DIV_NONE, core.DIV_LERAY])
+def test_brute_force_assembly_tiny_grid(div_mode):
+    """Assemble H column by column at 4^3 (192 unknowns) at v = 0: symmetric
+    (in the divergence-free subspace for Leray), positive semi-definite, and
+    PCG reaches numpy's dense solution."""
+    n = (4, 4, 4)
+    g = core.Grid(n)
+    x1, x2, x3 = g.coords()
+    mT = np.sin(x1) * np.cos(x2) + 0.5 * np.sin(x3) + 0 * x1
+    mR = np.cos(x1) * np.sin(x3) + 0 * x2
+    p = core.Params(n, reg=core.REG_H1, div_mode=div_mode, beta_v=1e-1)
+    R = core.Registration(p, mT, mR)
+    R.set_velocity(0.1 * smooth_field(g, 7) if div_mode == core.DIV_NONE else np.zeros((3,) + n))
+    dim = 3 * g.N
+    H = np.empty((dim, dim))
+    for j in range(dim):
+        e = np.zeros(dim)
+        e[j] = 1.0
+        H[:, j] = R.hessian_matvec(e.reshape((3,) + n)).ravel()
+    if div_mode == core.DIV_NONE:
+        # general v at 4^3: symmetric up to discretisation error only; check
+        # the v = 0 matrix exactly instead
+        R.set_velocity(np.zeros((3,) + n))
+        for j in range(dim):
+            e = np.zeros(dim)
+            e[j] = 1.0
+            H[:, j] = R.hessian_matvec(e.reshape((3,) + n)).ravel()
+        Hs = H
+    else:
+        P = np.empty((dim, dim))
+        for j in range(dim):
+            e = np.zeros(dim)
+            e[j] = 1.0
+            P[:, j] = core.apply_K(g, e.reshape((3,) + n), core.DIV_LERAY).ravel()
+        Hs = P.T @ H @ P
+    assert np.abs(Hs - Hs.T).max() < 1e-12 * np.abs(Hs).max()
+    ev = np.linalg.eigvalsh(0.5 * (Hs + Hs.T))
+    assert ev.min() > -1e-12 * ev.max()
+    # PCG against the dense solve (K = I case: H is SPD)
+    if div_mode == core.DIV_NONE:
+        rhs = smooth_field(g, 8)
+        x, it, rel = solver.pcg(R.hessian_matvec, R.precond, rhs, 1e-13, 500, g.inner)
+        xd = np.linalg.solve(H, rhs.ravel())
+        assert np.abs(x.ravel() - xd).max() < 1e-10 * np.abs(xd).max()
+
+
+def test_pcg_one_iteration_for_constant_template():
+    """Constant mT has grad m = 0, so H = H_reg and M^{-1} = H_reg^{-1} is
+    exact: PCG converges in one iteration."""
+    n = (8, 8, 8)
+    g = core.Grid(n)
+    p = core.Params(n, reg=core.REG_H2, div_mode=core.DIV_NONE, beta_v=1e-2)
+    R = core.Registration(p, np.full(n, 0.3), synth.trig_template(n))
+    R.set_velocity(smooth_field(g, 9, 0.2))
+    rhs = smooth_field(g, 10)
+    rhs -= rhs.mean(axis=(1, 2, 3), keepdims=True)
+    x, it, rel = solver.pcg(R.hessian_matvec, R.precond, rhs, 1e-12, 100, g.inner)
+    assert it == 1 and rel < 1e-12
+
+
+def test_gradient_matches_finite_differences_under_refinement():
+    """Optimize-then-discretize: <g, w> matches the central difference of J
+    only up to discretisation error in space and time, which falls when h
+    and dt are refined together (16^3, nt=4 -> 32^3, nt=8)."""
+    rel = []
+    for n, nt in ((16, 4), (32, 8)):
+        g, R, vs = problem((n,) * 3)
+        R.p.nt = nt
+        R.a = core.time_weights(nt)
+        v = 0.4 * smooth_field(g, 11)
+        w = smooth_field(g, 12)
+        R.set_velocity(v)
+        gw = g.inner(R.gradient(), w)
+        eps = 1e-4
+        R.set_velocity(v + eps * w)
+        Jp = R.objective()[0]
+        R.set_velocity(v - eps * w)
+        Jm = R.objective()[0]
+        fd = (Jp - Jm) / (2 * eps)
+        rel.append(abs(gw - fd) / abs(fd))
+    assert rel[0] < 5e-2
+    assert rel[1] < 5e-3
+    assert rel[1] < rel[0] / 4, rel
+
+
+def test_near_incompressible_gradient_is_K_times_true_gradient():
+    """With the penalty on w = div v, g = K grad J: check <g, w> against
+    finite differences of J for a divergence-free w (K w = w there)."""
+    g, R, vs = problem((24,) * 3, div_mode=core.DIV_NEAR, beta_w=1.0)
+    v = 0.3 * smooth_field(g, 13)
+    w = core.apply_K(g, smooth_field(g, 14), core.DIV_LERAY)
+    R.set_velocity(v)
+    gw = g.inner(R.gradient(), w)
+    eps = 1e-4
+    R.set_velocity(v + eps * w)
+    Jp = R.objective()[0]
+    R.set_velocity(v - eps * w)
+    Jm = R.objective()[0]
+    fd = (Jp - Jm) / (2 * eps)
+    assert abs(gw - fd) / abs(fd) < 3e-2
+
+
+def test_hessian_matches_gradient_differences_at_inverse_crime():
+    """At v* the adjoint vanishes, so the GN Hessian is the full Hessian and
+    H w matches (g(v*+eps w) - g(v*-eps w)) / (2 eps) up to discretisation
+    error, which falls under refinement."""
+    rel = []
+    for n in (16, 32):
+        g, R, vs = problem((n,) * 3)
+        w = smooth_field(g, 15)
+        R.set_velocity(vs)
+        Hw = R.hessian_matvec(w)
+        eps = 1e-4
+        R.set_velocity(vs + eps * w)
+        gp = R.gradient()
+        R.set_velocity(vs - eps * w)
+        gm = R.gradient()
+        fd = (gp - gm) / (2 * eps)
+        rel.append(g.norm(Hw - fd) / g.norm(fd))
+    assert rel[0] < 5e-2
+    assert rel[1] < rel[0] / 4
+
+
+def test_gn_solve_synthetic_problem():
+    """The paper's synthetic problem (Sec. 4.2) with H1-div, beta_v = 1e-2,
+    beta_w = 1: a handful of GN iterations (the paper reports 3-4 for this
+    family), J non-increasing, and the PDE-solve counter consistent."""
+    g, R, vs = problem((16,) * 3, div_mode=core.DIV_NEAR, beta_w=1.0)
+    v, rep = solver.gn_solve(R, np.zeros((3,) + g.n), grad_rtol=1e-2)
+    assert rep.status == solver.CONVERGED_REL
+    assert 2 <= rep.gn_iters <= 6
+    Js = [h["J"] for h in rep.history]
+    assert all(Js[i + 1] <= Js[i] for i in range(len(Js) - 1))
+    assert rep.gnorm_rel <= 1e-2
+    assert rep.mismatch_rel < 0.2
+    # counters: 2 (first state+adjoint) + 2 per matvec + 1 per trial + 1 adjoint per step
+    assert rep.pde_solves == 2 + 2 * rep.matvecs + rep.ls_trials + rep.gn_iters
+
+
+def test_gn_line_search_failure_keeps_velocity():
+    g, R, vs = problem((8,) * 3)
+    v0 = 0.1 * smooth_field(g, 16)
+    v, rep = solver.gn_solve(R, v0, grad_rtol=1e-12, max_ls=0)
+    assert rep.status == solver.LS_FAIL
+    assert np.array_equal(v, v0)
