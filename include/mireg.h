@@ -1,0 +1,197 @@
+/*
+ * mireg: reduced-space Gauss-Newton-Krylov registration hot path on one
+ * MI355X (gfx950), after Mang, Gholami, Davatzikos and Biros, "CLAIRE: A
+ * distributed-memory solver for constrained large deformation diffeomorphic
+ * image registration" (arXiv 1808.04487).
+ *
+ * Problem (Sec. 2.1, eq. "varopt"): find a stationary velocity v on the
+ * periodic box (0, 2 pi)^3 minimising
+ *     J(v) = 1/2 ||m(1) - mR||^2 + beta_v/2 <A v, v> [+ beta_w/2 (||grad w||^2 + ||w||^2)]
+ * where m solves dm/dt + grad m . v = 0, m(0) = mT, and w = div v.
+ *
+ * Conventions shared by every entry point:
+ *  - Grid: n = (n1, n2, n3), each a power of two in [8, 512]; point
+ *    (i1, i2, i3) sits at x_a = 2 pi i_a / n_a.  Scalar fields are dense
+ *    C-ordered [n1][n2][n3] arrays (x3 fastest); vector fields are
+ *    [3][n1][n2][n3].  Element type is the context dtype (float or double).
+ *  - Memory: every field pointer is a DEVICE pointer owned by the caller,
+ *    borrowed for the duration of the call only.  Scalars (J, norms, counts)
+ *    are HOST pointers.  mireg_set_images / mireg_set_velocity copy their
+ *    input into library-owned device memory.
+ *  - Streams: all work is enqueued on the stream given to mireg_create
+ *    (a hipStream_t, NULL for the default stream).  Calls returning host
+ *    scalars synchronise that stream before returning.  A context is not
+ *    thread safe; use one context per host thread.
+ *  - Errors: functions return MIREG_OK (0) or a negative MIREG_E_* code;
+ *    mireg_last_error gives a message.  Non-convergence of a solve is not an
+ *    error: it is reported in mireg_report.status.
+ *  - Inner products and norms are the trapezoidal L2 ones of the grid,
+ *    h1 h2 h3 sum(a b), accumulated in FP64 for both dtypes.
+ */
+#ifndef MIREG_H
+#define MIREG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MIREG_OK = 0,
+    MIREG_E_ARG = -1,       /* invalid argument or NULL pointer */
+    MIREG_E_SHAPE = -2,     /* unsupported grid size */
+    MIREG_E_STATE = -3,     /* call order violated (e.g. no images set) */
+    MIREG_E_HIP = -4,       /* a HIP runtime call failed */
+    MIREG_E_NOMEM = -5,     /* device allocation failed */
+    MIREG_E_NONFINITE = -6  /* NaN or Inf in an input */
+};
+
+typedef enum { MIREG_F32 = 0, MIREG_F64 = 1 } mireg_dtype;
+
+/* Regularisation operator A = B*B (Sec. 2.1): H1 seminorm B = grad gives
+ * A = -Lap; H2 seminorm B = -Lap gives A = Lap^2. */
+typedef enum { MIREG_H1 = 1, MIREG_H2 = 2 } mireg_reg;
+
+/* Projection K of the reduced gradient (Sec. 2.2): identity without a
+ * divergence constraint, the near-incompressible operator
+ * K = I - grad (beta_v (beta_w(-Lap + I))^{-1} + I)^{-1} Lap^{-1} div, or the
+ * Leray projection I - grad Lap^{-1} div of the incompressible model. */
+typedef enum { MIREG_DIV_NONE = 0, MIREG_DIV_NEAR = 1, MIREG_DIV_LERAY = 2 } mireg_div;
+
+typedef struct {
+    int n[3];           /* grid size, powers of two in [8, 512] */
+    int nt;             /* number of time steps (the paper uses 4), 1..64 */
+    int interp_order;   /* 3: tricubic Lagrange (paper), 1: trilinear */
+    int reg;            /* mireg_reg */
+    int div;            /* mireg_div */
+    double beta_v;      /* > 0, weight of the velocity regulariser */
+    double beta_w;      /* >= 0, weight of the divergence penalty (DIV_NEAR) */
+    int dtype;          /* mireg_dtype of every field passed in or out */
+} mireg_params;
+
+typedef struct {
+    double grad_rtol;   /* stop when ||g_k|| <= grad_rtol ||g_0|| (paper: 5e-2) */
+    double grad_atol;   /* or when ||g_k|| <= grad_atol (paper: 1e-6) */
+    int max_gn;         /* GN iteration cap (50) */
+    int max_pcg;        /* PCG iteration cap per Newton step (100) */
+    double armijo_c1;   /* sufficient-decrease constant (1e-4) */
+    int max_ls;         /* line-search trials, step halved each time (10) */
+    int log_level;      /* 0 silent, 1 one line per GN iteration on stderr */
+} mireg_solve_opts;
+
+enum {
+    MIREG_CONVERGED_REL = 1,
+    MIREG_CONVERGED_ABS = 2,
+    MIREG_MAXIT = 3,
+    MIREG_LS_FAIL = 4
+};
+
+typedef struct {
+    int status;         /* MIREG_CONVERGED_REL / _ABS / MIREG_MAXIT / MIREG_LS_FAIL */
+    int gn_iters;       /* accepted GN steps */
+    int matvecs;        /* Hessian matvecs (= PCG iterations) */
+    int pde_solves;     /* state/adjoint solves: 1 each, 2 per matvec */
+    int pcg_iters;
+    int ls_trials;      /* objective evaluations in the line search */
+    double J0, J;       /* objective at the initial and final velocity */
+    double mismatch_rel;/* ||m(1) - mR||^2 / ||mT - mR||^2 at the final velocity */
+    double gnorm0, gnorm, gnorm_rel;
+    double seconds;     /* wall time of the solve */
+} mireg_report;
+
+typedef struct mireg_ctx mireg_ctx;
+
+/* Fill *p / *o with the defaults named above (n and beta_v still to set). */
+void mireg_default_params(mireg_params *p);
+void mireg_default_solve_opts(mireg_solve_opts *o);
+
+/* Create a context for one problem size on the current HIP device and
+ * allocate all of its device workspace (about 75 fields).  `stream` is a
+ * hipStream_t or NULL.  Returns MIREG_E_SHAPE for unsupported sizes,
+ * MIREG_E_ARG for invalid parameters, MIREG_E_NOMEM if allocation fails. */
+int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out);
+int mireg_destroy(mireg_ctx *ctx);
+const char *mireg_last_error(const mireg_ctx *ctx);
+/* Bytes of device memory the context holds. */
+size_t mireg_workspace_bytes(const mireg_ctx *ctx);
+
+/* Template mT (transported from t = 0) and reference mR (Sec. 2.1), scalar
+ * fields.  Copied; checked for NaN/Inf (MIREG_E_NONFINITE). */
+int mireg_set_images(mireg_ctx *ctx, const void *mT, const void *mR);
+
+/* Current velocity v, vector field.  Copied; checked for NaN/Inf; every
+ * cached quantity that depends on v is invalidated.  The initial velocity
+ * of a new context is zero. */
+int mireg_set_velocity(mireg_ctx *ctx, const void *v);
+int mireg_get_velocity(mireg_ctx *ctx, void *v);
+
+/* Objective (eq. "varopt:objective") at the current v: *J = *mismatch +
+ * *reg (host doubles; any may be NULL).  One state solve (Sec. 2.3.1). */
+int mireg_objective(mireg_ctx *ctx, double *J, double *mismatch, double *reg);
+
+/* Reduced gradient g = beta_v A v + K[int_0^1 lambda grad m dt] (eq.
+ * "reduced-gradient") at the current v, written to the device vector field
+ * g; *gnorm (may be NULL) gets its L2 norm.  State and adjoint solves. */
+int mireg_gradient(mireg_ctx *ctx, void *g, double *gnorm);
+
+/* Gauss-Newton Hessian matvec (eqs. "inc-state", "inc-adj",
+ * "hessian-matvec", GN form of Sec. 2.3.2): Hvt = beta_v A vt +
+ * K[int_0^1 lt grad m dt] at the current v.  vt and Hvt are device vector
+ * fields and must not alias.  Incremental state and adjoint solves; no host
+ * synchronisation. */
+int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt);
+
+/* Spectral preconditioner z = (beta_v A)^{-1} r with the zero singular value
+ * of the regulariser set to one (Sec. 2.3.3).  r and z may alias. */
+int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z);
+
+/* PCG (Algorithm "inner iteration") for H x = rhs at the current v, x0 = 0;
+ * stops when ||r|| <= rtol ||rhs||, after maxit iterations, or on
+ * non-positive curvature.  *iters and *relres (host, may be NULL). */
+int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit,
+                    int *iters, double *relres);
+
+/* Inexact GN-Krylov solve (Algorithm "outer iteration", Sec. 2.3.2) with
+ * forcing eps_H = min(0.5, sqrt(||g_k||/||g_0||)) and Armijo line search,
+ * starting from v_inout (device vector field; a warm start or zeros) and
+ * writing the final velocity back to it.  opts may be NULL (defaults).
+ * On return the context's current velocity is the final one. */
+int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts,
+                   mireg_report *rep);
+
+/* Individual operators for tests and input preparation.  `in` and `out`
+ * are device fields of the context dtype; `arg` is an op parameter. */
+enum {
+    MIREG_OP_GRAD = 1,           /* scalar -> vector, spectral gradient */
+    MIREG_OP_DIV = 2,            /* vector -> scalar, spectral divergence */
+    MIREG_OP_LAPLACE = 3,        /* scalar -> scalar, Lap */
+    MIREG_OP_APPLY_A = 4,        /* vector -> vector, A (H1 or H2 of the context) */
+    MIREG_OP_APPLY_K = 5,        /* vector -> vector, K of the context */
+    MIREG_OP_LERAY = 6,          /* vector -> vector, Leray projection */
+    MIREG_OP_PRECOND = 7,        /* vector -> vector, (beta_v A)^{-1}, zero mode -> 1 */
+    MIREG_OP_GAUSS = 8,          /* scalar -> scalar, Gaussian, arg = sigma in cells */
+    MIREG_OP_DEPARTURE_X = 9,    /* vector v -> vector displacement (cells) of X */
+    MIREG_OP_DEPARTURE_Y = 10,   /* vector v -> vector displacement (cells) of Y */
+    MIREG_OP_TRANSPORT_STATE = 11,/* scalar mT -> scalar m(1) at the current v */
+    MIREG_OP_INTERP = 12,        /* scalar f -> scalar I[f](x + d): `in` holds f
+                                    followed by the displacement field d */
+    MIREG_OP_RESCALE01 = 13,     /* scalar -> scalar, (u - min u)/(max u - min u) */
+    MIREG_OP_SCALE_MAXNORM = 14  /* vector -> vector scaled so max_x |v(x)|_2 = arg */
+};
+int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg);
+
+/* Per-phase GPU time accumulated since the last reset (milliseconds), for
+ * the FFT / interpolation split the paper reports. */
+typedef struct {
+    double fft_ms, interp_ms, other_ms;
+    long launches;
+} mireg_timers;
+int mireg_timers_enable(mireg_ctx *ctx, int on);
+int mireg_timers_read(mireg_ctx *ctx, mireg_timers *t, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIREG_H */

@@ -1,0 +1,53 @@
+// Shared device/host helpers of the mireg HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mireg {
+
+// Complex number held in two registers; 8 bytes (float) or 16 bytes (double).
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> make_cx(T r, T i) {
+    cx<T> z;
+    z.re = r;
+    z.im = i;
+    return z;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return make_cx(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return make_cx(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+    return make_cx(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return make_cx(a.re * s, a.im * s); }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return make_cx(a.re, -a.im); }
+// multiply by i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return make_cx(-a.im, a.re); }
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return make_cx(a.im, -a.re); }
+
+// Integer wavenumber of FFT index j on an axis of length n (the Nyquist
+// index n/2 maps to -n/2).
+__device__ __forceinline__ int wavenumber(int j, int n) { return j < n / 2 ? j : j - n; }
+
+// Grid geometry passed by value to kernels.
+struct Grid {
+    int n1, n2, n3;
+    int k3;          // n3/2 + 1, length of the half-spectrum rows
+    long long N;     // n1 n2 n3
+    long long NS;    // n1 n2 k3 (complex entries of one half spectrum)
+};
+
+}  // namespace mireg

@@ -1,0 +1,416 @@
+// Pencil FFT passes and fused pseudospectral operators for gfx950.
+//
+// Spectral derivatives and their inverses follow the paper's scheme (Sec.
+// 2.3.1): forward FFT, pointwise weights, inverse FFT.  A real field
+// [n1][n2][n3] maps to a half spectrum [n1][n2][n3/2+1] (complex).  Each
+// operator is five launches, every one a single coalesced sweep over HBM:
+//   1. x3: real-to-complex along the contiguous axis (an n3/2-point complex
+//      FFT of the even/odd pairs, then the split into n3/2+1 modes),
+//   2. x2: complex transform of the columns at stride n3/2+1,
+//   3. x1: forward transform, the operator's weights for every field at
+//      this mode, inverse transform -- one kernel, the spectrum of the
+//      operator's inputs never goes back to HBM,
+//   4. x2 inverse, 5. x3 complex-to-real.
+// Odd symbols (i k_a: gradient, divergence and the wavenumbers inside K)
+// vanish at the Nyquist index; even symbols (|k|^2, |k|^4, Gaussian) keep it.
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace mireg {
+
+// ---------------------------------------------------------------------------
+// x3 real-to-complex and complex-to-real passes (lines contiguous in memory)
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__global__ __launch_bounds__(kFftThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
+                                                        long long lines,
+                                                        const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, M>;
+    constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
+    using Lay = LayoutRows<W, M>;
+    __shared__ cx<T> lds[Lay::size(M)];
+    const int t = threadIdx.x % TPC, c = threadIdx.x / TPC;
+    const long long line = (long long)blockIdx.x * W + c;
+    const bool ok = line < lines;
+    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * M;
+    cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * (M + 1);
+    cx<T> reg[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) reg[e] = ok ? in[t + TPC * e] : make_cx<T>(0, 0);
+    fft_line<T, M, -1, Lay>(reg, t, c, tw, 2, lds);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) lds[Lay::at(c, t + TPC * e)] = reg[e];
+    __syncthreads();
+    if (ok) {
+        // X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[M-k])/2, O = (Z[k] - conj Z[M-k])/(2i)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int k = t + TPC * e;
+            const cx<T> zk = lds[Lay::at(c, k)];
+            const cx<T> zm = conj(lds[Lay::at(c, (M - k) & (M - 1))]);
+            const cx<T> E = scale(zk + zm, (T)0.5);
+            const cx<T> O = scale(mul_mi(zk - zm), (T)0.5);
+            out[k] = E + tw[k] * O;
+        }
+        if (t == 0) {
+            const cx<T> z0 = lds[Lay::at(c, 0)];
+            out[M] = make_cx<T>(z0.re - z0.im, (T)0);
+        }
+    }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kFftThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs dst,
+                                                        long long lines,
+                                                        const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, M>;
+    constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
+    using Lay = LayoutRows<W, M>;
+    __shared__ cx<T> lds[Lay::size(M)];
+    const int t = threadIdx.x % TPC, c = threadIdx.x / TPC;
+    const long long line = (long long)blockIdx.x * W + c;
+    const bool ok = line < lines;
+    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * (M + 1);
+    cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * M;
+    cx<T> reg[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int k = t + TPC * e;
+        if (ok) {
+            cx<T> xk = in[k], xm = in[M - k];
+            if (k == 0) {  // self-conjugate modes of a real line
+                xk.im = 0;
+                xm.im = 0;
+            }
+            const cx<T> E = xk + conj(xm);
+            const cx<T> O = (xk - conj(xm)) * conj(tw[k]);
+            reg[e] = E + mul_i(O);
+        } else {
+            reg[e] = make_cx<T>(0, 0);
+        }
+    }
+    fft_line<T, M, +1, Lay>(reg, t, c, tw, 2, lds);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) out[t + TPC * e] = reg[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Strided complex pass: columns q < Q, column base (q / inner) * ostride +
+// q % inner, element p of a column at base + p * pstride.
+// ---------------------------------------------------------------------------
+template <typename T, int L, int DIR>
+__global__ __launch_bounds__(kFftThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
+                                                          long long ostride, long long pstride,
+                                                          const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, L>;
+    constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
+    using Lay = LayoutCols<W>;
+    __shared__ cx<T> lds[Lay::size(L)];
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const long long q = (long long)blockIdx.x * W + c;
+    const bool ok = q < Q;
+    const long long base = ok ? (q / inner) * ostride + (q % inner) : 0;
+    cx<T> *p = reinterpret_cast<cx<T> *>(f.p[blockIdx.y]) + base;
+    cx<T> reg[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) reg[e] = ok ? p[(long long)(t + TPC * e) * pstride] : make_cx<T>(0, 0);
+    fft_line<T, L, DIR, Lay>(reg, t, c, tw, 1, lds);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) p[(long long)(t + TPC * e) * pstride] = reg[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x1 pass with the operator in the middle.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct OpConst {
+    int n1, n2, n3, k3;
+    int sym, nf, reg, div;
+    T alpha, beta_v, beta_w;
+    T gs1, gs2, gs3;  // Gaussian: (2 pi sigma / n_a)^2 / 2
+    T norm;           // 1 / (n1 n2 n3)
+};
+
+template <typename T>
+struct Mode {
+    T k1, k2, k3;     // full wavenumbers (Nyquist as -n/2 or n3/2)
+    T t1, t2, t3;     // odd-symbol wavenumbers (Nyquist -> 0)
+};
+
+template <typename T>
+__device__ __forceinline__ T ksq(const Mode<T> &m) { return m.k1 * m.k1 + m.k2 * m.k2 + m.k3 * m.k3; }
+template <typename T>
+__device__ __forceinline__ T reg_symbol(const Mode<T> &m, int reg) {
+    const T s = ksq(m);
+    return reg == 2 ? s * s : s;
+}
+
+template <typename T>
+__device__ __forceinline__ T scalar_symbol(const Mode<T> &m, const OpConst<T> &oc) {
+    switch (oc.sym) {
+        case SYM_A: return oc.alpha * reg_symbol(m, oc.reg);
+        case SYM_AINV: {
+            const T s = oc.alpha * reg_symbol(m, oc.reg);
+            return ksq(m) == (T)0 ? (T)1 : (T)1 / s;  // zero singular value set to one
+        }
+        case SYM_LAP: return -ksq(m);
+        case SYM_GAUSS:
+            return exp(-(oc.gs1 * m.k1 * m.k1 + oc.gs2 * m.k2 * m.k2 + oc.gs3 * m.k3 * m.k3));
+        default: return (T)1;
+    }
+}
+
+// K b per mode: b - c(k) kt (kt . b) / |kt|^2
+template <typename T>
+__device__ __forceinline__ void project(const Mode<T> &m, const OpConst<T> &oc, cx<T> &b1, cx<T> &b2,
+                                        cx<T> &b3) {
+    if (oc.div == 0) return;
+    const T kts = m.t1 * m.t1 + m.t2 * m.t2 + m.t3 * m.t3;
+    if (kts == (T)0) return;
+    T cw = (T)1;
+    if (oc.div == 1) {
+        const T w = oc.beta_w * (kts + (T)1);
+        cw = w / (oc.beta_v + w);
+    }
+    const T f = cw / kts;
+    const cx<T> s = scale(scale(b1, m.t1) + scale(b2, m.t2) + scale(b3, m.t3), f);
+    b1 = b1 - scale(s, m.t1);
+    b2 = b2 - scale(s, m.t2);
+    b3 = b3 - scale(s, m.t3);
+}
+
+template <typename T, int L, int KIND>
+__global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q, OpConst<T> oc,
+                                                       const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, L>;
+    constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
+    using Lay = LayoutCols<W>;
+    __shared__ cx<T> lds[Lay::size(L)];
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const long long q = (long long)blockIdx.x * W + c;
+    const bool ok = q < Q;
+    const long long qq = ok ? q : 0;
+    const long long pstride = Q;
+    // mode of register e: k1 index t + TPC e, column q -> (k2, k3)
+    const int i2 = (int)(qq / oc.k3), i3 = (int)(qq % oc.k3);
+    const T k2 = (T)wavenumber(i2, oc.n2), k3 = (T)i3;
+    const T t2 = (2 * i2 == oc.n2) ? (T)0 : k2, t3 = (2 * i3 == oc.n3) ? (T)0 : k3;
+    auto mode = [&](int e) {
+        Mode<T> m;
+        const int i1 = t + TPC * e;
+        m.k1 = (T)wavenumber(i1, oc.n1);
+        m.t1 = (2 * i1 == oc.n1) ? (T)0 : m.k1;
+        m.k2 = k2;
+        m.t2 = t2;
+        m.k3 = k3;
+        m.t3 = t3;
+        return m;
+    };
+    auto load = [&](int slot, cx<T>(&r)[EPT]) {
+        const cx<T> *p = reinterpret_cast<const cx<T> *>(f.p[slot]) + qq;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r[e] = ok ? p[(long long)(t + TPC * e) * pstride] : make_cx<T>(0, 0);
+    };
+    auto store = [&](int slot, cx<T>(&r)[EPT]) {
+        cx<T> *p = reinterpret_cast<cx<T> *>(f.p[slot]) + qq;
+        if (ok) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) p[(long long)(t + TPC * e) * pstride] = r[e];
+        }
+    };
+    cx<T> reg[EPT];
+    if constexpr (KIND == SPEC_SCALE) {
+        for (int fi = 0; fi < oc.nf; ++fi) {
+            load(fi, reg);
+            fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], scalar_symbol(mode(e), oc) * oc.norm);
+            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            store(fi, reg);
+        }
+    } else if constexpr (KIND == SPEC_GRAD) {
+        cx<T> u[EPT];
+        load(0, u);
+        fft_line<T, L, -1, Lay>(u, t, c, tw, 1, lds);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const Mode<T> m = mode(e);
+                const T ka = a == 0 ? m.t1 : (a == 1 ? m.t2 : m.t3);
+                reg[e] = scale(mul_i(u[e]), ka * oc.norm);
+            }
+            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            store(a, reg);
+        }
+    } else if constexpr (KIND == SPEC_DIV) {
+        cx<T> acc[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc[e] = make_cx<T>(0, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            load(a, reg);
+            fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const Mode<T> m = mode(e);
+                const T ka = a == 0 ? m.t1 : (a == 1 ? m.t2 : m.t3);
+                acc[e] = acc[e] + scale(mul_i(reg[e]), ka * oc.norm);
+            }
+        }
+        fft_line<T, L, +1, Lay>(acc, t, c, tw, 1, lds);
+        store(0, acc);
+    } else {
+        // SPEC_PROJ: K u for u in slots 0..2.
+        // SPEC_TAIL: alpha A u + K b, u in slots 0..2, b in slots 3..5.
+        constexpr int boff = (KIND == SPEC_TAIL) ? 3 : 0;
+        cx<T> b0[EPT], b1[EPT], b2[EPT];
+        load(boff + 0, b0);
+        fft_line<T, L, -1, Lay>(b0, t, c, tw, 1, lds);
+        load(boff + 1, b1);
+        fft_line<T, L, -1, Lay>(b1, t, c, tw, 1, lds);
+        load(boff + 2, b2);
+        fft_line<T, L, -1, Lay>(b2, t, c, tw, 1, lds);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) project(mode(e), oc, b0[e], b1[e], b2[e]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T>(&ba)[EPT] = a == 0 ? b0 : (a == 1 ? b1 : b2);
+            if constexpr (KIND == SPEC_TAIL) {
+                load(a, reg);
+                fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const T s = oc.alpha * reg_symbol(mode(e), oc.reg);
+                    reg[e] = scale(scale(reg[e], s) + ba[e], oc.norm);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) reg[e] = scale(ba[e], oc.norm);
+            }
+            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            store(a, reg);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+#define MIREG_SWITCH_POW2(n, MACRO) \
+    switch (n) {                    \
+        case 4: MACRO(4); break;    \
+        case 8: MACRO(8); break;    \
+        case 16: MACRO(16); break;  \
+        case 32: MACRO(32); break;  \
+        case 64: MACRO(64); break;  \
+        case 128: MACRO(128); break;\
+        case 256: MACRO(256); break;\
+        case 512: MACRO(512); break;\
+        default: break;             \
+    }
+
+template <typename T>
+static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
+                       hipStream_t s) {
+    const long long lines = (long long)g.n1 * g.n2;
+#define MIREG_L(M)                                                                          \
+    {                                                                                       \
+        dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
+        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kFftThreads), 0, s, src, dst, lines, tw); \
+    }
+    MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T>
+static void launch_c2r(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
+                       hipStream_t s) {
+    const long long lines = (long long)g.n1 * g.n2;
+#define MIREG_L(M)                                                                          \
+    {                                                                                       \
+        dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
+        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(kFftThreads), 0, s, src, dst, lines, tw); \
+    }
+    MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T, int DIR>
+static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipStream_t s) {
+    const long long Q = (long long)g.n1 * g.k3, inner = g.k3, ostride = (long long)g.n2 * g.k3,
+                    pstride = g.k3;
+#define MIREG_L(L)                                                                           \
+    {                                                                                        \
+        dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W), nf);          \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kFftThreads), 0, s, f, Q, inner, \
+                           ostride, pstride, tw);                                            \
+    }
+    MIREG_SWITCH_POW2(g.n2, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T, int KIND>
+static void launch_x1(const Grid &g, FieldPtrs f, const OpConst<T> &oc, const cx<T> *tw,
+                      hipStream_t s) {
+    const long long Q = (long long)g.n2 * g.k3;
+#define MIREG_L(L)                                                                              \
+    {                                                                                           \
+        dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W));                 \
+        hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(kFftThreads), 0, s, f, Q, oc, tw); \
+    }
+    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T>
+void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *in, T *const *out,
+                    cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
+    FieldPtrs fin{}, fspec{}, fout{};
+    for (int i = 0; i < nin; ++i) fin.p[i] = const_cast<T *>(in[i]);
+    for (int i = 0; i < 6; ++i) fspec.p[i] = spec + (long long)i * g.NS;
+    for (int i = 0; i < nout; ++i) fout.p[i] = out[i];
+
+    OpConst<T> oc;
+    oc.n1 = g.n1;
+    oc.n2 = g.n2;
+    oc.n3 = g.n3;
+    oc.k3 = g.k3;
+    oc.sym = sp.sym;
+    oc.nf = sp.nf;
+    oc.reg = sp.reg;
+    oc.div = sp.div;
+    oc.alpha = (T)sp.alpha;
+    oc.beta_v = (T)sp.beta_v;
+    oc.beta_w = (T)sp.beta_w;
+    const double two_pi = 6.283185307179586476925;
+    oc.gs1 = (T)(0.5 * (two_pi * sp.sigma / g.n1) * (two_pi * sp.sigma / g.n1));
+    oc.gs2 = (T)(0.5 * (two_pi * sp.sigma / g.n2) * (two_pi * sp.sigma / g.n2));
+    oc.gs3 = (T)(0.5 * (two_pi * sp.sigma / g.n3) * (two_pi * sp.sigma / g.n3));
+    oc.norm = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+
+    launch_r2c<T>(g, fin, fspec, nin, tw.t[2], s);
+    launch_x2<T, -1>(g, fspec, nin, tw.t[1], s);
+    switch (kind) {
+        case SPEC_SCALE: launch_x1<T, SPEC_SCALE>(g, fspec, oc, tw.t[0], s); break;
+        case SPEC_GRAD: launch_x1<T, SPEC_GRAD>(g, fspec, oc, tw.t[0], s); break;
+        case SPEC_DIV: launch_x1<T, SPEC_DIV>(g, fspec, oc, tw.t[0], s); break;
+        case SPEC_PROJ: launch_x1<T, SPEC_PROJ>(g, fspec, oc, tw.t[0], s); break;
+        default: launch_x1<T, SPEC_TAIL>(g, fspec, oc, tw.t[0], s); break;
+    }
+    launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
+    launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
+}
+
+template void spectral_apply<float>(const Grid &, int, int, int, const float *const *, float *const *,
+                                    cx<float> *, const Twiddles<float> &, const SpecParams &,
+                                    hipStream_t);
+template void spectral_apply<double>(const Grid &, int, int, int, const double *const *,
+                                     double *const *, cx<double> *, const Twiddles<double> &,
+                                     const SpecParams &, hipStream_t);
+
+}  // namespace mireg

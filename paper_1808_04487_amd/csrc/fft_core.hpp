@@ -1,0 +1,241 @@
+// Register/LDS building blocks of the pencil FFT passes.
+//
+// A line of length L (a power of two) is held by TPC = L/EPT threads; thread
+// t keeps the elements at positions t + TPC*e, e = 0..EPT-1, in registers.
+// The transform is a mixed-radix Stockham sequence (radices R0, R1, R2 from
+// FftCfg): every stage takes butterflies j = t + TPC*b, reads inputs
+// j + m*L/R (which are exactly the thread's own registers b + m*EPT/R),
+// twiddles them by w_{Ns R}^{m (j mod Ns)}, applies an R-point DFT and sends
+// output m to position (j / Ns) Ns R + (j mod Ns) + m Ns.  Between stages the
+// outputs pass through LDS; after the last stage they land back on the
+// thread's own positions, so loads and stores of a pass use the same
+// coalesced pattern.
+#pragma once
+
+#include "common.hpp"
+
+namespace mireg {
+
+// cos / sin of 2 pi j / 16, exact to double rounding.
+__host__ __device__ constexpr double cos16(int j) {
+    return ((j & 15) == 0)   ? 1.0
+           : ((j & 15) == 1) ? 0.92387953251128675613
+           : ((j & 15) == 2) ? 0.70710678118654752440
+           : ((j & 15) == 3) ? 0.38268343236508977173
+           : ((j & 15) == 4) ? 0.0
+           : ((j & 15) == 5) ? -0.38268343236508977173
+           : ((j & 15) == 6) ? -0.70710678118654752440
+           : ((j & 15) == 7) ? -0.92387953251128675613
+           : ((j & 15) == 8) ? -1.0
+           : ((j & 15) == 9) ? -0.92387953251128675613
+           : ((j & 15) == 10) ? -0.70710678118654752440
+           : ((j & 15) == 11) ? -0.38268343236508977173
+           : ((j & 15) == 12) ? 0.0
+           : ((j & 15) == 13) ? 0.38268343236508977173
+           : ((j & 15) == 14) ? 0.70710678118654752440
+                              : 0.92387953251128675613;
+}
+__host__ __device__ constexpr double sin16(int j) { return cos16(j - 4); }
+
+// w_R^p = exp(DIR * 2 pi i p / R) for R dividing 16 (DIR = -1 forward).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ cx<T> root(int p) {
+    const int j = (p * (16 / R)) & 15;
+    return make_cx<T>((T)cos16(j), (T)(DIR * sin16(j)));
+}
+
+// In-register DFT of length R in {1, 2, 4, 8, 16}, natural order in and out.
+template <typename T, int R, int DIR>
+struct Dft {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        // R = R1 * R2 with R1 = 4: inputs n = R2 n1 + n2, outputs k = k1 + 4 k2
+        constexpr int R1 = 4, R2 = R / 4;
+        cx<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            cx<T> a[4];
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n1] = x[R2 * n1 + n2];
+            Dft<T, 4, DIR>::run(a);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2 * 4 + k1] = (n2 * k1 == 0) ? a[k1] : a[k1] * root<T, R, DIR>(n2 * k1);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cx<T> b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = y[n2 * 4 + k1];
+            Dft<T, R2, DIR>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) x[k1 + 4 * k2] = b[k2];
+        }
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 1, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *) {}
+};
+template <typename T, int DIR>
+struct Dft<T, 2, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        cx<T> a = x[0], b = x[1];
+        x[0] = a + b;
+        x[1] = a - b;
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 4, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        cx<T> s02 = x[0] + x[2], d02 = x[0] - x[2];
+        cx<T> s13 = x[1] + x[3], d13 = x[1] - x[3];
+        // w_4 = -i forward, +i inverse
+        cx<T> r = (DIR < 0) ? mul_mi(d13) : mul_i(d13);
+        x[0] = s02 + s13;
+        x[2] = s02 - s13;
+        x[1] = d02 + r;
+        x[3] = d02 - r;
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 8, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        // 8 = 4 x 2: inputs n = 2 n1 + n2, outputs k = k1 + 4 k2
+        cx<T> y[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 2; ++n2) {
+            cx<T> a[4] = {x[n2], x[2 + n2], x[4 + n2], x[6 + n2]};
+            Dft<T, 4, DIR>::run(a);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2 * 4 + k1] = (n2 * k1 == 0) ? a[k1] : a[k1] * root<T, 8, DIR>(n2 * k1);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            x[k1] = y[k1] + y[4 + k1];
+            x[k1 + 4] = y[k1] - y[4 + k1];
+        }
+    }
+};
+
+// Elements per thread and radices per line length.  Every radix divides EPT
+// so that a thread's butterflies read only its own registers.
+template <typename T, int L>
+struct FftCfg;
+#define MIREG_FFTCFG(TY, LL, E, A, B, C) \
+    template <>                          \
+    struct FftCfg<TY, LL> {              \
+        static constexpr int EPT = E;    \
+        static constexpr int R0 = A;     \
+        static constexpr int R1 = B;     \
+        static constexpr int R2 = C;     \
+    };
+MIREG_FFTCFG(float, 2, 2, 2, 1, 1)
+MIREG_FFTCFG(float, 4, 4, 4, 1, 1)
+MIREG_FFTCFG(float, 8, 4, 4, 2, 1)
+MIREG_FFTCFG(float, 16, 4, 4, 4, 1)
+MIREG_FFTCFG(float, 32, 8, 8, 4, 1)
+MIREG_FFTCFG(float, 64, 8, 8, 8, 1)
+MIREG_FFTCFG(float, 128, 16, 16, 8, 1)
+MIREG_FFTCFG(float, 256, 16, 16, 16, 1)
+MIREG_FFTCFG(float, 512, 16, 16, 8, 4)
+MIREG_FFTCFG(double, 2, 2, 2, 1, 1)
+MIREG_FFTCFG(double, 4, 4, 4, 1, 1)
+MIREG_FFTCFG(double, 8, 4, 4, 2, 1)
+MIREG_FFTCFG(double, 16, 4, 4, 4, 1)
+MIREG_FFTCFG(double, 32, 8, 8, 4, 1)
+MIREG_FFTCFG(double, 64, 8, 8, 8, 1)
+MIREG_FFTCFG(double, 128, 8, 8, 4, 4)
+MIREG_FFTCFG(double, 256, 8, 8, 8, 4)
+MIREG_FFTCFG(double, 512, 8, 8, 8, 8)
+#undef MIREG_FFTCFG
+
+// Register array of one thread's share of a line.
+template <typename T, int L>
+using Regs = cx<T>[FftCfg<T, L>::EPT];
+
+// Threads per workgroup of every FFT pass.
+constexpr int kFftThreads = 256;
+
+template <typename T, int L>
+struct FftShape {
+    static constexpr int EPT = FftCfg<T, L>::EPT;
+    static constexpr int TPC = L / EPT;          // threads per line
+    static constexpr int W = kFftThreads / TPC;  // lines per workgroup
+};
+
+// LDS index of (line c, position p): strided passes keep lines (columns)
+// fastest, the contiguous x3 passes keep positions fastest (padded rows).
+template <int W>
+struct LayoutCols {
+    static __device__ __forceinline__ int at(int c, int p) { return p * W + c; }
+    static constexpr int size(int L) { return L * W; }
+};
+template <int W, int L>
+struct LayoutRows {
+    static constexpr int PITCH = L + 1;
+    static __device__ __forceinline__ int at(int c, int p) { return c * PITCH + p; }
+    static constexpr int size(int) { return W * PITCH; }
+};
+
+// One Stockham stage of radix R after sub-transforms of length NS.
+// tw: table exp(-2 pi i j / Ltab), read at stride Ltab / L.
+template <typename T, int L, int R, int NS, int DIR, bool LAST, class Lay>
+__device__ __forceinline__ void stockham_stage(Regs<T, L> &reg, int t, int c,
+                                               const cx<T> *__restrict__ tw, int twstride,
+                                               cx<T> *lds) {
+    constexpr int EPT = FftCfg<T, L>::EPT;
+    constexpr int TPC = L / EPT;
+    constexpr int NB = EPT / R;
+    cx<T> out[EPT];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + TPC * b;
+        const int k = j & (NS - 1);
+        cx<T> v[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = reg[b + m * NB];
+        if (NS > 1) {
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+                cx<T> w = tw[(m * k) * (L / (NS * R)) * twstride];
+                if (DIR > 0) w.im = -w.im;
+                v[m] = v[m] * w;
+            }
+        }
+        Dft<T, R, DIR>::run(v);
+#pragma unroll
+        for (int m = 0; m < R; ++m) out[b + m * NB] = v[m];
+    }
+    if (LAST) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) reg[e] = out[e];
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = t + TPC * b;
+            const int k = j & (NS - 1);
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) lds[Lay::at(c, base + m * NS)] = out[b + m * NB];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) reg[e] = lds[Lay::at(c, t + TPC * e)];
+        __syncthreads();
+    }
+}
+
+// Full unnormalised transform of one line: X[k] = sum_n x[n] exp(DIR 2 pi i n k / L).
+template <typename T, int L, int DIR, class Lay>
+__device__ __forceinline__ void fft_line(Regs<T, L> &reg, int t, int c,
+                                         const cx<T> *__restrict__ tw, int twstride, cx<T> *lds) {
+    using C = FftCfg<T, L>;
+    constexpr bool one = (C::R1 == 1);
+    constexpr bool two = (C::R1 > 1 && C::R2 == 1);
+    stockham_stage<T, L, C::R0, 1, DIR, one, Lay>(reg, t, c, tw, twstride, lds);
+    if constexpr (C::R1 > 1)
+        stockham_stage<T, L, C::R1, C::R0, DIR, two, Lay>(reg, t, c, tw, twstride, lds);
+    if constexpr (C::R2 > 1)
+        stockham_stage<T, L, C::R2, C::R0 * C::R1, DIR, true, Lay>(reg, t, c, tw, twstride, lds);
+}
+
+}  // namespace mireg

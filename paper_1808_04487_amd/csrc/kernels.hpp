@@ -1,0 +1,107 @@
+// Internal interface between the host solver and the HIP kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace mireg {
+
+// Up to six field base pointers handed to one launch.
+struct FieldPtrs {
+    void *p[6];
+};
+
+// Spectral operators applied between the forward and inverse x1 passes.
+enum SpecKind {
+    SPEC_SCALE = 0,  // n -> n fields, one scalar symbol per mode
+    SPEC_GRAD = 1,   // 1 -> 3
+    SPEC_DIV = 2,    // 3 -> 1
+    SPEC_PROJ = 3,   // 3 -> 3, K
+    SPEC_TAIL = 4    // 6 -> 3, alpha A u + K b (u in slots 0..2, b in 3..5)
+};
+enum SymKind { SYM_ID = 0, SYM_A = 1, SYM_AINV = 2, SYM_LAP = 3, SYM_GAUSS = 4 };
+
+struct SpecParams {
+    int sym;        // SymKind for SPEC_SCALE
+    int nf;         // fields for SPEC_SCALE
+    int reg;        // 1: |k|^2, 2: |k|^4
+    int div;        // 0 none, 1 near-incompressible, 2 Leray
+    double alpha;   // factor of A (SYM_A, SYM_AINV, SPEC_TAIL)
+    double beta_v, beta_w;
+    double sigma;   // Gaussian width in cells
+};
+
+// Device twiddle tables exp(-2 pi i j / n_a), j < n_a, for the three axes.
+template <typename T>
+struct Twiddles {
+    const cx<T> *t[3];
+};
+
+// 3D pipeline: R2C(x3) -> C2C(x2) -> [x1 forward, operator, x1 inverse]
+// -> C2C(x2 inverse) -> C2R(x3).  spec holds max(nin, nout) half spectra.
+template <typename T>
+void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *in, T *const *out,
+                    cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+
+// ---- semi-Lagrangian transport (transport.hip) ----
+struct StepConst {
+    double dt;
+    double coef;       // step-specific weight
+    double aj;         // trapezoidal time weight of the slice being produced
+};
+
+// disp = sign dt/2 (v + I[v](x + sign dt v)) / h  (cell units)
+template <typename T>
+void departure(const Grid &g, int order, int sign, double dt, const T *v, T *disp, hipStream_t s);
+// out = I[f](x + disp)
+template <typename T>
+void interp_field(const Grid &g, int order, const T *f, const T *disp, T *out, hipStream_t s);
+// Adjoint first slice: lam = mR - m, b = a_nt lam grad m
+template <typename T>
+void adjoint_init(const Grid &g, double a_nt, const T *mR, const T *m, const T *gradm, T *lam,
+                  T *b, hipStream_t s);
+// One adjoint step with fused time quadrature: lam_out = step(lam_in), b += a_j lam_out grad m^j
+// (lam_out may be null when not needed).
+template <typename T>
+void adjoint_step(const Grid &g, int order, double dt, double aj, const T *lam_in, const T *d,
+                  const T *Y, const T *gradm_j, T *lam_out, T *b, hipStream_t s);
+// Incremental state: q0 = -dt/2 grad m^0 . vt
+template <typename T>
+void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s);
+// q_out = I[q_in](X) + coef f^{j+1}, f = -grad m^{j+1} . vt; on the last step
+// (lam_out, b non-null) write lt = -(I[q](X) + dt/2 f^nt) and b = a_nt lt grad m^nt.
+template <typename T>
+void incstate_step(const Grid &g, int order, double coef, const T *q_in, const T *X,
+                   const T *gradm_next, const T *vt, T *q_out, double a_nt, T *lt_out, T *b_out,
+                   hipStream_t s);
+
+// ---- vector kernels and FP64 reductions (vec.hip) ----
+// result[k] (device doubles) for k < nres; see the individual descriptions.
+template <typename T>
+void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s);
+template <typename T>
+void sumsq_diff(const T *a, const T *b, long long n, double *partials, double *result,
+                hipStream_t s);
+// y = a x + b y
+template <typename T>
+void axpby(long long n, double a, const T *x, double b, T *y, hipStream_t s);
+// z = x + a y  (z may alias x or y)
+template <typename T>
+void xpay(long long n, const T *x, double a, const T *y, T *z, hipStream_t s);
+// PCG update: x += k s; r -= k Hs; result[0] = <r, r> (unweighted)
+template <typename T>
+void pcg_update(long long n, double k, const T *sdir, const T *Hs, T *x, T *r, double *partials,
+                double *result, hipStream_t s);
+// result[0] = min, result[1] = max, result[2] = count of non-finite values
+template <typename T>
+void minmax_nonfinite(const T *a, long long n, double *partials, double *result, hipStream_t s);
+// result[0] = max_x sum_c v_c(x)^2 over a vector field of N points
+template <typename T>
+void max_norm2(const T *v, long long N, double *partials, double *result, hipStream_t s);
+template <typename T>
+void affine(long long n, const T *x, double a, double b, T *y, hipStream_t s);  // y = a x + b
+template <typename T>
+void fill(long long n, T val, T *y, hipStream_t s);
+// Number of partial sums the reductions use.
+constexpr int kRedBlocks = 1024;
+
+}  // namespace mireg

@@ -1,0 +1,835 @@
+// Host side of the mireg C-ABI: context and workspace, the velocity-dependent
+// caches, the reduced gradient and Gauss-Newton Hessian matvec (Sec. 2.2),
+// PCG (Algorithm "inner iteration") and the inexact Gauss-Newton-Krylov
+// loop with Armijo line search (Algorithm "outer iteration").  Every field
+// operation runs in the HIP kernels of fft.hip, transport.hip and vec.hip;
+// the host only sequences launches on the context stream and reads back
+// FP64 scalars.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mireg.h"
+#include "kernels.hpp"
+
+using namespace mireg;
+
+namespace {
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+struct Timers {
+    bool on = false;
+    double fft_ms = 0, interp_ms = 0, other_ms = 0;
+    long launches = 0;
+};
+
+}  // namespace
+
+struct mireg_ctx {
+    mireg_params p{};
+    hipStream_t stream = nullptr;
+    Grid g{};
+    size_t elem = 4;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    std::string err;
+
+    // fields (typed at use)
+    void *mT = nullptr, *mR = nullptr, *v = nullptr, *X = nullptr, *Y = nullptr;
+    void *m = nullptr;      // (nt+1) N  state history
+    void *gradm = nullptr;  // (nt+1) 3N
+    void *d = nullptr;      // N, div v
+    void *lam = nullptr;    // 2N, ping-pong for adjoint steps and incremental state
+    void *b = nullptr;      // 3N, time integral of the gradient / matvec
+    void *vecs = nullptr;   // kVecs x 3N work vectors
+    void *spec = nullptr;   // 6 half spectra
+    void *tw[3] = {nullptr, nullptr, nullptr};
+    double *partials = nullptr, *dres = nullptr;  // device reduction buffers
+    double *hres = nullptr;                       // pinned host mirror of dres
+
+    bool have_images = false;
+    bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
+    Timers tm;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    static constexpr int kVecs = 8;
+
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    void invalidate() { have_X = have_Y = have_state = have_gradm = have_d = false; }
+    long long N() const { return g.N; }
+    double cell() const {
+        const double two_pi = 6.283185307179586476925;
+        return (two_pi / g.n1) * (two_pi / g.n2) * (two_pi / g.n3);
+    }
+    template <typename T>
+    T *f(void *p) const {
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *vec(int i) const {
+        return static_cast<T *>(vecs) + (long long)i * 3 * g.N;
+    }
+};
+
+namespace {
+
+#define HIP_OK(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return ctx->fail(MIREG_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Phase timing (only when enabled): events around a phase, synchronised.
+struct Phase {
+    mireg_ctx *ctx;
+    int kind;  // 0 fft, 1 interp, 2 other
+    Phase(mireg_ctx *c, int k) : ctx(c), kind(k) {
+        if (ctx->tm.on) hipEventRecord(ctx->ev0, ctx->stream);
+    }
+    ~Phase() {
+        if (!ctx->tm.on) return;
+        hipEventRecord(ctx->ev1, ctx->stream);
+        hipEventSynchronize(ctx->ev1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        (kind == 0 ? ctx->tm.fft_ms : kind == 1 ? ctx->tm.interp_ms : ctx->tm.other_ms) += ms;
+        ctx->tm.launches++;
+    }
+};
+
+int check_launch(mireg_ctx *ctx) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->fail(MIREG_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return MIREG_OK;
+}
+
+// Read nres FP64 results back (synchronises the stream).
+int readback(mireg_ctx *ctx, int nres) {
+    HIP_OK(hipMemcpyAsync(ctx->hres, ctx->dres, nres * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return MIREG_OK;
+}
+
+template <typename T>
+SpecParams spec_params(const mireg_ctx *ctx) {
+    SpecParams sp{};
+    sp.reg = ctx->p.reg;
+    sp.div = ctx->p.div;
+    sp.beta_v = ctx->p.beta_v;
+    sp.beta_w = ctx->p.beta_w;
+    sp.alpha = 1.0;
+    sp.nf = 1;
+    return sp;
+}
+
+template <typename T>
+Twiddles<T> twiddles(const mireg_ctx *ctx) {
+    Twiddles<T> t;
+    for (int a = 0; a < 3; ++a) t.t[a] = static_cast<const cx<T> *>(ctx->tw[a]);
+    return t;
+}
+
+template <typename T>
+void spec(mireg_ctx *ctx, int kind, int nin, int nout, const T *const *in, T *const *out, const SpecParams &sp) {
+    Phase ph(ctx, 0);
+    spectral_apply<T>(ctx->g, kind, nin, nout, in, out, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp,
+                      ctx->stream);
+}
+
+// ---- individual spectral operators ----
+template <typename T>
+void op_grad(mireg_ctx *ctx, const T *u, T *out) {
+    const long long N = ctx->N();
+    const T *in[1] = {u};
+    T *o[3] = {out, out + N, out + 2 * N};
+    spec<T>(ctx, SPEC_GRAD, 1, 3, in, o, spec_params<T>(ctx));
+}
+template <typename T>
+void op_div(mireg_ctx *ctx, const T *v, T *out) {
+    const long long N = ctx->N();
+    const T *in[3] = {v, v + N, v + 2 * N};
+    T *o[1] = {out};
+    spec<T>(ctx, SPEC_DIV, 3, 1, in, o, spec_params<T>(ctx));
+}
+template <typename T>
+void op_scale(mireg_ctx *ctx, int sym, int nf, double alpha, double sigma, const T *u, T *out) {
+    const long long N = ctx->N();
+    const T *in[3] = {u, u + N, u + 2 * N};
+    T *o[3] = {out, out + N, out + 2 * N};
+    SpecParams sp = spec_params<T>(ctx);
+    sp.sym = sym;
+    sp.nf = nf;
+    sp.alpha = alpha;
+    sp.sigma = sigma;
+    spec<T>(ctx, SPEC_SCALE, nf, nf, in, o, sp);
+}
+template <typename T>
+void op_proj(mireg_ctx *ctx, int div, const T *u, T *out) {
+    const long long N = ctx->N();
+    const T *in[3] = {u, u + N, u + 2 * N};
+    T *o[3] = {out, out + N, out + 2 * N};
+    SpecParams sp = spec_params<T>(ctx);
+    sp.div = div;
+    spec<T>(ctx, SPEC_PROJ, 3, 3, in, o, sp);
+}
+// out = alpha A u + K b
+template <typename T>
+void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
+    const long long N = ctx->N();
+    const T *in[6] = {u, u + N, u + 2 * N, b, b + N, b + 2 * N};
+    T *o[3] = {out, out + N, out + 2 * N};
+    SpecParams sp = spec_params<T>(ctx);
+    sp.alpha = alpha;
+    spec<T>(ctx, SPEC_TAIL, 6, 3, in, o, sp);
+}
+
+// ---- velocity-dependent caches ----
+template <typename T>
+void ensure_X(mireg_ctx *ctx) {
+    if (ctx->have_X) return;
+    Phase ph(ctx, 1);
+    departure<T>(ctx->g, ctx->p.interp_order, -1, 1.0 / ctx->p.nt, ctx->f<T>(ctx->v), ctx->f<T>(ctx->X),
+                 ctx->stream);
+    ctx->have_X = true;
+}
+template <typename T>
+void ensure_Y(mireg_ctx *ctx) {
+    if (ctx->have_Y) return;
+    Phase ph(ctx, 1);
+    departure<T>(ctx->g, ctx->p.interp_order, +1, 1.0 / ctx->p.nt, ctx->f<T>(ctx->v), ctx->f<T>(ctx->Y),
+                 ctx->stream);
+    ctx->have_Y = true;
+}
+// State equation forward in time: m^0 = mT, m^{j+1} = I[m^j](X).
+template <typename T>
+void ensure_state(mireg_ctx *ctx) {
+    if (ctx->have_state) return;
+    ensure_X<T>(ctx);
+    const long long N = ctx->N();
+    T *m = ctx->f<T>(ctx->m);
+    hipMemcpyAsync(m, ctx->mT, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream);
+    Phase ph(ctx, 1);
+    for (int j = 0; j < ctx->p.nt; ++j)
+        interp_field<T>(ctx->g, ctx->p.interp_order, m + j * N, ctx->f<T>(ctx->X), m + (j + 1) * N, ctx->stream);
+    ctx->have_state = true;
+}
+template <typename T>
+void ensure_gradm(mireg_ctx *ctx) {
+    if (ctx->have_gradm) return;
+    ensure_state<T>(ctx);
+    const long long N = ctx->N();
+    for (int j = 0; j <= ctx->p.nt; ++j)
+        op_grad<T>(ctx, ctx->f<T>(ctx->m) + j * N, ctx->f<T>(ctx->gradm) + 3 * j * N);
+    ctx->have_gradm = true;
+}
+template <typename T>
+void ensure_d(mireg_ctx *ctx) {
+    if (ctx->have_d) return;
+    op_div<T>(ctx, ctx->f<T>(ctx->v), ctx->f<T>(ctx->d));
+    ctx->have_d = true;
+}
+
+double time_weight(int j, int nt) { return (j == 0 || j == nt) ? 0.5 / nt : 1.0 / nt; }
+
+// Backward sweep shared by the adjoint and the incremental adjoint: from
+// lam^nt in lam buffer `cur`, accumulate b += a_j lam^j grad m^j, j < nt.
+template <typename T>
+void backward_sweep(mireg_ctx *ctx, T *l0, T *l1, T *b) {
+    const int nt = ctx->p.nt;
+    const long long N = ctx->N();
+    const double dt = 1.0 / nt;
+    T *cur = l0, *nxt = l1;
+    Phase ph(ctx, 1);
+    for (int j = nt - 1; j >= 0; --j) {
+        adjoint_step<T>(ctx->g, ctx->p.interp_order, dt, time_weight(j, nt), cur, ctx->f<T>(ctx->d),
+                        ctx->f<T>(ctx->Y), ctx->f<T>(ctx->gradm) + 3 * j * N, j > 0 ? nxt : nullptr, b,
+                        ctx->stream);
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+template <typename T>
+int dot_h(mireg_ctx *ctx, const T *a, const T *b, long long n, double *out) {
+    dot<T>(a, b, n, ctx->partials, ctx->dres, ctx->stream);
+    int rc = readback(ctx, 1);
+    if (rc) return rc;
+    *out = ctx->cell() * ctx->hres[0];
+    return MIREG_OK;
+}
+
+// ---- objective ----
+template <typename T>
+int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T>(ctx);
+    const long long N = ctx->N();
+    const int nt = ctx->p.nt;
+    sumsq_diff<T>(ctx->f<T>(ctx->m) + nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    int rc = readback(ctx, 1);
+    if (rc) return rc;
+    const double mis = 0.5 * ctx->cell() * ctx->hres[0];
+    // beta_v/2 <A v, v>
+    T *Av = ctx->vec<T>(7);
+    op_scale<T>(ctx, SYM_A, 3, 1.0, 0.0, ctx->f<T>(ctx->v), Av);
+    double vAv = 0;
+    if ((rc = dot_h<T>(ctx, Av, ctx->f<T>(ctx->v), 3 * N, &vAv))) return rc;
+    double r = 0.5 * ctx->p.beta_v * vAv;
+    if (ctx->p.div == MIREG_DIV_NEAR) {
+        // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2)
+        ensure_d<T>(ctx);
+        T *gw = ctx->vec<T>(7);
+        op_grad<T>(ctx, ctx->f<T>(ctx->d), gw);
+        double a = 0, c = 0;
+        if ((rc = dot_h<T>(ctx, gw, gw, 3 * N, &a))) return rc;
+        if ((rc = dot_h<T>(ctx, ctx->f<T>(ctx->d), ctx->f<T>(ctx->d), N, &c))) return rc;
+        r += 0.5 * ctx->p.beta_w * (a + c);
+    }
+    if (J) *J = mis + r;
+    if (mism) *mism = mis;
+    if (reg) *reg = r;
+    return check_launch(ctx);
+}
+
+// ---- reduced gradient ----
+template <typename T>
+int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T>(ctx);
+    ensure_gradm<T>(ctx);
+    ensure_d<T>(ctx);
+    ensure_Y<T>(ctx);
+    const long long N = ctx->N();
+    const int nt = ctx->p.nt;
+    T *l0 = ctx->f<T>(ctx->lam), *l1 = l0 + N, *b = ctx->f<T>(ctx->b);
+    {
+        Phase ph(ctx, 2);
+        adjoint_init<T>(ctx->g, time_weight(nt, nt), ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N,
+                        ctx->f<T>(ctx->gradm) + 3 * nt * N, l0, b, ctx->stream);
+    }
+    backward_sweep<T>(ctx, l0, l1, b);
+    op_tail<T>(ctx, ctx->p.beta_v, ctx->f<T>(ctx->v), b, g);
+    if (gnorm) {
+        double gg = 0;
+        int rc = dot_h<T>(ctx, g, g, 3 * N, &gg);
+        if (rc) return rc;
+        *gnorm = std::sqrt(gg);
+    }
+    return check_launch(ctx);
+}
+
+// ---- Gauss-Newton Hessian matvec ----
+template <typename T>
+int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T>(ctx);
+    ensure_gradm<T>(ctx);
+    ensure_d<T>(ctx);
+    ensure_Y<T>(ctx);
+    const long long N = ctx->N();
+    const int nt = ctx->p.nt;
+    const double dt = 1.0 / nt;
+    T *q0 = ctx->f<T>(ctx->lam), *q1 = q0 + N, *b = ctx->f<T>(ctx->b);
+    const T *gm = ctx->f<T>(ctx->gradm);
+    {
+        Phase ph(ctx, 1);
+        // incremental state: q^0 = mt^0 + dt/2 f^0 with mt^0 = 0
+        incstate_init<T>(ctx->g, dt, gm, vt, q0, ctx->stream);
+        T *cur = q0, *nxt = q1;
+        for (int j = 0; j < nt; ++j) {
+            const bool last = (j == nt - 1);
+            // q^{j+1} = I[q^j](X) + dt f^{j+1}; last: lt = -(I[q](X) + dt/2 f^nt), b = a_nt lt grad m^nt
+            incstate_step<T>(ctx->g, ctx->p.interp_order, last ? 0.5 * dt : dt, cur, ctx->f<T>(ctx->X),
+                             gm + 3 * (j + 1) * N, vt, nxt, time_weight(nt, nt), last ? nxt : nullptr,
+                             last ? b : nullptr, ctx->stream);
+            T *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        // cur now holds lt^nt
+        backward_sweep<T>(ctx, cur, nxt, b);
+    }
+    op_tail<T>(ctx, ctx->p.beta_v, vt, b, Hvt);
+    return check_launch(ctx);
+}
+
+template <typename T>
+int impl_precond(mireg_ctx *ctx, const T *r, T *z) {
+    op_scale<T>(ctx, SYM_AINV, 3, ctx->p.beta_v, 0.0, r, z);
+    return check_launch(ctx);
+}
+
+// ---- PCG (Algorithm "inner iteration") ----
+template <typename T>
+int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
+    const long long n = 3 * ctx->N();
+    const double h3 = ctx->cell();
+    T *r = ctx->vec<T>(0), *z = ctx->vec<T>(1), *s = ctx->vec<T>(2), *Hs = ctx->vec<T>(3);
+    int rc;
+    HIP_OK(hipMemcpyAsync(r, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    fill<T>(n, (T)0, x, ctx->stream);
+    double rr = 0;
+    if ((rc = dot_h<T>(ctx, r, r, n, &rr))) return rc;
+    const double r0 = std::sqrt(rr);
+    int it = 0;
+    double rnorm = r0;
+    if (r0 > 0) {
+        impl_precond<T>(ctx, r, z);
+        HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+        double rz = 0;
+        if ((rc = dot_h<T>(ctx, r, z, n, &rz))) return rc;
+        while (it < maxit) {
+            if ((rc = impl_matvec<T>(ctx, s, Hs))) return rc;
+            double sHs = 0;
+            if ((rc = dot_h<T>(ctx, s, Hs, n, &sHs))) return rc;
+            if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate
+                if (it == 0) HIP_OK(hipMemcpyAsync(x, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+                break;
+            }
+            const double kappa = rz / sHs;
+            pcg_update<T>(n, kappa, s, Hs, x, r, ctx->partials, ctx->dres, ctx->stream);
+            if ((rc = readback(ctx, 1))) return rc;
+            ++it;
+            rnorm = std::sqrt(h3 * ctx->hres[0]);
+            if (rnorm <= rtol * r0) break;
+            impl_precond<T>(ctx, r, z);
+            double rz_new = 0;
+            if ((rc = dot_h<T>(ctx, r, z, n, &rz_new))) return rc;
+            const double mu = rz_new / rz;
+            rz = rz_new;
+            xpay<T>(n, z, mu, s, s, ctx->stream);  // s = z + mu s
+        }
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = r0 > 0 ? rnorm / r0 : 0.0;
+    return check_launch(ctx);
+}
+
+template <typename T>
+int impl_set_velocity(mireg_ctx *ctx, const T *v);
+
+// ---- GN (Algorithm "outer iteration") ----
+template <typename T>
+int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    const long long n = 3 * ctx->N();
+    const double h3 = ctx->cell();
+    mireg_report R{};
+    // vectors 0..3 belong to PCG; 4: g, 5: vt, 6: accepted v
+    T *g = ctx->vec<T>(4), *vt = ctx->vec<T>(5), *vk = ctx->vec<T>(6);
+    int rc;
+    if ((rc = impl_set_velocity<T>(ctx, v_io))) return rc;
+    HIP_OK(hipMemcpyAsync(vk, v_io, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    double J = 0;
+    if ((rc = impl_objective<T>(ctx, &J, nullptr, nullptr))) return rc;
+    R.pde_solves += 1;
+    double gn = 0;
+    if ((rc = impl_gradient<T>(ctx, g, &gn))) return rc;
+    R.pde_solves += 1;
+    const double g0 = gn;
+    R.J0 = J;
+    R.gnorm0 = g0;
+    int k = 0;
+    for (;;) {
+        if (o->log_level > 0)
+            fprintf(stderr, "[mireg] gn %d J %.6e |g| %.6e |g|/|g0| %.3e\n", k, J, gn, g0 > 0 ? gn / g0 : 0.0);
+        if (gn <= o->grad_rtol * g0) {
+            R.status = MIREG_CONVERGED_REL;
+            break;
+        }
+        if (gn <= o->grad_atol) {
+            R.status = MIREG_CONVERGED_ABS;
+            break;
+        }
+        if (k >= o->max_gn) {
+            R.status = MIREG_MAXIT;
+            break;
+        }
+        const double eps_h = std::fmin(0.5, std::sqrt(gn / g0));
+        // rhs = -g in vector 7
+        T *rhs = ctx->vec<T>(7);
+        affine<T>(n, g, -1.0, 0.0, rhs, ctx->stream);
+        int its = 0;
+        if ((rc = impl_pcg<T>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr))) return rc;
+        R.matvecs += its;
+        R.pcg_iters += its;
+        R.pde_solves += 2 * its;
+        double slope = 0;
+        if ((rc = dot_h<T>(ctx, g, vt, n, &slope))) return rc;
+        double alpha = 1.0, Jt = 0;
+        bool accepted = false;
+        for (int ls = 0; ls < o->max_ls; ++ls) {
+            // trial velocity v = vk + alpha vt, written into the context velocity
+            xpay<T>(n, vk, alpha, vt, ctx->f<T>(ctx->v), ctx->stream);
+            ctx->invalidate();
+            if ((rc = impl_objective<T>(ctx, &Jt, nullptr, nullptr))) return rc;
+            R.ls_trials += 1;
+            R.pde_solves += 1;
+            if (Jt <= J + o->armijo_c1 * alpha * slope) {
+                accepted = true;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        if (!accepted) {
+            HIP_OK(hipMemcpyAsync(ctx->v, vk, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->invalidate();
+            R.status = MIREG_LS_FAIL;
+            break;
+        }
+        HIP_OK(hipMemcpyAsync(vk, ctx->v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+        J = Jt;
+        if ((rc = impl_gradient<T>(ctx, g, &gn))) return rc;
+        R.pde_solves += 1;
+        ++k;
+    }
+    R.gn_iters = k;
+    R.J = J;
+    R.gnorm = gn;
+    R.gnorm_rel = g0 > 0 ? gn / g0 : 0.0;
+    // mismatch_rel = ||m(1) - mR||^2 / ||mT - mR||^2
+    ensure_state<T>(ctx);
+    const long long N = ctx->N();
+    sumsq_diff<T>(ctx->f<T>(ctx->m) + ctx->p.nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    if ((rc = readback(ctx, 1))) return rc;
+    const double num = ctx->hres[0];
+    sumsq_diff<T>(ctx->f<T>(ctx->mT), ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    if ((rc = readback(ctx, 1))) return rc;
+    R.mismatch_rel = ctx->hres[0] > 0 ? num / ctx->hres[0] : 0.0;
+    HIP_OK(hipMemcpyAsync(v_io, vk, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    (void)h3;
+    if (rep) *rep = R;
+    return check_launch(ctx);
+}
+
+template <typename T>
+int check_finite(mireg_ctx *ctx, const T *a, long long n, const char *what) {
+    minmax_nonfinite<T>(a, n, ctx->partials, ctx->dres, ctx->stream);
+    int rc = readback(ctx, 3);
+    if (rc) return rc;
+    if (ctx->hres[2] != 0) return ctx->fail(MIREG_E_NONFINITE, "%s contains %.0f non-finite values", what, ctx->hres[2]);
+    return MIREG_OK;
+}
+
+template <typename T>
+int impl_set_images(mireg_ctx *ctx, const T *mT, const T *mR) {
+    const long long N = ctx->N();
+    int rc;
+    if ((rc = check_finite<T>(ctx, mT, N, "mT"))) return rc;
+    if ((rc = check_finite<T>(ctx, mR, N, "mR"))) return rc;
+    HIP_OK(hipMemcpyAsync(ctx->mT, mT, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ctx->mR, mR, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->have_images = true;
+    ctx->have_state = ctx->have_gradm = false;
+    return MIREG_OK;
+}
+
+template <typename T>
+int impl_set_velocity(mireg_ctx *ctx, const T *v) {
+    const long long n = 3 * ctx->N();
+    int rc;
+    if ((rc = check_finite<T>(ctx, v, n, "v"))) return rc;
+    if (v != ctx->v) HIP_OK(hipMemcpyAsync(ctx->v, v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->invalidate();
+    return MIREG_OK;
+}
+
+template <typename T>
+int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
+    const long long N = ctx->N();
+    switch (opcode) {
+        case MIREG_OP_GRAD: op_grad<T>(ctx, in, out); break;
+        case MIREG_OP_DIV: op_div<T>(ctx, in, out); break;
+        case MIREG_OP_LAPLACE: op_scale<T>(ctx, SYM_LAP, 1, 1.0, 0.0, in, out); break;
+        case MIREG_OP_APPLY_A: op_scale<T>(ctx, SYM_A, 3, 1.0, 0.0, in, out); break;
+        case MIREG_OP_APPLY_K: op_proj<T>(ctx, ctx->p.div, in, out); break;
+        case MIREG_OP_LERAY: op_proj<T>(ctx, MIREG_DIV_LERAY, in, out); break;
+        case MIREG_OP_PRECOND: impl_precond<T>(ctx, in, out); break;
+        case MIREG_OP_GAUSS:
+            if (!(arg >= 0)) return ctx->fail(MIREG_E_ARG, "Gaussian width must be >= 0");
+            op_scale<T>(ctx, SYM_GAUSS, 1, 1.0, arg, in, out);
+            break;
+        case MIREG_OP_DEPARTURE_X:
+        case MIREG_OP_DEPARTURE_Y: {
+            Phase ph(ctx, 1);
+            departure<T>(ctx->g, ctx->p.interp_order, opcode == MIREG_OP_DEPARTURE_X ? -1 : +1, 1.0 / ctx->p.nt, in,
+                         out, ctx->stream);
+            break;
+        }
+        case MIREG_OP_TRANSPORT_STATE: {
+            ensure_X<T>(ctx);
+            T *a = ctx->f<T>(ctx->lam), *b = a + N;
+            Phase ph(ctx, 1);
+            const T *src = in;
+            for (int j = 0; j < ctx->p.nt; ++j) {
+                T *dst = (j == ctx->p.nt - 1) ? out : ((j & 1) ? b : a);
+                interp_field<T>(ctx->g, ctx->p.interp_order, src, ctx->f<T>(ctx->X), dst, ctx->stream);
+                src = dst;
+            }
+            break;
+        }
+        case MIREG_OP_INTERP: {
+            Phase ph(ctx, 1);
+            interp_field<T>(ctx->g, ctx->p.interp_order, in, in + N, out, ctx->stream);
+            break;
+        }
+        case MIREG_OP_RESCALE01: {
+            minmax_nonfinite<T>(in, N, ctx->partials, ctx->dres, ctx->stream);
+            int rc = readback(ctx, 3);
+            if (rc) return rc;
+            const double lo = ctx->hres[0], hi = ctx->hres[1];
+            if (!(hi > lo)) return ctx->fail(MIREG_E_ARG, "constant field cannot be rescaled");
+            affine<T>(N, in, 1.0 / (hi - lo), -lo / (hi - lo), out, ctx->stream);
+            break;
+        }
+        case MIREG_OP_SCALE_MAXNORM: {
+            max_norm2<T>(in, N, ctx->partials, ctx->dres, ctx->stream);
+            int rc = readback(ctx, 1);
+            if (rc) return rc;
+            const double peak = std::sqrt(ctx->hres[0]);
+            if (!(peak > 0)) return ctx->fail(MIREG_E_ARG, "zero field cannot be scaled");
+            affine<T>(3 * N, in, arg / peak, 0.0, out, ctx->stream);
+            break;
+        }
+        default: return ctx->fail(MIREG_E_ARG, "unknown opcode %d", opcode);
+    }
+    return check_launch(ctx);
+}
+
+template <typename T>
+int make_twiddles(mireg_ctx *ctx) {
+    const int n[3] = {ctx->g.n1, ctx->g.n2, ctx->g.n3};
+    for (int a = 0; a < 3; ++a) {
+        std::vector<cx<T>> h(n[a]);
+        for (int j = 0; j < n[a]; ++j) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * j / n[a];
+            h[j].re = (T)cosl(ang);
+            h[j].im = (T)sinl(ang);
+        }
+        HIP_OK(hipMemcpy(ctx->tw[a], h.data(), n[a] * sizeof(cx<T>), hipMemcpyHostToDevice));
+    }
+    return MIREG_OK;
+}
+
+int alloc(mireg_ctx *ctx, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return ctx->fail(MIREG_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    ctx->allocs.push_back(*p);
+    ctx->bytes += bytes;
+    return MIREG_OK;
+}
+
+#define DISPATCH(ctx, CALL_F, CALL_D) ((ctx)->p.dtype == MIREG_F64 ? (CALL_D) : (CALL_F))
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+void mireg_default_params(mireg_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->n[0] = p->n[1] = p->n[2] = 32;
+    p->nt = 4;
+    p->interp_order = 3;
+    p->reg = MIREG_H1;
+    p->div = MIREG_DIV_NONE;
+    p->beta_v = 1e-2;
+    p->beta_w = 0.0;
+    p->dtype = MIREG_F32;
+}
+
+void mireg_default_solve_opts(mireg_solve_opts *o) {
+    if (!o) return;
+    o->grad_rtol = 5e-2;
+    o->grad_atol = 1e-6;
+    o->max_gn = 50;
+    o->max_pcg = 100;
+    o->armijo_c1 = 1e-4;
+    o->max_ls = 10;
+    o->log_level = 0;
+}
+
+int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
+    if (!p || !out) return MIREG_E_ARG;
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a)
+        if (!pow2_in_range(p->n[a])) return MIREG_E_SHAPE;
+    if (p->nt < 1 || p->nt > 64 || (p->interp_order != 1 && p->interp_order != 3) ||
+        (p->reg != MIREG_H1 && p->reg != MIREG_H2) || p->div < 0 || p->div > 2 || !(p->beta_v > 0) ||
+        !(p->beta_w >= 0) || (p->div == MIREG_DIV_NEAR && !(p->beta_w > 0)) ||
+        (p->dtype != MIREG_F32 && p->dtype != MIREG_F64))
+        return MIREG_E_ARG;
+    mireg_ctx *ctx = new (std::nothrow) mireg_ctx;
+    if (!ctx) return MIREG_E_NOMEM;
+    ctx->p = *p;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->g.n1 = p->n[0];
+    ctx->g.n2 = p->n[1];
+    ctx->g.n3 = p->n[2];
+    ctx->g.k3 = p->n[2] / 2 + 1;
+    ctx->g.N = (long long)p->n[0] * p->n[1] * p->n[2];
+    ctx->g.NS = (long long)p->n[0] * p->n[1] * ctx->g.k3;
+    ctx->elem = p->dtype == MIREG_F64 ? 8 : 4;
+    const size_t F = (size_t)ctx->g.N * ctx->elem;
+    const int nt = p->nt;
+    int rc = MIREG_OK;
+    if (!rc) rc = alloc(ctx, &ctx->mT, F);
+    if (!rc) rc = alloc(ctx, &ctx->mR, F);
+    if (!rc) rc = alloc(ctx, &ctx->v, 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->X, 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->Y, 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->m, (size_t)(nt + 1) * F);
+    if (!rc) rc = alloc(ctx, &ctx->gradm, (size_t)(nt + 1) * 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->d, F);
+    if (!rc) rc = alloc(ctx, &ctx->lam, 2 * F);
+    if (!rc) rc = alloc(ctx, &ctx->b, 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->vecs, (size_t)mireg_ctx::kVecs * 3 * F);
+    if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);
+    for (int a = 0; a < 3 && !rc; ++a) rc = alloc(ctx, &ctx->tw[a], (size_t)p->n[a] * 2 * ctx->elem);
+    if (!rc) rc = alloc(ctx, (void **)&ctx->partials, 4 * kRedBlocks * sizeof(double));
+    if (!rc) rc = alloc(ctx, (void **)&ctx->dres, 8 * sizeof(double));
+    if (!rc && hipHostMalloc((void **)&ctx->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        rc = ctx->fail(MIREG_E_NOMEM, "hipHostMalloc failed");
+    if (!rc) rc = DISPATCH(ctx, make_twiddles<float>(ctx), make_twiddles<double>(ctx));
+    if (!rc && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
+        rc = ctx->fail(MIREG_E_HIP, "hipEventCreate failed");
+    if (!rc) {
+        // zero initial velocity
+        if (hipMemsetAsync(ctx->v, 0, 3 * F, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            rc = ctx->fail(MIREG_E_HIP, "initialising the velocity failed");
+    }
+    if (rc) {
+        fprintf(stderr, "[mireg] create failed: %s\n", ctx->err.c_str());
+        mireg_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return MIREG_OK;
+}
+
+int mireg_destroy(mireg_ctx *ctx) {
+    if (!ctx) return MIREG_E_ARG;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    else hipDeviceSynchronize();
+    for (void *p : ctx->allocs) hipFree(p);
+    if (ctx->hres) hipHostFree(ctx->hres);
+    if (ctx->ev0) hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return MIREG_OK;
+}
+
+const char *mireg_last_error(const mireg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t mireg_workspace_bytes(const mireg_ctx *ctx) { return ctx ? ctx->bytes : 0; }
+
+int mireg_set_images(mireg_ctx *ctx, const void *mT, const void *mR) {
+    if (!ctx || !mT || !mR) return ctx ? ctx->fail(MIREG_E_ARG, "null image pointer") : MIREG_E_ARG;
+    return DISPATCH(ctx, impl_set_images<float>(ctx, (const float *)mT, (const float *)mR),
+                    impl_set_images<double>(ctx, (const double *)mT, (const double *)mR));
+}
+
+int mireg_set_velocity(mireg_ctx *ctx, const void *v) {
+    if (!ctx || !v) return ctx ? ctx->fail(MIREG_E_ARG, "null velocity pointer") : MIREG_E_ARG;
+    return DISPATCH(ctx, impl_set_velocity<float>(ctx, (const float *)v),
+                    impl_set_velocity<double>(ctx, (const double *)v));
+}
+
+int mireg_get_velocity(mireg_ctx *ctx, void *v) {
+    if (!ctx || !v) return ctx ? ctx->fail(MIREG_E_ARG, "null velocity pointer") : MIREG_E_ARG;
+    HIP_OK(hipMemcpyAsync(v, ctx->v, 3 * ctx->N() * ctx->elem, hipMemcpyDeviceToDevice, ctx->stream));
+    return MIREG_OK;
+}
+
+int mireg_objective(mireg_ctx *ctx, double *J, double *mismatch, double *reg) {
+    if (!ctx) return MIREG_E_ARG;
+    return DISPATCH(ctx, impl_objective<float>(ctx, J, mismatch, reg), impl_objective<double>(ctx, J, mismatch, reg));
+}
+
+int mireg_gradient(mireg_ctx *ctx, void *g, double *gnorm) {
+    if (!ctx || !g) return ctx ? ctx->fail(MIREG_E_ARG, "null gradient pointer") : MIREG_E_ARG;
+    return DISPATCH(ctx, impl_gradient<float>(ctx, (float *)g, gnorm), impl_gradient<double>(ctx, (double *)g, gnorm));
+}
+
+int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt) {
+    if (!ctx || !vt || !Hvt) return ctx ? ctx->fail(MIREG_E_ARG, "null matvec pointer") : MIREG_E_ARG;
+    if (vt == Hvt) return ctx->fail(MIREG_E_ARG, "vt and Hvt must not alias");
+    return DISPATCH(ctx, impl_matvec<float>(ctx, (const float *)vt, (float *)Hvt),
+                    impl_matvec<double>(ctx, (const double *)vt, (double *)Hvt));
+}
+
+int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
+    if (!ctx || !r || !z) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
+    return DISPATCH(ctx, impl_precond<float>(ctx, (const float *)r, (float *)z),
+                    impl_precond<double>(ctx, (const double *)r, (double *)z));
+}
+
+int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit, int *iters,
+                    double *relres) {
+    if (!ctx || !rhs || !x) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
+    if (maxit < 0 || !(rtol >= 0)) return ctx->fail(MIREG_E_ARG, "invalid rtol/maxit");
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    return DISPATCH(ctx, impl_pcg<float>(ctx, (const float *)rhs, (float *)x, rtol, maxit, iters, relres),
+                    impl_pcg<double>(ctx, (const double *)rhs, (double *)x, rtol, maxit, iters, relres));
+}
+
+int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts, mireg_report *rep) {
+    if (!ctx || !v_inout) return ctx ? ctx->fail(MIREG_E_ARG, "null velocity pointer") : MIREG_E_ARG;
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    mireg_solve_opts o;
+    mireg_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_gn < 0 || o.max_pcg < 0 || o.max_ls < 0) return ctx->fail(MIREG_E_ARG, "negative iteration cap");
+    return DISPATCH(ctx, impl_gn<float>(ctx, (float *)v_inout, &o, rep), impl_gn<double>(ctx, (double *)v_inout, &o, rep));
+}
+
+int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg) {
+    if (!ctx || !in || !out) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
+    return DISPATCH(ctx, impl_op<float>(ctx, opcode, (const float *)in, (float *)out, arg),
+                    impl_op<double>(ctx, opcode, (const double *)in, (double *)out, arg));
+}
+
+int mireg_timers_enable(mireg_ctx *ctx, int on) {
+    if (!ctx) return MIREG_E_ARG;
+    ctx->tm.on = on != 0;
+    return MIREG_OK;
+}
+
+int mireg_timers_read(mireg_ctx *ctx, mireg_timers *t, int reset) {
+    if (!ctx || !t) return MIREG_E_ARG;
+    t->fft_ms = ctx->tm.fft_ms;
+    t->interp_ms = ctx->tm.interp_ms;
+    t->other_ms = ctx->tm.other_ms;
+    t->launches = ctx->tm.launches;
+    if (reset) {
+        bool on = ctx->tm.on;
+        ctx->tm = Timers{};
+        ctx->tm.on = on;
+    }
+    return MIREG_OK;
+}
+
+}  // extern "C"

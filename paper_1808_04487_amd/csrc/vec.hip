@@ -1,0 +1,269 @@
+// Vector kernels and FP64 reductions for the Krylov and line-search scalars.
+//
+// Reductions are two-stage and deterministic: kRedBlocks workgroups each
+// reduce a grid-stride share into one FP64 partial, then a single workgroup
+// combines the partials in a fixed order.  FP32 inputs are widened to FP64
+// before any arithmetic, so dot products, norms and the objective are FP64
+// for both storage types.
+#include <float.h>
+
+#include "kernels.hpp"
+
+namespace mireg {
+
+constexpr int kRedThreads = 256;
+
+// Block-wide sum of NV doubles per thread; thread 0 ends with the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double sh[NV][kRedThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[k][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0;
+            for (int w = 0; w < kRedThreads / 64; ++w) s += sh[k][w];
+            v[k] = s;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_dot(const T *__restrict__ a, const T *__restrict__ b,
+                                                     long long n, double *__restrict__ part) {
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads)
+        v[0] += (double)a[i] * (double)b[i];
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_sumsq_diff(const T *__restrict__ a, const T *__restrict__ b,
+                                                            long long n, double *__restrict__ part) {
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double d = (double)a[i] - (double)b[i];
+        v[0] += d * d;
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_pcg_update(long long n, double k, const T *__restrict__ s,
+                                                            const T *__restrict__ Hs, T *__restrict__ x,
+                                                            T *__restrict__ r, double *__restrict__ part) {
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        x[i] = (T)((double)x[i] + k * (double)s[i]);
+        const T ri = (T)((double)r[i] - k * (double)Hs[i]);
+        r[i] = ri;
+        v[0] += (double)ri * (double)ri;
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Final stage for sums: result[k] = sum_b part[b * NV + k] ... partials are
+// stored field-major: part[k * kRedBlocks + b].
+template <int NV>
+__global__ __launch_bounds__(kRedThreads) void k_finish_sum(const double *__restrict__ part, double *__restrict__ res) {
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0;
+        for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads) s += part[k * kRedBlocks + b];
+        v[k] = s;
+    }
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) res[k] = v[k];
+    }
+}
+
+// min, max and non-finite count in one sweep
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_minmax(const T *__restrict__ a, long long n,
+                                                        double *__restrict__ part) {
+    __shared__ double smin[kRedThreads], smax[kRedThreads], sbad[kRedThreads];
+    double mn = DBL_MAX, mx = -DBL_MAX, bad = 0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double x = (double)a[i];
+        if (!isfinite(x)) {
+            bad += 1;
+        } else {
+            mn = fmin(mn, x);
+            mx = fmax(mx, x);
+        }
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = smin[0];
+        part[kRedBlocks + blockIdx.x] = smax[0];
+        part[2 * kRedBlocks + blockIdx.x] = sbad[0];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_finish_minmax(const double *__restrict__ part,
+                                                               double *__restrict__ res) {
+    if (threadIdx.x == 0) {
+        double mn = DBL_MAX, mx = -DBL_MAX, bad = 0;
+        for (int b = 0; b < kRedBlocks; ++b) {
+            mn = fmin(mn, part[b]);
+            mx = fmax(mx, part[kRedBlocks + b]);
+            bad += part[2 * kRedBlocks + b];
+        }
+        res[0] = mn;
+        res[1] = mx;
+        res[2] = bad;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_max_norm2(const T *__restrict__ v, long long N,
+                                                           double *__restrict__ part) {
+    __shared__ double sm[kRedThreads];
+    double mx = 0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kRedThreads) {
+        const double a = v[i], b = v[N + i], c = v[2 * N + i];
+        mx = fmax(mx, a * a + b * b + c * c);
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_finish_max(const double *__restrict__ part,
+                                                            double *__restrict__ res) {
+    if (threadIdx.x == 0) {
+        double mx = 0;
+        for (int b = 0; b < kRedBlocks; ++b) mx = fmax(mx, part[b]);
+        res[0] = mx;
+    }
+}
+
+template <typename T>
+__global__ void k_axpby(long long n, double a, const T *__restrict__ x, double b, T *__restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+
+template <typename T>
+__global__ void k_xpay(long long n, const T *x, double a, const T *y, T *z) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        z[i] = (T)((double)x[i] + a * (double)y[i]);
+}
+
+template <typename T>
+__global__ void k_affine(long long n, const T *__restrict__ x, double a, double b, T *__restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = (T)(a * (double)x[i] + b);
+}
+
+template <typename T>
+__global__ void k_fill(long long n, T val, T *__restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = val;
+}
+
+static inline unsigned stream_blocks(long long n) {
+    long long b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <typename T>
+void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
+    hipLaunchKernelGGL((k_dot<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
+    hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
+}
+template <typename T>
+void sumsq_diff(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
+    hipLaunchKernelGGL((k_sumsq_diff<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
+    hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
+}
+template <typename T>
+void pcg_update(long long n, double k, const T *sdir, const T *Hs, T *x, T *r, double *partials,
+                double *result, hipStream_t s) {
+    hipLaunchKernelGGL((k_pcg_update<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, k, sdir, Hs, x, r,
+                       partials);
+    hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
+}
+template <typename T>
+void minmax_nonfinite(const T *a, long long n, double *partials, double *result, hipStream_t s) {
+    hipLaunchKernelGGL((k_minmax<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, n, partials);
+    hipLaunchKernelGGL(k_finish_minmax, dim3(1), dim3(kRedThreads), 0, s, partials, result);
+}
+template <typename T>
+void max_norm2(const T *v, long long N, double *partials, double *result, hipStream_t s) {
+    hipLaunchKernelGGL((k_max_norm2<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, v, N, partials);
+    hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(kRedThreads), 0, s, partials, result);
+}
+template <typename T>
+void axpby(long long n, double a, const T *x, double b, T *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpby<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, a, x, b, y);
+}
+template <typename T>
+void xpay(long long n, const T *x, double a, const T *y, T *z, hipStream_t s) {
+    hipLaunchKernelGGL((k_xpay<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, x, a, y, z);
+}
+template <typename T>
+void affine(long long n, const T *x, double a, double b, T *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_affine<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, x, a, b, y);
+}
+template <typename T>
+void fill(long long n, T val, T *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, val, y);
+}
+
+#define MIREG_INST(T)                                                                                 \
+    template void dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);           \
+    template void sumsq_diff<T>(const T *, const T *, long long, double *, double *, hipStream_t);    \
+    template void pcg_update<T>(long long, double, const T *, const T *, T *, T *, double *, double *, \
+                                hipStream_t);                                                         \
+    template void minmax_nonfinite<T>(const T *, long long, double *, double *, hipStream_t);         \
+    template void max_norm2<T>(const T *, long long, double *, double *, hipStream_t);                \
+    template void axpby<T>(long long, double, const T *, double, T *, hipStream_t);                   \
+    template void xpay<T>(long long, const T *, double, const T *, T *, hipStream_t);                 \
+    template void affine<T>(long long, const T *, double, double, T *, hipStream_t);                  \
+    template void fill<T>(long long, T, T *, hipStream_t);
+MIREG_INST(float)
+MIREG_INST(double)
+#undef MIREG_INST
+
+}  // namespace mireg

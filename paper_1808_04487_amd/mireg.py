@@ -1,0 +1,259 @@
+"""Python binding of the mireg C-ABI (include/mireg.h).
+
+Argument marshalling only: tensors are checked (device, dtype, shape,
+contiguity) and their device pointers handed to libmireg.so, which runs
+every step on the GPU.  There is no fallback: if the library is missing
+this module raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmireg.so")
+
+OK, E_ARG, E_SHAPE, E_STATE, E_HIP, E_NOMEM, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+H1, H2 = 1, 2
+DIV_NONE, DIV_NEAR, DIV_LERAY = 0, 1, 2
+CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL = 1, 2, 3, 4
+
+OPS = {
+    "grad": 1, "div": 2, "laplace": 3, "apply_A": 4, "apply_K": 5, "leray": 6, "precond": 7,
+    "gauss": 8, "departure_X": 9, "departure_Y": 10, "transport_state": 11, "interp": 12,
+    "rescale01": 13, "scale_maxnorm": 14,
+}
+# (input components, output components); interp takes f and a displacement (1 + 3)
+_OP_SHAPES = {
+    "grad": (1, 3), "div": (3, 1), "laplace": (1, 1), "apply_A": (3, 3), "apply_K": (3, 3),
+    "leray": (3, 3), "precond": (3, 3), "gauss": (1, 1), "departure_X": (3, 3),
+    "departure_Y": (3, 3), "transport_state": (1, 1), "interp": (4, 1), "rescale01": (1, 1),
+    "scale_maxnorm": (3, 3),
+}
+
+
+class MiregError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mireg error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("nt", ctypes.c_int), ("interp_order", ctypes.c_int),
+                ("reg", ctypes.c_int), ("div", ctypes.c_int), ("beta_v", ctypes.c_double),
+                ("beta_w", ctypes.c_double), ("dtype", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("grad_rtol", ctypes.c_double), ("grad_atol", ctypes.c_double),
+                ("max_gn", ctypes.c_int), ("max_pcg", ctypes.c_int),
+                ("armijo_c1", ctypes.c_double), ("max_ls", ctypes.c_int),
+                ("log_level", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("gn_iters", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("pde_solves", ctypes.c_int), ("pcg_iters", ctypes.c_int),
+                ("ls_trials", ctypes.c_int), ("J0", ctypes.c_double), ("J", ctypes.c_double),
+                ("mismatch_rel", ctypes.c_double), ("gnorm0", ctypes.c_double),
+                ("gnorm", ctypes.c_double), ("gnorm_rel", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Timers(ctypes.Structure):
+    _fields_ = [("fft_ms", ctypes.c_double), ("interp_ms", ctypes.c_double),
+                ("other_ms", ctypes.c_double), ("launches", ctypes.c_long)]
+
+
+# exported symbols and their signatures (argtypes, restype)
+_vp, _ip, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "mireg_default_params": ([ctypes.POINTER(Params)], None),
+    "mireg_default_solve_opts": ([ctypes.POINTER(SolveOpts)], None),
+    "mireg_create": ([ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "mireg_destroy": ([_vp], ctypes.c_int),
+    "mireg_last_error": ([_vp], ctypes.c_char_p),
+    "mireg_workspace_bytes": ([_vp], ctypes.c_size_t),
+    "mireg_set_images": ([_vp, _vp, _vp], ctypes.c_int),
+    "mireg_set_velocity": ([_vp, _vp], ctypes.c_int),
+    "mireg_get_velocity": ([_vp, _vp], ctypes.c_int),
+    "mireg_objective": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+    "mireg_gradient": ([_vp, _vp, _dp], ctypes.c_int),
+    "mireg_hessian_matvec": ([_vp, _vp, _vp], ctypes.c_int),
+    "mireg_precond_apply": ([_vp, _vp, _vp], ctypes.c_int),
+    "mireg_pcg_solve": ([_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp], ctypes.c_int),
+    "mireg_gn_solve": ([_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)], ctypes.c_int),
+    "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
+    "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mireg_timers_read": ([_vp, ctypes.POINTER(Timers), ctypes.c_int], ctypes.c_int),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libmireg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MiregError(E_STATE, "%s is missing: build it with __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _torch_dtype(dtype):
+    if dtype in (torch.float32, "f32", "float32", F32):
+        return torch.float32, F32
+    if dtype in (torch.float64, "f64", "float64", F64):
+        return torch.float64, F64
+    raise ValueError("dtype must be float32 or float64")
+
+
+class Context:
+    """One registration problem on the current CUDA (HIP) device.
+
+    n: grid (n1, n2, n3); nt: time steps; order: 3 (tricubic) or 1
+    (trilinear); reg: H1 or H2; div: DIV_NONE / DIV_NEAR / DIV_LERAY.
+    All work runs on the torch stream current at creation.
+    """
+
+    def __init__(self, n, nt=4, order=3, reg=H1, div=DIV_NONE, beta_v=1e-2, beta_w=0.0,
+                 dtype=torch.float32, device=None):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise MiregError(E_STATE, "no HIP device available")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.dtype, code = _torch_dtype(dtype)
+        self.n = tuple(int(x) for x in n)
+        p = Params()
+        self.lib.mireg_default_params(ctypes.byref(p))
+        p.n[0], p.n[1], p.n[2] = self.n
+        p.nt, p.interp_order, p.reg, p.div = int(nt), int(order), int(reg), int(div)
+        p.beta_v, p.beta_w, p.dtype = float(beta_v), float(beta_w), code
+        self.params = p
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            rc = self.lib.mireg_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise MiregError(rc, "mireg_create failed for n=%s" % (self.n,))
+        self.h = h
+        self.N = self.n[0] * self.n[1] * self.n[2]
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != OK:
+            raise MiregError(rc, self.lib.mireg_last_error(self.h).decode())
+
+    def _arg(self, t, comps, name):
+        shape = self.n if comps == 1 else (comps,) + self.n
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device != self.device or t.dtype != self.dtype:
+            raise ValueError("%s must be %s on %s" % (name, self.dtype, self.device))
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous tensor of shape %s" % (name, shape))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self, comps=1):
+        shape = self.n if comps == 1 else (comps,) + self.n
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mireg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- C-ABI mirrors ------------------------------------------------------
+    def workspace_bytes(self):
+        return int(self.lib.mireg_workspace_bytes(self.h))
+
+    def set_images(self, mT, mR):
+        self._check(self.lib.mireg_set_images(self.h, self._arg(mT, 1, "mT"), self._arg(mR, 1, "mR")))
+
+    def set_velocity(self, v):
+        self._check(self.lib.mireg_set_velocity(self.h, self._arg(v, 3, "v")))
+
+    def get_velocity(self, out=None):
+        out = self.empty(3) if out is None else out
+        self._check(self.lib.mireg_get_velocity(self.h, self._arg(out, 3, "out")))
+        return out
+
+    def objective(self):
+        J, mis, reg = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.mireg_objective(self.h, ctypes.byref(J), ctypes.byref(mis), ctypes.byref(reg)))
+        return J.value, mis.value, reg.value
+
+    def gradient(self, out=None):
+        out = self.empty(3) if out is None else out
+        gn = ctypes.c_double()
+        self._check(self.lib.mireg_gradient(self.h, self._arg(out, 3, "g"), ctypes.byref(gn)))
+        return out, gn.value
+
+    def hessian_matvec(self, vt, out=None):
+        out = self.empty(3) if out is None else out
+        self._check(self.lib.mireg_hessian_matvec(self.h, self._arg(vt, 3, "vt"), self._arg(out, 3, "Hvt")))
+        return out
+
+    def precond(self, r, out=None):
+        out = self.empty(3) if out is None else out
+        self._check(self.lib.mireg_precond_apply(self.h, self._arg(r, 3, "r"), self._arg(out, 3, "z")))
+        return out
+
+    def pcg(self, rhs, rtol=1e-3, maxit=100, out=None):
+        out = self.empty(3) if out is None else out
+        it, rel = ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.mireg_pcg_solve(self.h, self._arg(rhs, 3, "rhs"), self._arg(out, 3, "x"),
+                                             float(rtol), int(maxit), ctypes.byref(it), ctypes.byref(rel)))
+        return out, it.value, rel.value
+
+    def gn_solve(self, v0=None, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
+                 armijo_c1=1e-4, max_ls=10, log_level=0):
+        """Returns (v, report dict); v0 (warm start) defaults to zero."""
+        v = torch.zeros((3,) + self.n, dtype=self.dtype, device=self.device) if v0 is None else v0.clone()
+        o = SolveOpts(float(grad_rtol), float(grad_atol), int(max_gn), int(max_pcg), float(armijo_c1),
+                      int(max_ls), int(log_level))
+        rep = Report()
+        self._check(self.lib.mireg_gn_solve(self.h, self._arg(v, 3, "v"), ctypes.byref(o), ctypes.byref(rep)))
+        return v, rep.as_dict()
+
+    def op(self, name, x, arg=0.0, out=None):
+        cin, cout = _OP_SHAPES[name]
+        if name == "interp":
+            if not (isinstance(x, torch.Tensor) and x.numel() == 4 * self.N and x.is_contiguous()):
+                raise ValueError("interp takes a contiguous [4][n...] tensor (f then displacement)")
+            ptr = self._arg(x.view((4,) + self.n), 4, "x")
+        else:
+            ptr = self._arg(x, cin, "x")
+        out = self.empty(cout) if out is None else out
+        self._check(self.lib.mireg_op(self.h, OPS[name], ptr, self._arg(out, cout, "out"), float(arg)))
+        return out
+
+    def timers(self, enable=None, reset=False):
+        if enable is not None:
+            self._check(self.lib.mireg_timers_enable(self.h, int(bool(enable))))
+        t = Timers()
+        self._check(self.lib.mireg_timers_read(self.h, ctypes.byref(t), int(bool(reset))))
+        return {"fft_ms": t.fft_ms, "interp_ms": t.interp_ms, "other_ms": t.other_ms, "launches": t.launches}
