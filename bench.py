@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the GN-Krylov registration hot path on one MI355X.
+
+Workload (the paper's method on a 256^3 FP32 problem): a periodic Voronoi
+phantom (120 seeds, Gaussian-smoothed with sigma = 2 cells, rescaled to
+[0, 1]) as template, transported by a smooth random velocity (Gaussian-
+filtered white noise, Leray-projected, max |v| = 0.15 * 2 pi) to make the
+reference; H1-div regularisation with beta_v = 5e-3, beta_w = 1; nt = 4,
+tricubic interpolation, spectral preconditioner, GN-Krylov to relative
+gradient 5e-2.  Inputs are synthetic and seeded; they are generated and
+uploaded before any timed region.
+
+One step = one full GN-Krylov solve from v = 0 (departure points, state,
+objective, adjoint, gradient, PCG with Hessian matvecs, line search).
+value = Hessian matvecs per second of the whole job: matvecs performed in
+the K timed solves divided by their wall time.  The matvec-only rate, the
+per-kernel breakdown (HIP events on the library stream) and the dominant
+kernel's HBM roofline are reported beside it, and the FP64 CPU oracle is
+timed on a bounded sample of the same recipe as the CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, vendor figure
+TWO_PI = 2.0 * math.pi
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed GN solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed GN solves")
+    ap.add_argument("--n", type=int, default=256, help="grid size per axis")
+    ap.add_argument("--matvecs", type=int, default=20, help="matvecs in the matvec-only timing")
+    ap.add_argument("--cpu-n", type=int, default=128, help="grid of the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_inputs(ctx, n, torch):
+    """Config recipe on the GPU with the library's own operators."""
+    from paper_1808_04487_amd import synth
+
+    dev = ctx.device
+    raw = torch.from_numpy(synth.voronoi_phantom((n, n, n), nseeds=120, seed=1)).to(dev, torch.float32)
+    mT = ctx.op("rescale01", ctx.op("gauss", raw, 2.0))
+    sig = n / 8.0  # physical sigma pi/4 in cells
+
+    def smooth_velocity(seed):
+        noise = torch.from_numpy(synth.white_noise((n, n, n), seed=seed)).to(dev, torch.float32)
+        sm = torch.stack([ctx.op("gauss", noise[c].contiguous(), sig) for c in range(3)]).contiguous()
+        return ctx.op("scale_maxnorm", ctx.op("leray", sm), 0.15 * TWO_PI)
+
+    v_true = smooth_velocity(2)
+    probe = smooth_velocity(3)
+    ctx.set_velocity(v_true)
+    mR = ctx.op("transport_state", mT)
+    ctx.set_velocity(torch.zeros_like(v_true))
+    return mT, mR, v_true, probe
+
+
+def cpu_baseline(args):
+    """FP64 oracle on the host cores: per-velocity setup, then Hessian matvecs
+    at --cpu-n^3 on the same recipe; the rate is scaled to 256^3 by the point
+    count (the matvec is dominated by O(N) transport work)."""
+    import numpy as np
+
+    from oracle import core, prep
+    from paper_1808_04487_amd import synth
+
+    m = args.cpu_n
+    n = (m, m, m)
+    g = core.Grid(n)
+    raw = synth.voronoi_phantom(n, nseeds=120, seed=1)
+    mT = prep.smooth_rescale(g, raw, 2.0)
+    v_true = prep.smooth_velocity(g, synth.white_noise(n, seed=2), math.pi / 4, 0.15 * TWO_PI)
+    probe = prep.smooth_velocity(g, synth.white_noise(n, seed=3), math.pi / 4, 0.15 * TWO_PI)
+    mR = prep.transport(g, mT, v_true)
+    p = core.Params(n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
+    R = core.Registration(p, mT, mR)
+    R.set_velocity(v_true)
+    t0 = time.perf_counter()
+    R.gradient()  # builds X, Y, state history, grad m, div v
+    t_setup = time.perf_counter() - t0
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        R.hessian_matvec(probe)
+    t_mv = (time.perf_counter() - t0) / reps
+    scale = (m ** 3) / float(args.n ** 3)
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {
+        "value": round(scale / t_mv, 6),
+        "unit": "Hessian matvecs/s at %d^3 (scaled from %d^3 by point count)" % (args.n, m),
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "FP64 oracle, %d^3 same recipe: setup %.2f s, %d GN Hessian matvecs at %.2f s each"
+                  % (m, t_setup, reps, t_mv),
+    }
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_1808_04487_amd import mireg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    n = args.n
+    ctx = mireg.Context((n, n, n), nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3,
+                        beta_w=1.0, dtype=torch.float32)
+    log(args, "context %d^3, workspace %.2f GB" % (n, ctx.workspace_bytes() / 1e9))
+    t0 = time.perf_counter()
+    mT, mR, v_true, probe = make_inputs(ctx, n, torch)
+    ctx.set_images(mT, mR)
+    torch.cuda.synchronize()
+    log(args, "inputs ready in %.1f s" % (time.perf_counter() - t0))
+
+    opts = dict(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+    for w in range(args.warmup):
+        _, rep = ctx.gn_solve(**opts)
+        log(args, "warmup solve %d: %s" % (w, rep))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for k in range(args.steps):
+        _, rep = ctx.gn_solve(**opts)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for k, rep in enumerate(reps):
+        log(args, "timed solve %d: %s" % (k, rep))
+    total_mv = sum(r["matvecs"] for r in reps)
+    value = total_mv / wall
+
+    # matvec-only rate at the generating velocity with the probe direction
+    ctx.set_velocity(v_true)
+    out = ctx.empty(3)
+    for _ in range(3):
+        ctx.hessian_matvec(probe, out)
+    stream = ctx.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.matvecs):
+        ctx.hessian_matvec(probe, out)
+    e1.record(stream)
+    e1.synchronize()
+    mv_ms = e0.elapsed_time(e1) / args.matvecs
+    log(args, "matvec-only: %.3f ms (%.1f matvecs/s)" % (mv_ms, 1000.0 / mv_ms))
+
+    # per-kernel event timing over a separate run of matvecs
+    ctx.kernel_stats(enable=True, reset=True)
+    for _ in range(args.matvecs):
+        ctx.hessian_matvec(probe, out)
+    stats = ctx.kernel_stats(enable=False, reset=True)
+    per_mv = {k: (v[1] / args.matvecs, v[0] / args.matvecs, v[1] / v[0], v[2]) for k, v in stats.items()}
+    dom = max(per_mv, key=lambda k: per_mv[k][0])
+    avg_ms, bytes_launch = per_mv[dom][2], per_mv[dom][3]
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"ms_per_matvec": round(v[0], 4), "launches_per_matvec": v[1],
+                   "avg_ms": round(v[2], 4), "GBps": round(v[3] / (v[2] * 1e-3) / 1e9, 1)}
+               for k, v in sorted(per_mv.items(), key=lambda kv: -kv[1][0])}
+    for k, v in kernels.items():
+        log(args, "kernel %-18s %s" % (k, v))
+    fft_ms = sum(v[0] for k, v in per_mv.items() if k.startswith("fft"))
+    sl_ms = sum(v[0] for k, v in per_mv.items() if k.startswith("sl_"))
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            from paper_1808_04487_amd import build as hb
+
+            t = json.load(open(tpath))
+            if t.get("kernel") == dom and t.get("source_sha") == hb.source_sha():
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "timing the CPU oracle sample")
+        cpu = cpu_baseline(args)
+
+    solve_s = wall / max(1, args.steps)
+    line = {
+        "metric": "Hessian matvecs/s at 256^3 (whole GN-Krylov solve), time-to-tol, fraction of HBM BW",
+        "value": round(value, 3),
+        "unit": "Hessian matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * solve_s, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "voronoi-phantom registration %d^3 FP32, H1-div beta_v=5e-3 beta_w=1, "
+                               "nt=4 tricubic, spectral PC, eps_g=5e-2" % n,
+                   "grid": [n, n, n], "nt": 4, "parallelism": "single-gpu"},
+        "time_to_tol_s": round(solve_s, 4),
+        "solve": {k: reps[-1][k] for k in ("status", "gn_iters", "matvecs", "pde_solves", "ls_trials",
+                                            "mismatch_rel", "gnorm_rel")},
+        "matvec_only_per_s": round(1000.0 / mv_ms, 2),
+        "matvec_ms": round(mv_ms, 4),
+        "fft_ms_per_matvec": round(fft_ms, 4),
+        "interp_ms_per_matvec": round(sl_ms, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

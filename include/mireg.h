@@ -190,6 +190,23 @@ typedef struct {
 int mireg_timers_enable(mireg_ctx *ctx, int on);
 int mireg_timers_read(mireg_ctx *ctx, mireg_timers *t, int reset);
 
+/* Per-kernel statistics: when enabled, every kernel launch of the context is
+ * bracketed by HIP events on the context stream; reading synchronises the
+ * stream and returns, per kernel kind, the number of launches, the summed
+ * event time and the algorithmic bytes of one launch (compulsory reads and
+ * writes of its distinct operands, stencil re-reads not counted).  The
+ * events add a little launch overhead; timing runs use them on their own. */
+typedef struct {
+    char name[32];
+    long launches;
+    double total_ms;
+    double bytes_per_launch;  /* average over the launches */
+} mireg_kernel_stat;
+int mireg_kernel_stats_enable(mireg_ctx *ctx, int on);
+/* Writes up to `max` entries (kernel kinds with at least one launch) and
+ * sets *count; reset != 0 clears the accumulators. */
+int mireg_kernel_stats_read(mireg_ctx *ctx, mireg_kernel_stat *out, int max, int *count, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -318,6 +318,7 @@ template <typename T>
 static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
                        hipStream_t s) {
     const long long lines = (long long)g.n1 * g.n2;
+    HookScope hs(K_R2C, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
 #define MIREG_L(M)                                                                          \
     {                                                                                       \
         dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
@@ -331,6 +332,7 @@ template <typename T>
 static void launch_c2r(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
                        hipStream_t s) {
     const long long lines = (long long)g.n1 * g.n2;
+    HookScope hs(K_C2R, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
 #define MIREG_L(M)                                                                          \
     {                                                                                       \
         dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
@@ -344,6 +346,7 @@ template <typename T, int DIR>
 static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipStream_t s) {
     const long long Q = (long long)g.n1 * g.k3, inner = g.k3, ostride = (long long)g.n2 * g.k3,
                     pstride = g.k3;
+    HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
 #define MIREG_L(L)                                                                           \
     {                                                                                        \
         dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W), nf);          \
@@ -355,9 +358,10 @@ static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipSt
 }
 
 template <typename T, int KIND>
-static void launch_x1(const Grid &g, FieldPtrs f, const OpConst<T> &oc, const cx<T> *tw,
-                      hipStream_t s) {
+static void launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpConst<T> &oc,
+                      const cx<T> *tw, hipStream_t s) {
     const long long Q = (long long)g.n2 * g.k3;
+    HookScope hs(K_X1_SCALE + KIND, (double)(nin + nout) * sizeof(T) * 2.0 * g.NS);
 #define MIREG_L(L)                                                                              \
     {                                                                                           \
         dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W));                 \
@@ -396,11 +400,11 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *
     launch_r2c<T>(g, fin, fspec, nin, tw.t[2], s);
     launch_x2<T, -1>(g, fspec, nin, tw.t[1], s);
     switch (kind) {
-        case SPEC_SCALE: launch_x1<T, SPEC_SCALE>(g, fspec, oc, tw.t[0], s); break;
-        case SPEC_GRAD: launch_x1<T, SPEC_GRAD>(g, fspec, oc, tw.t[0], s); break;
-        case SPEC_DIV: launch_x1<T, SPEC_DIV>(g, fspec, oc, tw.t[0], s); break;
-        case SPEC_PROJ: launch_x1<T, SPEC_PROJ>(g, fspec, oc, tw.t[0], s); break;
-        default: launch_x1<T, SPEC_TAIL>(g, fspec, oc, tw.t[0], s); break;
+        case SPEC_SCALE: launch_x1<T, SPEC_SCALE>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        case SPEC_GRAD: launch_x1<T, SPEC_GRAD>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        case SPEC_DIV: launch_x1<T, SPEC_DIV>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        case SPEC_PROJ: launch_x1<T, SPEC_PROJ>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        default: launch_x1<T, SPEC_TAIL>(g, fspec, nin, nout, oc, tw.t[0], s); break;
     }
     launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
     launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);

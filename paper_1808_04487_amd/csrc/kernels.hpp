@@ -5,6 +5,31 @@
 
 namespace mireg {
 
+// Kernel kinds for the per-launch statistics.
+enum KernelId {
+    K_R2C = 0, K_C2C_FWD, K_C2C_INV, K_X1_SCALE, K_X1_GRAD, K_X1_DIV, K_X1_PROJ, K_X1_TAIL, K_C2R,
+    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
+    K_COUNT
+};
+extern const char *const kKernelNames[K_COUNT];
+
+// Optional observer of kernel launches (per-kernel event timing); set by the
+// host for the duration of an entry point, null otherwise.
+struct KernelHook {
+    virtual void begin(int kid, double bytes) = 0;
+    virtual void end() = 0;
+    virtual ~KernelHook() {}
+};
+extern thread_local KernelHook *g_hook;
+struct HookScope {
+    explicit HookScope(int kid, double bytes) {
+        if (g_hook) g_hook->begin(kid, bytes);
+    }
+    ~HookScope() {
+        if (g_hook) g_hook->end();
+    }
+};
+
 // Up to six field base pointers handed to one launch.
 struct FieldPtrs {
     void *p[6];

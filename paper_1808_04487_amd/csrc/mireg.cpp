@@ -31,6 +31,71 @@ struct Timers {
     long launches = 0;
 };
 
+// Per-kernel HIP-event timing: each launch is bracketed by two events on the
+// context stream; elapsed times are harvested lazily (pool of event pairs).
+struct StatsHook : mireg::KernelHook {
+    hipStream_t stream = nullptr;
+    struct Pending {
+        int kid;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> free_ev;
+    std::vector<Pending> pending;
+    Pending cur{};
+    int depth = 0;
+    struct Acc {
+        long n = 0;
+        double ms = 0, bytes = 0;
+    } acc[mireg::K_COUNT];
+
+    hipEvent_t take() {
+        if (free_ev.empty()) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            return e;
+        }
+        hipEvent_t e = free_ev.back();
+        free_ev.pop_back();
+        return e;
+    }
+    void begin(int kid, double bytes) override {
+        if (depth++ > 0) return;
+        if (pending.size() >= 4096) harvest();
+        cur.kid = kid;
+        cur.bytes = bytes;
+        cur.a = take();
+        cur.b = take();
+        hipEventRecord(cur.a, stream);
+    }
+    void end() override {
+        if (--depth > 0) return;
+        hipEventRecord(cur.b, stream);
+        pending.push_back(cur);
+    }
+    void harvest() {
+        for (auto &p : pending) {
+            hipEventSynchronize(p.b);
+            float ms = 0;
+            hipEventElapsedTime(&ms, p.a, p.b);
+            acc[p.kid].n += 1;
+            acc[p.kid].ms += ms;
+            acc[p.kid].bytes += p.bytes;
+            free_ev.push_back(p.a);
+            free_ev.push_back(p.b);
+        }
+        pending.clear();
+    }
+    void reset() {
+        harvest();
+        for (auto &a : acc) a = Acc{};
+    }
+    ~StatsHook() override {
+        harvest();
+        for (hipEvent_t e : free_ev) hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 struct mireg_ctx {
@@ -59,6 +124,8 @@ struct mireg_ctx {
     bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool stats_on = false;
+    StatsHook stats;
 
     static constexpr int kVecs = 8;
 
@@ -638,7 +705,14 @@ int alloc(mireg_ctx *ctx, void **p, size_t bytes) {
     return MIREG_OK;
 }
 
-#define DISPATCH(ctx, CALL_F, CALL_D) ((ctx)->p.dtype == MIREG_F64 ? (CALL_D) : (CALL_F))
+// Installs the context's kernel observer for the duration of an entry point.
+struct HookGuard {
+    explicit HookGuard(mireg_ctx *ctx) { mireg::g_hook = (ctx && ctx->stats_on) ? &ctx->stats : nullptr; }
+    ~HookGuard() { mireg::g_hook = nullptr; }
+};
+
+#define DISPATCH(ctx, CALL_F, CALL_D) \
+    (HookGuard{ctx}, ((ctx)->p.dtype == MIREG_F64 ? (CALL_D) : (CALL_F)))
 
 }  // namespace
 
@@ -810,6 +884,32 @@ int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg) 
     if (!ctx || !in || !out) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
     return DISPATCH(ctx, impl_op<float>(ctx, opcode, (const float *)in, (float *)out, arg),
                     impl_op<double>(ctx, opcode, (const double *)in, (double *)out, arg));
+}
+
+int mireg_kernel_stats_enable(mireg_ctx *ctx, int on) {
+    if (!ctx) return MIREG_E_ARG;
+    ctx->stats.stream = ctx->stream;
+    ctx->stats_on = on != 0;
+    return MIREG_OK;
+}
+
+int mireg_kernel_stats_read(mireg_ctx *ctx, mireg_kernel_stat *out, int max, int *count, int reset) {
+    if (!ctx || (max > 0 && !out)) return MIREG_E_ARG;
+    ctx->stats.harvest();
+    int k = 0;
+    for (int id = 0; id < K_COUNT && k < max; ++id) {
+        const auto &a = ctx->stats.acc[id];
+        if (a.n == 0) continue;
+        std::memset(&out[k], 0, sizeof out[k]);
+        std::snprintf(out[k].name, sizeof out[k].name, "%s", kKernelNames[id]);
+        out[k].launches = a.n;
+        out[k].total_ms = a.ms;
+        out[k].bytes_per_launch = a.bytes / a.n;
+        ++k;
+    }
+    if (count) *count = k;
+    if (reset) ctx->stats.reset();
+    return MIREG_OK;
 }
 
 int mireg_timers_enable(mireg_ctx *ctx, int on) {

@@ -250,6 +250,7 @@ static inline unsigned blocks_for(long long n) { return (unsigned)((n + kPtThrea
 template <typename T>
 void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *disp, hipStream_t s) {
     const PGrid g = pgrid(gg);
+    HookScope hs(K_DEPARTURE, 6.0 * g.N * sizeof(T));
     const double two_pi = 6.283185307179586476925;
     const T sdt = (T)(sign * dt);
     const T ih1 = (T)(g.n1 / two_pi), ih2 = (T)(g.n2 / two_pi), ih3 = (T)(g.n3 / two_pi);
@@ -264,6 +265,7 @@ void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *di
 template <typename T>
 void interp_field(const Grid &gg, int order, const T *f, const T *disp, T *out, hipStream_t s) {
     const PGrid g = pgrid(gg);
+    HookScope hs(K_INTERP, 5.0 * g.N * sizeof(T));
     if (order == 3)
         hipLaunchKernelGGL((k_interp<T, 3>), dim3(blocks_for(g.N)), dim3(kPtThreads), 0, s, g, f, disp, out);
     else
@@ -273,6 +275,7 @@ void interp_field(const Grid &gg, int order, const T *f, const T *disp, T *out, 
 template <typename T>
 void adjoint_init(const Grid &g, double a_nt, const T *mR, const T *m, const T *gradm, T *lam, T *b,
                   hipStream_t s) {
+    HookScope hs(K_ADJ_INIT, 9.0 * g.N * sizeof(T));
     hipLaunchKernelGGL((k_adjoint_init<T>), dim3(blocks_for(g.N)), dim3(kPtThreads), 0, s, g.N, (T)a_nt, mR,
                        m, gradm, lam, b);
 }
@@ -281,6 +284,7 @@ template <typename T>
 void adjoint_step(const Grid &gg, int order, double dt, double aj, const T *lam_in, const T *d,
                   const T *Y, const T *gradm_j, T *lam_out, T *b, hipStream_t s) {
     const PGrid g = pgrid(gg);
+    HookScope hs(K_ADJ_STEP, (lam_out ? 15.0 : 14.0) * g.N * sizeof(T));
     if (order == 3)
         hipLaunchKernelGGL((k_adjoint_step<T, 3>), dim3(blocks_for(g.N)), dim3(kPtThreads), 0, s, g, (T)dt,
                            (T)aj, lam_in, d, Y, gradm_j, lam_out, b);
@@ -291,6 +295,7 @@ void adjoint_step(const Grid &gg, int order, double dt, double aj, const T *lam_
 
 template <typename T>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s) {
+    HookScope hs(K_INC_INIT, 7.0 * g.N * sizeof(T));
     hipLaunchKernelGGL((k_incstate_init<T>), dim3(blocks_for(g.N)), dim3(kPtThreads), 0, s, g.N,
                        (T)(0.5 * dt), gradm0, vt, q);
 }
@@ -299,6 +304,7 @@ template <typename T>
 void incstate_step(const Grid &gg, int order, double coef, const T *q_in, const T *X, const T *gradm_next,
                    const T *vt, T *q_out, double a_nt, T *lt_out, T *b_out, hipStream_t s) {
     const PGrid g = pgrid(gg);
+    HookScope hs(K_INC_STEP, (lt_out ? 14.0 : 11.0) * g.N * sizeof(T));
     if (order == 3)
         hipLaunchKernelGGL((k_incstate_step<T, 3>), dim3(blocks_for(g.N)), dim3(kPtThreads), 0, s, g, (T)coef,
                            q_in, X, gradm_next, vt, q_out, (T)a_nt, lt_out, b_out);

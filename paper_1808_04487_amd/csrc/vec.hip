@@ -207,47 +207,62 @@ static inline unsigned stream_blocks(long long n) {
     return (unsigned)b;
 }
 
+thread_local KernelHook *g_hook = nullptr;
+const char *const kKernelNames[K_COUNT] = {
+    "fft_r2c_x3", "fft_c2c_x2_fwd", "fft_c2c_x2_inv", "fft_x1_scale", "fft_x1_grad", "fft_x1_div",
+    "fft_x1_proj", "fft_x1_tail", "fft_c2r_x3", "sl_departure", "sl_interp", "sl_adjoint_init",
+    "sl_adjoint_step", "sl_incstate_init", "sl_incstate_step", "reduce", "vector"};
+
 template <typename T>
 void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
+    HookScope hs(K_REDUCE, 2.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_dot<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
 void sumsq_diff(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
+    HookScope hs(K_REDUCE, 2.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_sumsq_diff<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
 void pcg_update(long long n, double k, const T *sdir, const T *Hs, T *x, T *r, double *partials,
                 double *result, hipStream_t s) {
+    HookScope hs(K_VECTOR, 6.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, k, sdir, Hs, x, r,
                        partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
 void minmax_nonfinite(const T *a, long long n, double *partials, double *result, hipStream_t s) {
+    HookScope hs(K_REDUCE, 1.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_minmax<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, n, partials);
     hipLaunchKernelGGL(k_finish_minmax, dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
 void max_norm2(const T *v, long long N, double *partials, double *result, hipStream_t s) {
+    HookScope hs(K_REDUCE, 3.0 * N * sizeof(T));
     hipLaunchKernelGGL((k_max_norm2<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, v, N, partials);
     hipLaunchKernelGGL(k_finish_max, dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
 void axpby(long long n, double a, const T *x, double b, T *y, hipStream_t s) {
+    HookScope hs(K_VECTOR, 3.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_axpby<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, a, x, b, y);
 }
 template <typename T>
 void xpay(long long n, const T *x, double a, const T *y, T *z, hipStream_t s) {
+    HookScope hs(K_VECTOR, 3.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_xpay<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, x, a, y, z);
 }
 template <typename T>
 void affine(long long n, const T *x, double a, double b, T *y, hipStream_t s) {
+    HookScope hs(K_VECTOR, 2.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_affine<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, x, a, b, y);
 }
 template <typename T>
 void fill(long long n, T val, T *y, hipStream_t s) {
+    HookScope hs(K_VECTOR, 1.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_fill<T>), dim3(stream_blocks(n)), dim3(256), 0, s, n, val, y);
 }
 

@@ -69,6 +69,11 @@ class Timers(ctypes.Structure):
                 ("other_ms", ctypes.c_double), ("launches", ctypes.c_long)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_long), ("total_ms", ctypes.c_double),
+                ("bytes_per_launch", ctypes.c_double)]
+
+
 # exported symbols and their signatures (argtypes, restype)
 _vp, _ip, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
@@ -89,6 +94,8 @@ SIGNATURES = {
     "mireg_gn_solve": ([_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)], ctypes.c_int),
     "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
     "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mireg_kernel_stats_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
     "mireg_timers_read": ([_vp, ctypes.POINTER(Timers), ctypes.c_int], ctypes.c_int),
 }
 
@@ -250,6 +257,16 @@ class Context:
         out = self.empty(cout) if out is None else out
         self._check(self.lib.mireg_op(self.h, OPS[name], ptr, self._arg(out, cout, "out"), float(arg)))
         return out
+
+    def kernel_stats(self, enable=None, reset=False):
+        """Per-kernel event timing: {name: (launches, total_ms, bytes_per_launch)}."""
+        if enable is not None:
+            self._check(self.lib.mireg_kernel_stats_enable(self.h, int(bool(enable))))
+        buf = (KernelStat * 64)()
+        cnt = ctypes.c_int()
+        self._check(self.lib.mireg_kernel_stats_read(self.h, buf, 64, ctypes.byref(cnt), int(bool(reset))))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].bytes_per_launch)
+                for i in range(cnt.value)}
 
     def timers(self, enable=None, reset=False):
         if enable is not None:
