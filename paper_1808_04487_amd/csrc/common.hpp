@@ -48,6 +48,8 @@ struct Grid {
     int k3;          // n3/2 + 1, length of the half-spectrum rows
     long long N;     // n1 n2 n3
     long long NS;    // n1 n2 k3 (complex entries of one half spectrum)
+    int lds_cap;     // largest stencil box (points) staged in LDS; 0: gather from global memory
+    int sl_tile;     // tile shape of the semi-Lagrangian kernels (0, 1, 2)
 };
 
 }  // namespace mireg

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -765,6 +766,17 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     ctx->g.k3 = p->n[2] / 2 + 1;
     ctx->g.N = (long long)p->n[0] * p->n[1] * p->n[2];
     ctx->g.NS = (long long)p->n[0] * p->n[1] * ctx->g.k3;
+    // MIREG_LDS_STENCIL=0 makes every semi-Lagrangian step gather from global
+    // memory (the path taken by tiles whose stencil box exceeds LDS).
+    {
+        const char *e = getenv("MIREG_LDS_STENCIL");
+        ctx->g.lds_cap = (e && atoi(e) == 0) ? 0 : 1 << 30;
+        // MIREG_SL_TILE selects the tile shape of the transport kernels:
+        // 0: 4x8x32, 1: 8x8x16, 2: 8x16x16 (x1 x x2 x x3).
+        const char *t = getenv("MIREG_SL_TILE");
+        ctx->g.sl_tile = t ? atoi(t) : 1;
+        if (ctx->g.sl_tile < 0 || ctx->g.sl_tile > 2) ctx->g.sl_tile = 1;
+    }
     ctx->elem = p->dtype == MIREG_F64 ? 8 : 4;
     const size_t F = (size_t)ctx->g.N * ctx->elem;
     const int nt = p->nt;

@@ -43,16 +43,21 @@ def test_spectral_operators(n, dtype):
     ctx2.close()
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 64)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 64), (64, 64, 64)])
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("order", [3, 1])
-def test_departure_interp_transport(n, dtype, order):
+@pytest.mark.parametrize("staging", ["lds", "global"])
+def test_departure_interp_transport(n, dtype, order, staging, monkeypatch):
+    """Both gather paths: stencil boxes staged in LDS, and direct global
+    gathers (taken by tiles whose box exceeds LDS; forced here)."""
     need_gpu()
     g = core.Grid(n)
+    if staging == "global":
+        monkeypatch.setenv("MIREG_LDS_STENCIL", "0")
     ctx = mireg.Context(n, order=order, dtype=dtype)
     # displacements of several cells, both signs
-    v_t, v = as_input(smooth_vector(g, 5, amp=1.5, sigma=1.5), dtype)
-    print("transport", n, dtype, order, flush=True)
+    v_t, v = as_input(smooth_vector(g, 5, amp=1.5, sigma=max(1.5, n[0] / 16)), dtype)
+    print("transport", n, dtype, order, staging, flush=True)
     X = ctx.op("departure_X", v_t)
     Y = ctx.op("departure_Y", v_t)
     Xo = core.departure_points(g, v, 4, order, -1)
@@ -117,3 +122,25 @@ def test_errors_are_reported():
     assert e.value.code == mireg.E_NONFINITE
     with pytest.raises(ValueError):
         ctx.set_velocity(torch.zeros((3, 8, 8, 8), dtype=torch.float32, device="cuda"))
+
+
+def test_tile_shapes_agree_bitwise(monkeypatch):
+    """The three tile shapes of the transport kernels run the same arithmetic
+    per point: the state transport and the matvec are bitwise identical."""
+    need_gpu()
+    n = (32, 64, 64)
+    g = core.Grid(n)
+    v_t, _ = as_input(smooth_vector(g, 21, amp=1.0, sigma=3.0), torch.float32)
+    f_t, _ = as_input(smooth_scalar(g, 22), torch.float32)
+    vt_t, _ = as_input(smooth_vector(g, 23), torch.float32)
+    outs = []
+    for shape in ("0", "1", "2"):
+        monkeypatch.setenv("MIREG_SL_TILE", shape)
+        ctx = mireg.Context(n, dtype=torch.float32, div=mireg.DIV_LERAY)
+        ctx.set_images(f_t, f_t.flip(0).contiguous())
+        ctx.set_velocity(v_t)
+        outs.append((ctx.op("transport_state", f_t), ctx.hessian_matvec(vt_t)))
+        ctx.close()
+    for m, h in outs[1:]:
+        assert torch.equal(m, outs[0][0])
+        assert torch.equal(h, outs[0][1])
