@@ -21,11 +21,14 @@ namespace mireg {
 // ---------------------------------------------------------------------------
 // x3 real-to-complex and complex-to-real passes (lines contiguous in memory)
 // ---------------------------------------------------------------------------
+constexpr int kLineThreads = 256;  // x3 passes
+constexpr int kColThreads = 512;   // strided passes: wide column tiles
+
 template <typename T, int M>
-__global__ __launch_bounds__(kFftThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
-                                                        long long lines,
-                                                        const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, M>;
+__global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
+                                                         long long lines,
+                                                         const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, M, 0, kLineThreads>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
     __shared__ cx<T> lds[Lay::size(M)];
@@ -37,7 +40,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs
     cx<T> reg[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) reg[e] = ok ? in[t + TPC * e] : make_cx<T>(0, 0);
-    fft_line<T, M, -1, Lay>(reg, t, c, tw, 2, lds);
+    fft_line<T, M, 0, -1, Lay>(reg, t, c, tw, 2, lds);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) lds[Lay::at(c, t + TPC * e)] = reg[e];
     __syncthreads();
@@ -60,10 +63,10 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(kFftThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs dst,
-                                                        long long lines,
-                                                        const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, M>;
+__global__ __launch_bounds__(kLineThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs dst,
+                                                         long long lines,
+                                                         const cx<T> *__restrict__ tw) {
+    using S = FftShape<T, M, 0, kLineThreads>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
     __shared__ cx<T> lds[Lay::size(M)];
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs
             reg[e] = make_cx<T>(0, 0);
         }
     }
-    fft_line<T, M, +1, Lay>(reg, t, c, tw, 2, lds);
+    fft_line<T, M, 0, +1, Lay>(reg, t, c, tw, 2, lds);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) out[t + TPC * e] = reg[e];
@@ -101,10 +104,10 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs
 // q % inner, element p of a column at base + p * pstride.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int DIR>
-__global__ __launch_bounds__(kFftThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
+__global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
                                                           long long ostride, long long pstride,
                                                           const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, L>;
+    using S = FftShape<T, L, 0, kColThreads>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2c_cols(FieldPtrs f, long long
     cx<T> reg[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) reg[e] = ok ? p[(long long)(t + TPC * e) * pstride] : make_cx<T>(0, 0);
-    fft_line<T, L, DIR, Lay>(reg, t, c, tw, 1, lds);
+    fft_line<T, L, 0, DIR, Lay>(reg, t, c, tw, 1, lds);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) p[(long long)(t + TPC * e) * pstride] = reg[e];
@@ -183,10 +186,16 @@ __device__ __forceinline__ void project(const Mode<T> &m, const OpConst<T> &oc, 
     b3 = b3 - scale(s, m.t3);
 }
 
+// The x1 operators keep several lines (or the operator's symbols) in
+// registers: they use the low-register variant of the line transform.
+template <int KIND>
+constexpr int x1_variant() { return 1; }
+
 template <typename T, int L, int KIND>
-__global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q, OpConst<T> oc,
+__global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q, OpConst<T> oc,
                                                        const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, L>;
+    constexpr int V = x1_variant<KIND>();
+    using S = FftShape<T, L, V, kColThreads>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
@@ -226,16 +235,16 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
     if constexpr (KIND == SPEC_SCALE) {
         for (int fi = 0; fi < oc.nf; ++fi) {
             load(fi, reg);
-            fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+            fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], scalar_symbol(mode(e), oc) * oc.norm);
-            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
             store(fi, reg);
         }
     } else if constexpr (KIND == SPEC_GRAD) {
         cx<T> u[EPT];
         load(0, u);
-        fft_line<T, L, -1, Lay>(u, t, c, tw, 1, lds);
+        fft_line<T, L, V, -1, Lay>(u, t, c, tw, 1, lds);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
                 const T ka = a == 0 ? m.t1 : (a == 1 ? m.t2 : m.t3);
                 reg[e] = scale(mul_i(u[e]), ka * oc.norm);
             }
-            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
             store(a, reg);
         }
     } else if constexpr (KIND == SPEC_DIV) {
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             load(a, reg);
-            fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+            fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const Mode<T> m = mode(e);
@@ -262,7 +271,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
                 acc[e] = acc[e] + scale(mul_i(reg[e]), ka * oc.norm);
             }
         }
-        fft_line<T, L, +1, Lay>(acc, t, c, tw, 1, lds);
+        fft_line<T, L, V, +1, Lay>(acc, t, c, tw, 1, lds);
         store(0, acc);
     } else {
         // SPEC_PROJ: K u for u in slots 0..2.
@@ -270,11 +279,11 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
         constexpr int boff = (KIND == SPEC_TAIL) ? 3 : 0;
         cx<T> b0[EPT], b1[EPT], b2[EPT];
         load(boff + 0, b0);
-        fft_line<T, L, -1, Lay>(b0, t, c, tw, 1, lds);
+        fft_line<T, L, V, -1, Lay>(b0, t, c, tw, 1, lds);
         load(boff + 1, b1);
-        fft_line<T, L, -1, Lay>(b1, t, c, tw, 1, lds);
+        fft_line<T, L, V, -1, Lay>(b1, t, c, tw, 1, lds);
         load(boff + 2, b2);
-        fft_line<T, L, -1, Lay>(b2, t, c, tw, 1, lds);
+        fft_line<T, L, V, -1, Lay>(b2, t, c, tw, 1, lds);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) project(mode(e), oc, b0[e], b1[e], b2[e]);
 #pragma unroll
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
             cx<T>(&ba)[EPT] = a == 0 ? b0 : (a == 1 ? b1 : b2);
             if constexpr (KIND == SPEC_TAIL) {
                 load(a, reg);
-                fft_line<T, L, -1, Lay>(reg, t, c, tw, 1, lds);
+                fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
                     const T s = oc.alpha * reg_symbol(mode(e), oc.reg);
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_op(FieldPtrs f, long long Q,
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) reg[e] = scale(ba[e], oc.norm);
             }
-            fft_line<T, L, +1, Lay>(reg, t, c, tw, 1, lds);
+            fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
             store(a, reg);
         }
     }
@@ -319,10 +328,11 @@ static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
                        hipStream_t s) {
     const long long lines = (long long)g.n1 * g.n2;
     HookScope hs(K_R2C, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
-#define MIREG_L(M)                                                                          \
-    {                                                                                       \
-        dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
-        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kFftThreads), 0, s, src, dst, lines, tw); \
+#define MIREG_L(M)                                                                                     \
+    {                                                                                                  \
+        constexpr int W = FftShape<T, M, 0, kLineThreads>::W;                                          \
+        dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
+        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);     \
     }
     MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
 #undef MIREG_L
@@ -333,10 +343,11 @@ static void launch_c2r(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
                        hipStream_t s) {
     const long long lines = (long long)g.n1 * g.n2;
     HookScope hs(K_C2R, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
-#define MIREG_L(M)                                                                          \
-    {                                                                                       \
-        dim3 grid((unsigned)((lines + FftShape<T, M>::W - 1) / FftShape<T, M>::W), nf);     \
-        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(kFftThreads), 0, s, src, dst, lines, tw); \
+#define MIREG_L(M)                                                                                     \
+    {                                                                                                  \
+        constexpr int W = FftShape<T, M, 0, kLineThreads>::W;                                          \
+        dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
+        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);     \
     }
     MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
 #undef MIREG_L
@@ -349,8 +360,9 @@ static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipSt
     HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
 #define MIREG_L(L)                                                                           \
     {                                                                                        \
-        dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W), nf);          \
-        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kFftThreads), 0, s, f, Q, inner, \
+        constexpr int W = FftShape<T, L, 0, kColThreads>::W;                                 \
+        dim3 grid((unsigned)((Q + W - 1) / W), nf);                                          \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kColThreads), 0, s, f, Q, inner, \
                            ostride, pstride, tw);                                            \
     }
     MIREG_SWITCH_POW2(g.n2, MIREG_L)
@@ -364,8 +376,9 @@ static void launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpCon
     HookScope hs(K_X1_SCALE + KIND, (double)(nin + nout) * sizeof(T) * 2.0 * g.NS);
 #define MIREG_L(L)                                                                              \
     {                                                                                           \
-        dim3 grid((unsigned)((Q + FftShape<T, L>::W - 1) / FftShape<T, L>::W));                 \
-        hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(kFftThreads), 0, s, f, Q, oc, tw); \
+        constexpr int W = FftShape<T, L, x1_variant<KIND>(), kColThreads>::W;                   \
+        dim3 grid((unsigned)((Q + W - 1) / W));                                                 \
+        hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(kColThreads), 0, s, f, Q, oc, tw); \
     }
     MIREG_SWITCH_POW2(g.n1, MIREG_L)
 #undef MIREG_L

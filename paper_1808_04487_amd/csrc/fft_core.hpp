@@ -116,50 +116,55 @@ struct Dft<T, 8, DIR> {
     }
 };
 
-// Elements per thread and radices per line length.  Every radix divides EPT
+// Elements per thread and radices per line length, in two variants: V = 0
+// (16 elements per thread for FP32 at L >= 128) and V = 1 (at most 8, for
+// kernels that keep several lines in registers).  Every radix divides EPT
 // so that a thread's butterflies read only its own registers.
-template <typename T, int L>
+template <typename T, int L, int V>
 struct FftCfg;
-#define MIREG_FFTCFG(TY, LL, E, A, B, C) \
-    template <>                          \
-    struct FftCfg<TY, LL> {              \
-        static constexpr int EPT = E;    \
-        static constexpr int R0 = A;     \
-        static constexpr int R1 = B;     \
-        static constexpr int R2 = C;     \
+#define MIREG_FFTCFG(TY, LL, VV, E, A, B, C) \
+    template <>                              \
+    struct FftCfg<TY, LL, VV> {              \
+        static constexpr int EPT = E;        \
+        static constexpr int R0 = A;         \
+        static constexpr int R1 = B;         \
+        static constexpr int R2 = C;         \
     };
-MIREG_FFTCFG(float, 2, 2, 2, 1, 1)
-MIREG_FFTCFG(float, 4, 4, 4, 1, 1)
-MIREG_FFTCFG(float, 8, 4, 4, 2, 1)
-MIREG_FFTCFG(float, 16, 4, 4, 4, 1)
-MIREG_FFTCFG(float, 32, 8, 8, 4, 1)
-MIREG_FFTCFG(float, 64, 8, 8, 8, 1)
-MIREG_FFTCFG(float, 128, 16, 16, 8, 1)
-MIREG_FFTCFG(float, 256, 16, 16, 16, 1)
-MIREG_FFTCFG(float, 512, 16, 16, 8, 4)
-MIREG_FFTCFG(double, 2, 2, 2, 1, 1)
-MIREG_FFTCFG(double, 4, 4, 4, 1, 1)
-MIREG_FFTCFG(double, 8, 4, 4, 2, 1)
-MIREG_FFTCFG(double, 16, 4, 4, 4, 1)
-MIREG_FFTCFG(double, 32, 8, 8, 4, 1)
-MIREG_FFTCFG(double, 64, 8, 8, 8, 1)
-MIREG_FFTCFG(double, 128, 8, 8, 4, 4)
-MIREG_FFTCFG(double, 256, 8, 8, 8, 4)
-MIREG_FFTCFG(double, 512, 8, 8, 8, 8)
+#define MIREG_FFTCFG2(TY, LL, E, A, B, C) MIREG_FFTCFG(TY, LL, 0, E, A, B, C) MIREG_FFTCFG(TY, LL, 1, E, A, B, C)
+MIREG_FFTCFG2(float, 2, 2, 2, 1, 1)
+MIREG_FFTCFG2(float, 4, 4, 4, 1, 1)
+MIREG_FFTCFG2(float, 8, 4, 4, 2, 1)
+MIREG_FFTCFG2(float, 16, 4, 4, 4, 1)
+MIREG_FFTCFG2(float, 32, 8, 8, 4, 1)
+MIREG_FFTCFG2(float, 64, 8, 8, 8, 1)
+MIREG_FFTCFG(float, 128, 0, 16, 16, 8, 1)
+MIREG_FFTCFG(float, 128, 1, 8, 8, 4, 4)
+MIREG_FFTCFG(float, 256, 0, 16, 16, 16, 1)
+MIREG_FFTCFG(float, 256, 1, 8, 8, 8, 4)
+MIREG_FFTCFG(float, 512, 0, 16, 16, 8, 4)
+MIREG_FFTCFG(float, 512, 1, 8, 8, 8, 8)
+MIREG_FFTCFG2(double, 2, 2, 2, 1, 1)
+MIREG_FFTCFG2(double, 4, 4, 4, 1, 1)
+MIREG_FFTCFG2(double, 8, 4, 4, 2, 1)
+MIREG_FFTCFG2(double, 16, 4, 4, 4, 1)
+MIREG_FFTCFG2(double, 32, 8, 8, 4, 1)
+MIREG_FFTCFG2(double, 64, 8, 8, 8, 1)
+MIREG_FFTCFG2(double, 128, 8, 8, 4, 4)
+MIREG_FFTCFG2(double, 256, 8, 8, 8, 4)
+MIREG_FFTCFG2(double, 512, 8, 8, 8, 8)
+#undef MIREG_FFTCFG2
 #undef MIREG_FFTCFG
 
 // Register array of one thread's share of a line.
-template <typename T, int L>
-using Regs = cx<T>[FftCfg<T, L>::EPT];
+template <typename T, int L, int V>
+using Regs = cx<T>[FftCfg<T, L, V>::EPT];
 
-// Threads per workgroup of every FFT pass.
-constexpr int kFftThreads = 256;
-
-template <typename T, int L>
+// Workgroup shape of a pass: NT threads, TPC per line, W lines.
+template <typename T, int L, int V, int NT>
 struct FftShape {
-    static constexpr int EPT = FftCfg<T, L>::EPT;
-    static constexpr int TPC = L / EPT;          // threads per line
-    static constexpr int W = kFftThreads / TPC;  // lines per workgroup
+    static constexpr int EPT = FftCfg<T, L, V>::EPT;
+    static constexpr int TPC = L / EPT;  // threads per line
+    static constexpr int W = NT / TPC;   // lines per workgroup
 };
 
 // LDS index of (line c, position p): strided passes keep lines (columns)
@@ -178,11 +183,11 @@ struct LayoutRows {
 
 // One Stockham stage of radix R after sub-transforms of length NS.
 // tw: table exp(-2 pi i j / Ltab), read at stride Ltab / L.
-template <typename T, int L, int R, int NS, int DIR, bool LAST, class Lay>
-__device__ __forceinline__ void stockham_stage(Regs<T, L> &reg, int t, int c,
+template <typename T, int L, int V, int R, int NS, int DIR, bool LAST, class Lay>
+__device__ __forceinline__ void stockham_stage(Regs<T, L, V> &reg, int t, int c,
                                                const cx<T> *__restrict__ tw, int twstride,
                                                cx<T> *lds) {
-    constexpr int EPT = FftCfg<T, L>::EPT;
+    constexpr int EPT = FftCfg<T, L, V>::EPT;
     constexpr int TPC = L / EPT;
     constexpr int NB = EPT / R;
     cx<T> out[EPT];
@@ -225,17 +230,17 @@ __device__ __forceinline__ void stockham_stage(Regs<T, L> &reg, int t, int c,
 }
 
 // Full unnormalised transform of one line: X[k] = sum_n x[n] exp(DIR 2 pi i n k / L).
-template <typename T, int L, int DIR, class Lay>
-__device__ __forceinline__ void fft_line(Regs<T, L> &reg, int t, int c,
+template <typename T, int L, int V, int DIR, class Lay>
+__device__ __forceinline__ void fft_line(Regs<T, L, V> &reg, int t, int c,
                                          const cx<T> *__restrict__ tw, int twstride, cx<T> *lds) {
-    using C = FftCfg<T, L>;
+    using C = FftCfg<T, L, V>;
     constexpr bool one = (C::R1 == 1);
     constexpr bool two = (C::R1 > 1 && C::R2 == 1);
-    stockham_stage<T, L, C::R0, 1, DIR, one, Lay>(reg, t, c, tw, twstride, lds);
+    stockham_stage<T, L, V, C::R0, 1, DIR, one, Lay>(reg, t, c, tw, twstride, lds);
     if constexpr (C::R1 > 1)
-        stockham_stage<T, L, C::R1, C::R0, DIR, two, Lay>(reg, t, c, tw, twstride, lds);
+        stockham_stage<T, L, V, C::R1, C::R0, DIR, two, Lay>(reg, t, c, tw, twstride, lds);
     if constexpr (C::R2 > 1)
-        stockham_stage<T, L, C::R2, C::R0 * C::R1, DIR, true, Lay>(reg, t, c, tw, twstride, lds);
+        stockham_stage<T, L, V, C::R2, C::R0 * C::R1, DIR, true, Lay>(reg, t, c, tw, twstride, lds);
 }
 
 }  // namespace mireg

@@ -147,7 +147,9 @@ __device__ __forceinline__ void contract(const AxisW<T, ORDER> &a1, const AxisW<
 }
 
 // Same contraction over an unwrapped box: node (p, q, r) at
-// base + p s1 + q s2 + r, so the r taps of a row use immediate offsets.
+// base + p s1 + q s2 + r, so the r taps of a row use immediate offsets.  All
+// taps of a plane p are read before any arithmetic, so a wave keeps 16
+// (NF = 1) or 32 (NF = 2) LDS words in flight instead of waiting row by row.
 template <typename T, int ORDER, int NF, class Get>
 __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const AxisW<T, ORDER> &a2,
                                              const AxisW<T, ORDER> &a3, int base, int s1, int s2,
@@ -157,24 +159,28 @@ __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const Ax
     for (int f = 0; f < NF; ++f) acc[f] = 0;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
+        T v[NP][NP][NF];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int row = base + p * s1 + q * s2;
+#pragma unroll
+            for (int r = 0; r < NP; ++r) get(row, r, v[q][r]);
+        }
         T ap[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) ap[f] = 0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int row = base + p * s1 + q * s2;
-            T s[NF];
+            T sr[NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) s[f] = 0;
+            for (int f = 0; f < NF; ++f) sr[f] = 0;
 #pragma unroll
             for (int r = 0; r < NP; ++r) {
-                T v[NF];
-                get(row, r, v);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) s[f] += a3.w[r] * v[f];
+                for (int f = 0; f < NF; ++f) sr[f] += a3.w[r] * v[q][r][f];
             }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) ap[f] += a2.w[q] * s[f];
+            for (int f = 0; f < NF; ++f) ap[f] += a2.w[q] * sr[f];
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] += a1.w[p] * ap[f];

@@ -1,0 +1,169 @@
+"""Parity at the benchmark's full size and in its launch configuration
+(256^3 FP32, the same kernels and tile shapes bench.py times), at the
+maximum grid (512^3) through exact properties, and edge cases: the largest
+line lengths on every FFT axis, the smallest grid, other time-step counts,
+and the degenerate constant template."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import core, prep
+from paper_1808_04487_amd import mireg, synth
+
+from gpu_util import (as_input, assert_close, assert_close_composite, fp32_reg_tol, need_gpu,
+                      rel_err_l2, smooth_scalar, smooth_vector)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def workload256():
+    """The benchmark recipe at 256^3, prepared by the oracle in FP64."""
+    n = (256, 256, 256)
+    g = core.Grid(n)
+    mT = prep.smooth_rescale(g, synth.voronoi_phantom(n, nseeds=120, seed=1), 2.0)
+    v = prep.smooth_velocity(g, synth.white_noise(n, seed=2), math.pi / 4, 0.15 * 2 * math.pi)
+    probe = prep.smooth_velocity(g, synth.white_noise(n, seed=3), math.pi / 4, 0.15 * 2 * math.pi)
+    return g, mT, v, probe
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_transport_gradient_matvec(workload256):
+    """256^3 FP32 at the workload's velocity (up to ~9 cells per step):
+    departure points, state m(1), reduced gradient and GN Hessian matvec,
+    element by element against the FP64 oracle."""
+    need_gpu()
+    g, mT0, v0, probe0 = workload256
+    dt = torch.float32
+    mT_t, mT = as_input(mT0, dt)
+    v_t, v = as_input(v0, dt)
+    p_t, p = as_input(probe0, dt)
+    print("fullsize 256^3: oracle reference", flush=True)
+    mR = prep.transport(g, mT, v)                      # reference image, oracle
+    mR_t, mR = as_input(mR, dt)
+    ctx = mireg.Context(g.n, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0, dtype=dt)
+    ctx.set_images(mT_t, mR_t)
+    ctx.set_velocity(v_t)
+    # departure points (cell units) and the transported template
+    Xo = core.departure_points(g, v, 4, 3, -1)
+    assert_close(ctx.op("departure_X", v_t), Xo, dt, what="X 256^3")
+    m1o = core.solve_state(g, mT, Xo, 4, 3)[-1]
+    assert_close(ctx.op("transport_state", mT_t), m1o, dt, factor=4, what="m(1) 256^3")
+    # reduced gradient and matvec at a velocity other than the generating one
+    vw = 0.7 * v
+    vw_t, vw = as_input(vw, dt)
+    ctx.set_velocity(vw_t)
+    p_ = core.Params(g.n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
+    R = core.Registration(p_, mT, mR)
+    R.set_velocity(vw)
+    gr, _ = ctx.gradient()
+    go = R.gradient()
+    assert_close_composite(gr, go, dt, what="gradient 256^3", tol32=fp32_reg_tol(g, 1, 5e-3, vw, go))
+    Hv = ctx.hessian_matvec(p_t)
+    Ho = R.hessian_matvec(p)
+    e = assert_close_composite(Hv, Ho, dt, what="matvec 256^3", tol32=fp32_reg_tol(g, 1, 5e-3, p, Ho))
+    print("256^3 matvec rel err %.2e (L2 %.2e)" % (e, rel_err_l2(Hv, Ho)), flush=True)
+    ctx.close()
+
+
+def test_max_grid_properties():
+    """512^3 FP32 (the largest supported grid): integer-shift transport is an
+    exact roll, the Leray projection is divergence-free, and the spectral
+    gradient of a single Fourier mode is exact."""
+    need_gpu()
+    n = (512, 512, 512)
+    dt = torch.float32
+    ctx = mireg.Context(n, dtype=dt)
+    h = 2 * math.pi / 512
+    s = (2, -1, 3)
+    v = torch.empty((3,) + n, dtype=dt, device="cuda")
+    for a in range(3):
+        v[a].fill_(s[a] * h * 4)
+    f = torch.randn(n, dtype=dt, device="cuda")
+    ctx.set_velocity(v)
+    m1 = ctx.op("transport_state", f)
+    # displacements are integers up to FP32 rounding of v h^-1: |t| ~ 1e-7
+    assert torch.allclose(m1, torch.roll(f, shifts=(8, -4, 12), dims=(0, 1, 2)), atol=1e-5, rtol=0)
+    w = torch.randn((3,) + n, dtype=dt, device="cuda")
+    P = ctx.op("leray", w)
+    d = ctx.op("div", P)
+    assert d.abs().max().item() < 1e-4 * ctx.op("div", w).abs().max().item()
+    x = torch.arange(512, dtype=torch.float64, device="cuda") * h
+    u = torch.sin(3 * x).view(-1, 1, 1) * torch.cos(200 * x).view(1, 1, -1) + 0 * x.view(1, -1, 1)
+    gu = ctx.op("grad", u.to(dt).contiguous())
+    ex0 = 3 * torch.cos(3 * x).view(-1, 1, 1) * torch.cos(200 * x).view(1, 1, -1)
+    assert (gu[0].double() - ex0).abs().max().item() < 2e-4 * 3
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [(512, 8, 16), (8, 512, 8), (16, 8, 512)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_longest_lines_every_axis(n, dtype):
+    """L = 512 on each FFT pass (x1 operator pass, x2 columns, x3 R2C/C2R)."""
+    need_gpu()
+    g = core.Grid(n)
+    ctx = mireg.Context(n, reg=mireg.H2, div=mireg.DIV_LERAY, beta_v=1e-2, dtype=dtype)
+    rng = np.random.default_rng(31)
+    u_t, u = as_input(rng.standard_normal(n), dtype)
+    v_t, v = as_input(rng.standard_normal((3,) + n), dtype)
+    assert_close(ctx.op("grad", u_t), core.grad(g, u), dtype, what="grad")
+    assert_close(ctx.op("leray", v_t), core.apply_K(g, v, core.DIV_LERAY), dtype, what="leray")
+    assert_close(ctx.op("gauss", u_t, 2.5), core.gauss_smooth(g, u, 2.5), dtype, what="gauss")
+    # precond symbol spans ~|k|^-4: compare in the L2 sense for FP32
+    z = ctx.op("precond", v_t)
+    zo = core.apply_Hreg_inverse(g, v, core.REG_H2, 1e-2)
+    assert rel_err_l2(z, zo) < (1e-12 if dtype == torch.float64 else 1e-5)
+    ctx.close()
+
+
+@pytest.mark.parametrize("nt", [1, 8])
+@pytest.mark.parametrize("n", [(8, 8, 8), (16, 8, 32)])
+def test_time_steps_and_smallest_grid(nt, n):
+    """Other time-step counts and the smallest grid, FP64 against the oracle."""
+    need_gpu()
+    g = core.Grid(n)
+    dt = torch.float64
+    mT = synth.trig_template(n)
+    vs = synth.trig_velocity(n)
+    mR = prep.transport(g, mT, vs, nt=nt)
+    p = core.Params(n, nt=nt, order=3, reg=core.REG_H1, div_mode=core.DIV_NONE, beta_v=1e-2)
+    R = core.Registration(p, mT, mR)
+    v = 0.8 * vs + smooth_vector(g, 41, amp=0.1, sigma=1.0)
+    R.set_velocity(v)
+    ctx = mireg.Context(n, nt=nt, reg=mireg.H1, div=mireg.DIV_NONE, beta_v=1e-2, dtype=dt)
+    ctx.set_images(torch.from_numpy(mT).cuda(), torch.from_numpy(mR).cuda())
+    ctx.set_velocity(torch.from_numpy(v).cuda())
+    gr, _ = ctx.gradient()
+    assert_close(gr, R.gradient(), dt, factor=5, what="gradient nt=%d" % nt)
+    vt = smooth_vector(g, 42)
+    assert_close(ctx.hessian_matvec(torch.from_numpy(vt).cuda()), R.hessian_matvec(vt), dt, factor=5,
+                 what="matvec nt=%d" % nt)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_constant_template_degenerate(dtype):
+    """A constant template has no gradient: the data terms vanish, so
+    g = beta_v A v and H vt = beta_v A vt, and PCG with the spectral
+    preconditioner converges in one iteration on zero-mean data."""
+    need_gpu()
+    n = (32, 16, 32)
+    g = core.Grid(n)
+    ctx = mireg.Context(n, reg=mireg.H2, div=mireg.DIV_NONE, beta_v=1e-2, dtype=dtype)
+    mT_t, _ = as_input(np.full(n, 0.25), dtype)
+    mR_t, _ = as_input(synth.trig_template(n), dtype)
+    ctx.set_images(mT_t, mR_t)
+    v_t, v = as_input(smooth_vector(g, 51, amp=0.5), dtype)
+    ctx.set_velocity(v_t)
+    gr, _ = ctx.gradient()
+    assert_close(gr, 1e-2 * core.apply_A(g, v, core.REG_H2), dtype, factor=5, what="g = beta A v")
+    rhs = smooth_vector(g, 52)
+    rhs -= rhs.mean(axis=(1, 2, 3), keepdims=True)
+    rhs_t, rhs = as_input(rhs, dtype)
+    # one PCG iteration solves H x = rhs; in FP32 the residual floor is the
+    # FFT roundoff of H M^-1 r, amplified by beta_v |k|^4 at the top modes
+    x, it, rel = ctx.pcg(rhs_t, rtol=0.0, maxit=1)
+    assert it == 1
+    assert rel < (1e-10 if dtype == torch.float64 else 1e-3)
