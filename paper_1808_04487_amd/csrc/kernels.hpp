@@ -8,7 +8,7 @@ namespace mireg {
 // Kernel kinds for the per-launch statistics.
 enum KernelId {
     K_R2C = 0, K_C2C_FWD, K_C2C_INV, K_X1_SCALE, K_X1_GRAD, K_X1_DIV, K_X1_PROJ, K_X1_TAIL, K_C2R,
-    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
+    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR, K_ACCUM,
     K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
@@ -80,24 +80,28 @@ void departure(const Grid &g, int order, int sign, double dt, const T *v, T *dis
 // out = I[f](x + disp)
 template <typename T>
 void interp_field(const Grid &g, int order, const T *f, const T *disp, T *out, hipStream_t s);
-// Adjoint first slice: lam = mR - m, b = a_nt lam grad m
+// Adjoint final condition: lam = mR - m(1)
 template <typename T>
-void adjoint_init(const Grid &g, double a_nt, const T *mR, const T *m, const T *gradm, T *lam,
-                  T *b, hipStream_t s);
-// One adjoint step with fused time quadrature: lam_out = step(lam_in), b += a_j lam_out grad m^j
-// (lam_out may be null when not needed).
+void adjoint_init(const Grid &g, const T *mR, const T *m, T *lam, hipStream_t s);
+// One adjoint step: lam_out = L + dt/2 (S + (L + dt S) d), L = I[lam_in](Y), S = I[lam_in d](Y)
 template <typename T>
-void adjoint_step(const Grid &g, int order, double dt, double aj, const T *lam_in, const T *d,
-                  const T *Y, const T *gradm_j, T *lam_out, T *b, hipStream_t s);
+void adjoint_step(const Grid &g, int order, double dt, const T *lam_in, const T *d, const T *Y,
+                  T *lam_out, hipStream_t s);
+// Last adjoint step fused with the time integral: lam^0 from lam^1 (in the
+// history), then b = sum_j a_j lam^j grad m^j (lam^0 is not stored)
+template <typename T>
+void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const T *lam, const T *d,
+                             const T *Y, const T *gradm, T *b, hipStream_t s);
+// b = sum_j a_j lam^j grad m^j over the histories lam [nt+1][N], gradm [nt+1][3][N]
+template <typename T>
+void accumulate(const Grid &g, int nt, const T *lam, const T *gradm, T *b, hipStream_t s);
 // Incremental state: q0 = -dt/2 grad m^0 . vt
 template <typename T>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s);
-// q_out = I[q_in](X) + coef f^{j+1}, f = -grad m^{j+1} . vt; on the last step
-// (lam_out, b non-null) write lt = -(I[q](X) + dt/2 f^nt) and b = a_nt lt grad m^nt.
+// q_out = sign (I[q_in](X) + coef f^{j+1}), f = -grad m^{j+1} . vt
 template <typename T>
-void incstate_step(const Grid &g, int order, double coef, const T *q_in, const T *X,
-                   const T *gradm_next, const T *vt, T *q_out, double a_nt, T *lt_out, T *b_out,
-                   hipStream_t s);
+void incstate_step(const Grid &g, int order, double coef, double sign, const T *q_in, const T *X,
+                   const T *gradm_next, const T *vt, T *q_out, hipStream_t s);
 
 // ---- vector kernels and FP64 reductions (vec.hip) ----
 // result[k] (device doubles) for k < nres; see the individual descriptions.

@@ -113,7 +113,8 @@ struct mireg_ctx {
     void *m = nullptr;      // (nt+1) N  state history
     void *gradm = nullptr;  // (nt+1) 3N
     void *d = nullptr;      // N, div v
-    void *lam = nullptr;    // 2N, ping-pong for adjoint steps and incremental state
+    void *lam = nullptr;    // (nt+1) N, adjoint / incremental adjoint history
+    void *q = nullptr;      // 2N, ping-pong of the incremental state
     void *b = nullptr;      // 3N, time integral of the gradient / matvec
     void *vecs = nullptr;   // kVecs x 3N work vectors
     void *spec = nullptr;   // 6 half spectra
@@ -313,25 +314,21 @@ void ensure_d(mireg_ctx *ctx) {
     ctx->have_d = true;
 }
 
-double time_weight(int j, int nt) { return (j == 0 || j == nt) ? 0.5 / nt : 1.0 / nt; }
 
 // Backward sweep shared by the adjoint and the incremental adjoint: from
-// lam^nt in lam buffer `cur`, accumulate b += a_j lam^j grad m^j, j < nt.
+// lam^nt in the history buffer, lam^j for j = nt-1..1, then the last step
+// fused with the time integral b = sum_j a_j lam^j grad m^j.
 template <typename T>
-void backward_sweep(mireg_ctx *ctx, T *l0, T *l1, T *b) {
+void backward_sweep(mireg_ctx *ctx, T *lam, T *b) {
     const int nt = ctx->p.nt;
     const long long N = ctx->N();
     const double dt = 1.0 / nt;
-    T *cur = l0, *nxt = l1;
     Phase ph(ctx, 1);
-    for (int j = nt - 1; j >= 0; --j) {
-        adjoint_step<T>(ctx->g, ctx->p.interp_order, dt, time_weight(j, nt), cur, ctx->f<T>(ctx->d),
-                        ctx->f<T>(ctx->Y), ctx->f<T>(ctx->gradm) + 3 * j * N, j > 0 ? nxt : nullptr, b,
-                        ctx->stream);
-        T *t = cur;
-        cur = nxt;
-        nxt = t;
-    }
+    for (int j = nt - 1; j >= 1; --j)
+        adjoint_step<T>(ctx->g, ctx->p.interp_order, dt, lam + (j + 1) * N, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
+                        lam + j * N, ctx->stream);
+    adjoint_step_accumulate<T>(ctx->g, ctx->p.interp_order, dt, nt, lam, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
+                               ctx->f<T>(ctx->gradm), b, ctx->stream);
 }
 
 template <typename T>
@@ -386,13 +383,12 @@ int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
     ensure_Y<T>(ctx);
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
-    T *l0 = ctx->f<T>(ctx->lam), *l1 = l0 + N, *b = ctx->f<T>(ctx->b);
+    T *lam = ctx->f<T>(ctx->lam), *b = ctx->f<T>(ctx->b);
     {
         Phase ph(ctx, 2);
-        adjoint_init<T>(ctx->g, time_weight(nt, nt), ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N,
-                        ctx->f<T>(ctx->gradm) + 3 * nt * N, l0, b, ctx->stream);
+        adjoint_init<T>(ctx->g, ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N, lam + nt * N, ctx->stream);
     }
-    backward_sweep<T>(ctx, l0, l1, b);
+    backward_sweep<T>(ctx, lam, b);
     op_tail<T>(ctx, ctx->p.beta_v, ctx->f<T>(ctx->v), b, g);
     if (gnorm) {
         double gg = 0;
@@ -414,7 +410,7 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
     const double dt = 1.0 / nt;
-    T *q0 = ctx->f<T>(ctx->lam), *q1 = q0 + N, *b = ctx->f<T>(ctx->b);
+    T *q0 = ctx->f<T>(ctx->q), *q1 = q0 + N, *lam = ctx->f<T>(ctx->lam), *b = ctx->f<T>(ctx->b);
     const T *gm = ctx->f<T>(ctx->gradm);
     {
         Phase ph(ctx, 1);
@@ -422,18 +418,21 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
         incstate_init<T>(ctx->g, dt, gm, vt, q0, ctx->stream);
         T *cur = q0, *nxt = q1;
         for (int j = 0; j < nt; ++j) {
-            const bool last = (j == nt - 1);
-            // q^{j+1} = I[q^j](X) + dt f^{j+1}; last: lt = -(I[q](X) + dt/2 f^nt), b = a_nt lt grad m^nt
-            incstate_step<T>(ctx->g, ctx->p.interp_order, last ? 0.5 * dt : dt, cur, ctx->f<T>(ctx->X),
-                             gm + 3 * (j + 1) * N, vt, nxt, time_weight(nt, nt), last ? nxt : nullptr,
-                             last ? b : nullptr, ctx->stream);
-            T *t = cur;
-            cur = nxt;
-            nxt = t;
+            if (j < nt - 1) {
+                // q^{j+1} = I[q^j](X) + dt f^{j+1}
+                incstate_step<T>(ctx->g, ctx->p.interp_order, dt, 1.0, cur, ctx->f<T>(ctx->X), gm + 3 * (j + 1) * N,
+                                 vt, nxt, ctx->stream);
+                T *t = cur;
+                cur = nxt;
+                nxt = t;
+            } else {
+                // mt(1) = I[q](X) + dt/2 f^nt; the incremental adjoint starts at lt^nt = -mt(1)
+                incstate_step<T>(ctx->g, ctx->p.interp_order, 0.5 * dt, -1.0, cur, ctx->f<T>(ctx->X),
+                                 gm + 3 * nt * N, vt, lam + nt * N, ctx->stream);
+            }
         }
-        // cur now holds lt^nt
-        backward_sweep<T>(ctx, cur, nxt, b);
     }
+    backward_sweep<T>(ctx, lam, b);
     op_tail<T>(ctx, ctx->p.beta_v, vt, b, Hvt);
     return check_launch(ctx);
 }
@@ -645,7 +644,7 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
         }
         case MIREG_OP_TRANSPORT_STATE: {
             ensure_X<T>(ctx);
-            T *a = ctx->f<T>(ctx->lam), *b = a + N;
+            T *a = ctx->f<T>(ctx->q), *b = a + N;
             Phase ph(ctx, 1);
             const T *src = in;
             for (int j = 0; j < ctx->p.nt; ++j) {
@@ -789,7 +788,8 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, &ctx->m, (size_t)(nt + 1) * F);
     if (!rc) rc = alloc(ctx, &ctx->gradm, (size_t)(nt + 1) * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->d, F);
-    if (!rc) rc = alloc(ctx, &ctx->lam, 2 * F);
+    if (!rc) rc = alloc(ctx, &ctx->lam, (size_t)(nt + 1) * F);
+    if (!rc) rc = alloc(ctx, &ctx->q, 2 * F);
     if (!rc) rc = alloc(ctx, &ctx->b, 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->vecs, (size_t)mireg_ctx::kVecs * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);

@@ -16,8 +16,9 @@
 //   3. each point finishes its step (sources, time quadrature) and writes.
 // Tiles are assigned XCD by XCD, so neighbouring tiles -- whose boxes
 // overlap -- are served by the same L2.
-// The time integrals of the gradient and the Hessian matvec are accumulated
-// inside the adjoint steps (Sec. 3.5, memory-reduced Gauss-Newton).
+// The adjoint sweeps store the adjoint history; the time integrals of the
+// gradient and the Hessian matvec are then formed in one streaming pass
+// (Sec. 3.5: only time histories are kept, no full space-time Newton).
 #include <limits.h>
 
 #include "kernels.hpp"
@@ -422,17 +423,15 @@ struct InterpOp {
 };
 
 // Adjoint step: lambda^j = L + dt/2 (S + (L + dt S) d), L = I[lambda^{j+1}](Y),
-// S = I[lambda^{j+1} d](Y); b += a_j lambda^j grad m^j.
+// S = I[lambda^{j+1} d](Y).
 template <typename T>
 struct AdjointOp {
     const T *__restrict__ lin;
     const T *__restrict__ dv;
     const T *__restrict__ Y;
-    const T *__restrict__ gm;
     T *__restrict__ lout;
-    T *__restrict__ b;
     int N;
-    T dt, aj;
+    T dt;
     __device__ void disp(int i, T *d) const {
         d[0] = Y[i];
         d[1] = Y[N + i];
@@ -444,24 +443,52 @@ struct AdjointOp {
         x[1] = l * dv[i];
     }
     struct Pre {
-        T d, g1, g2, g3, b1, b2, b3;
+        T d;
     };
-    __device__ Pre pre(int i) const {
-        return Pre{dv[i], gm[i], gm[N + i], gm[2 * N + i], b[i], b[N + i], b[2 * N + i]};
-    }
+    __device__ Pre pre(int i) const { return Pre{dv[i]}; }
     __device__ void finish(int i, const Pre &p, const T *a) const {
         const T L = a[0], S = a[1];
-        const T lam = L + (T)0.5 * dt * (S + (L + dt * S) * p.d);
-        if (lout) lout[i] = lam;
-        const T al = aj * lam;
-        b[i] = p.b1 + al * p.g1;
-        b[N + i] = p.b2 + al * p.g2;
-        b[2 * N + i] = p.b3 + al * p.g3;
+        lout[i] = L + (T)0.5 * dt * (S + (L + dt * S) * p.d);
+    }
+};
+
+// Last adjoint step (j = 0) fused with the time integral: lambda^0 as above,
+// then b = sum_j a_j lambda^j grad m^j from lambda^0 (in registers) and the
+// stored lambda^1..nt; the history reads overlap the gather-bound step.
+template <typename T>
+struct AdjointAccumOp {
+    AdjointOp<T> step;
+    const T *__restrict__ lam;  // history [nt+1][N]
+    const T *__restrict__ gm;   // [nt+1][3][N]
+    T *__restrict__ b;
+    int nt;
+    T a_end, a_mid;
+    __device__ void disp(int i, T *d) const { step.disp(i, d); }
+    __device__ void stage(int i, T *x) const { step.stage(i, x); }
+    using Pre = typename AdjointOp<T>::Pre;
+    __device__ Pre pre(int i) const { return step.pre(i); }
+    __device__ void finish(int i, const Pre &p, const T *a) const {
+        const int N = step.N;
+        const T L = a[0], S = a[1];
+        const T l0 = L + (T)0.5 * step.dt * (S + (L + step.dt * S) * p.d);
+        T al = a_end * l0;
+        T b1 = al * gm[i], b2 = al * gm[N + i], b3 = al * gm[2 * N + i];
+        for (int j = 1; j <= nt; ++j) {
+            al = (j == nt ? a_end : a_mid) * lam[j * N + i];
+            const T *g = gm + 3 * j * N;
+            b1 += al * g[i];
+            b2 += al * g[N + i];
+            b3 += al * g[2 * N + i];
+        }
+        b[i] = b1;
+        b[N + i] = b2;
+        b[2 * N + i] = b3;
     }
 };
 
 // Incremental state: q^{j+1} = I[q^j](X) + coef f^{j+1}, f = -grad m^{j+1} . vt;
-// last step: lt = -(I[q](X) + dt/2 f^nt), b = a_nt lt grad m^nt.
+// on the last step (coef = dt/2) the output is -mt(1), the final condition
+// of the incremental adjoint.
 template <typename T>
 struct IncStateOp {
     const T *__restrict__ qin;
@@ -469,10 +496,8 @@ struct IncStateOp {
     const T *__restrict__ gm;
     const T *__restrict__ vt;
     T *__restrict__ qout;
-    T *__restrict__ lt;
-    T *__restrict__ b;
     int N;
-    T coef, a_nt;
+    T coef, sign;
     __device__ void disp(int i, T *d) const {
         d[0] = X[i];
         d[1] = X[N + i];
@@ -480,39 +505,42 @@ struct IncStateOp {
     }
     __device__ void stage(int i, T *x) const { x[0] = qin[i]; }
     struct Pre {
-        T g1, g2, g3, f;
+        T f;
     };
     __device__ Pre pre(int i) const {
-        const T g1 = gm[i], g2 = gm[N + i], g3 = gm[2 * N + i];
-        return Pre{g1, g2, g3, -(g1 * vt[i] + g2 * vt[N + i] + g3 * vt[2 * N + i])};
+        return Pre{-(gm[i] * vt[i] + gm[N + i] * vt[N + i] + gm[2 * N + i] * vt[2 * N + i])};
     }
-    __device__ void finish(int i, const Pre &p, const T *a) const {
-        if (lt == nullptr) {
-            qout[i] = a[0] + coef * p.f;
-        } else {
-            const T l = -(a[0] + coef * p.f);
-            lt[i] = l;
-            const T al = a_nt * l;
-            b[i] = al * p.g1;
-            b[N + i] = al * p.g2;
-            b[2 * N + i] = al * p.g3;
-        }
-    }
+    __device__ void finish(int i, const Pre &p, const T *a) const { qout[i] = sign * (a[0] + coef * p.f); }
 };
 
+// Final condition of the adjoint: lambda(1) = mR - m(1).
 template <typename T>
-__global__ __launch_bounds__(kSlThreads) void k_adjoint_init(long long N, T a_nt, const T *__restrict__ mR,
-                                                             const T *__restrict__ m,
-                                                             const T *__restrict__ gm, T *__restrict__ lam,
-                                                             T *__restrict__ b) {
+__global__ __launch_bounds__(kSlThreads) void k_adjoint_init(long long N, const T *__restrict__ mR,
+                                                             const T *__restrict__ m, T *__restrict__ lam) {
     const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
     if (idx >= N) return;
-    const T l = mR[idx] - m[idx];  // final condition lambda(1) = mR - m(1)
-    lam[idx] = l;
-    const T al = a_nt * l;
-    b[idx] = al * gm[idx];
-    b[N + idx] = al * gm[N + idx];
-    b[2 * N + idx] = al * gm[2 * N + idx];
+    lam[idx] = mR[idx] - m[idx];
+}
+
+// Trapezoidal time integral b = sum_j a_j lambda^j grad m^j, j = 0..nt, in one
+// sweep over the stored histories (memory-reduced Gauss-Newton, Sec. 3.5).
+template <typename T>
+__global__ __launch_bounds__(kSlThreads) void k_accumulate(long long N, int nt, T a_end, T a_mid,
+                                                           const T *__restrict__ lam,
+                                                           const T *__restrict__ gm, T *__restrict__ b) {
+    const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
+    if (idx >= N) return;
+    T b1 = 0, b2 = 0, b3 = 0;
+    for (int j = 0; j <= nt; ++j) {
+        const T al = (j == 0 || j == nt ? a_end : a_mid) * lam[j * N + idx];
+        const T *g = gm + 3 * j * N;
+        b1 += al * g[idx];
+        b2 += al * g[N + idx];
+        b3 += al * g[2 * N + idx];
+    }
+    b[idx] = b1;
+    b[N + idx] = b2;
+    b[2 * N + idx] = b3;
 }
 
 template <typename T>
@@ -563,20 +591,37 @@ void interp_field(const Grid &gg, int order, const T *f, const T *disp, T *out, 
 }
 
 template <typename T>
-void adjoint_init(const Grid &g, double a_nt, const T *mR, const T *m, const T *gradm, T *lam, T *b,
-                  hipStream_t s) {
-    HookScope hs(K_ADJ_INIT, 9.0 * g.N * sizeof(T));
-    hipLaunchKernelGGL((k_adjoint_init<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, (T)a_nt, mR,
-                       m, gradm, lam, b);
+void adjoint_init(const Grid &g, const T *mR, const T *m, T *lam, hipStream_t s) {
+    HookScope hs(K_ADJ_INIT, 3.0 * g.N * sizeof(T));
+    hipLaunchKernelGGL((k_adjoint_init<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, mR, m, lam);
 }
 
 template <typename T>
-void adjoint_step(const Grid &gg, int order, double dt, double aj, const T *lam_in, const T *d,
-                  const T *Y, const T *gradm_j, T *lam_out, T *b, hipStream_t s) {
+void adjoint_step(const Grid &gg, int order, double dt, const T *lam_in, const T *d, const T *Y, T *lam_out,
+                  hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_ADJ_STEP, (lam_out ? 15.0 : 14.0) * g.N * sizeof(T));
-    AdjointOp<T> op{lam_in, d, Y, gradm_j, lam_out, b, (int)g.N, (T)dt, (T)aj};
+    HookScope hs(K_ADJ_STEP, 6.0 * g.N * sizeof(T));
+    AdjointOp<T> op{lam_in, d, Y, lam_out, (int)g.N, (T)dt};
     launch_sl<T, 2>(g, order, op, s);
+}
+
+template <typename T>
+void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const T *lam, const T *d,
+                             const T *Y, const T *gradm, T *b, hipStream_t s) {
+    const PGrid g = pgrid(gg);
+    HookScope hs(K_ADJ_STEP, (6.0 - 1.0 + 4.0 * nt + 3.0 + 3.0) * g.N * sizeof(T));
+    const long long N = g.N;
+    AdjointOp<T> step{lam + N, d, Y, nullptr, (int)N, (T)dt};
+    AdjointAccumOp<T> op{step, lam, gradm, b, nt, (T)(0.5 * dt), (T)dt};
+    launch_sl<T, 2>(g, order, op, s);
+}
+
+template <typename T>
+void accumulate(const Grid &g, int nt, const T *lam, const T *gradm, T *b, hipStream_t s) {
+    HookScope hs(K_ACCUM, (4.0 * (nt + 1) + 3.0) * g.N * sizeof(T));
+    const double dt = 1.0 / nt;
+    hipLaunchKernelGGL((k_accumulate<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, nt, (T)(0.5 * dt),
+                       (T)dt, lam, gradm, b);
 }
 
 template <typename T>
@@ -587,24 +632,26 @@ void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q,
 }
 
 template <typename T>
-void incstate_step(const Grid &gg, int order, double coef, const T *q_in, const T *X, const T *gradm_next,
-                   const T *vt, T *q_out, double a_nt, T *lt_out, T *b_out, hipStream_t s) {
+void incstate_step(const Grid &gg, int order, double coef, double sign, const T *q_in, const T *X,
+                   const T *gradm_next, const T *vt, T *q_out, hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_INC_STEP, (lt_out ? 14.0 : 11.0) * g.N * sizeof(T));
-    IncStateOp<T> op{q_in, X, gradm_next, vt, q_out, lt_out, b_out, (int)g.N, (T)coef, (T)a_nt};
+    HookScope hs(K_INC_STEP, 11.0 * g.N * sizeof(T));
+    IncStateOp<T> op{q_in, X, gradm_next, vt, q_out, (int)g.N, (T)coef, (T)sign};
     launch_sl<T, 1>(g, order, op, s);
 }
 
 #define MIREG_INST(T)                                                                                   \
     template void departure<T>(const Grid &, int, int, double, const T *, T *, hipStream_t);            \
     template void interp_field<T>(const Grid &, int, const T *, const T *, T *, hipStream_t);           \
-    template void adjoint_init<T>(const Grid &, double, const T *, const T *, const T *, T *, T *,      \
+    template void adjoint_init<T>(const Grid &, const T *, const T *, T *, hipStream_t);               \
+    template void adjoint_step<T>(const Grid &, int, double, const T *, const T *, const T *, T *,      \
                                   hipStream_t);                                                         \
-    template void adjoint_step<T>(const Grid &, int, double, double, const T *, const T *, const T *,   \
-                                  const T *, T *, T *, hipStream_t);                                    \
+    template void accumulate<T>(const Grid &, int, const T *, const T *, T *, hipStream_t);           \
+    template void adjoint_step_accumulate<T>(const Grid &, int, double, int, const T *, const T *,     \
+                                             const T *, const T *, T *, hipStream_t);               \
     template void incstate_init<T>(const Grid &, double, const T *, const T *, T *, hipStream_t);      \
-    template void incstate_step<T>(const Grid &, int, double, const T *, const T *, const T *,          \
-                                   const T *, T *, double, T *, T *, hipStream_t);
+    template void incstate_step<T>(const Grid &, int, double, double, const T *, const T *, const T *, \
+                                   const T *, T *, hipStream_t);
 MIREG_INST(float)
 MIREG_INST(double)
 #undef MIREG_INST
