@@ -8,7 +8,7 @@ namespace mireg {
 // Kernel kinds for the per-launch statistics.
 enum KernelId {
     K_R2C = 0, K_C2C_FWD, K_C2C_INV, K_X1_SCALE, K_X1_GRAD, K_X1_DIV, K_X1_PROJ, K_X1_TAIL, K_C2R,
-    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR, K_ACCUM,
+    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
     K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
@@ -92,9 +92,6 @@ void adjoint_step(const Grid &g, int order, double dt, const T *lam_in, const T 
 template <typename T>
 void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const T *lam, const T *d,
                              const T *Y, const T *gradm, T *b, hipStream_t s);
-// b = sum_j a_j lam^j grad m^j over the histories lam [nt+1][N], gradm [nt+1][3][N]
-template <typename T>
-void accumulate(const Grid &g, int nt, const T *lam, const T *gradm, T *b, hipStream_t s);
 // Incremental state: q0 = -dt/2 grad m^0 . vt
 template <typename T>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s);

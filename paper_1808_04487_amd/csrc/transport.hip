@@ -522,27 +522,6 @@ __global__ __launch_bounds__(kSlThreads) void k_adjoint_init(long long N, const 
     lam[idx] = mR[idx] - m[idx];
 }
 
-// Trapezoidal time integral b = sum_j a_j lambda^j grad m^j, j = 0..nt, in one
-// sweep over the stored histories (memory-reduced Gauss-Newton, Sec. 3.5).
-template <typename T>
-__global__ __launch_bounds__(kSlThreads) void k_accumulate(long long N, int nt, T a_end, T a_mid,
-                                                           const T *__restrict__ lam,
-                                                           const T *__restrict__ gm, T *__restrict__ b) {
-    const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
-    if (idx >= N) return;
-    T b1 = 0, b2 = 0, b3 = 0;
-    for (int j = 0; j <= nt; ++j) {
-        const T al = (j == 0 || j == nt ? a_end : a_mid) * lam[j * N + idx];
-        const T *g = gm + 3 * j * N;
-        b1 += al * g[idx];
-        b2 += al * g[N + idx];
-        b3 += al * g[2 * N + idx];
-    }
-    b[idx] = b1;
-    b[N + idx] = b2;
-    b[2 * N + idx] = b3;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kSlThreads) void k_incstate_init(long long N, T hdt, const T *__restrict__ gm,
                                                               const T *__restrict__ vt, T *__restrict__ q) {
@@ -617,14 +596,6 @@ void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const
 }
 
 template <typename T>
-void accumulate(const Grid &g, int nt, const T *lam, const T *gradm, T *b, hipStream_t s) {
-    HookScope hs(K_ACCUM, (4.0 * (nt + 1) + 3.0) * g.N * sizeof(T));
-    const double dt = 1.0 / nt;
-    hipLaunchKernelGGL((k_accumulate<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, nt, (T)(0.5 * dt),
-                       (T)dt, lam, gradm, b);
-}
-
-template <typename T>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s) {
     HookScope hs(K_INC_INIT, 7.0 * g.N * sizeof(T));
     hipLaunchKernelGGL((k_incstate_init<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N,
@@ -646,7 +617,6 @@ void incstate_step(const Grid &gg, int order, double coef, double sign, const T 
     template void adjoint_init<T>(const Grid &, const T *, const T *, T *, hipStream_t);               \
     template void adjoint_step<T>(const Grid &, int, double, const T *, const T *, const T *, T *,      \
                                   hipStream_t);                                                         \
-    template void accumulate<T>(const Grid &, int, const T *, const T *, T *, hipStream_t);           \
     template void adjoint_step_accumulate<T>(const Grid &, int, double, int, const T *, const T *,     \
                                              const T *, const T *, T *, hipStream_t);               \
     template void incstate_init<T>(const Grid &, double, const T *, const T *, T *, hipStream_t);      \
