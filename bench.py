@@ -16,7 +16,9 @@ value = Hessian matvecs per second of the whole job: matvecs performed in
 the K timed solves divided by their wall time.  The matvec-only rate, the
 per-kernel breakdown (HIP events on the library stream) and the dominant
 kernel's HBM roofline are reported beside it, and the FP64 CPU oracle is
-timed on a bounded sample of the same recipe as the CPU baseline.
+timed on a bounded sample of the same recipe as the CPU baseline.  The
+FP16-storage variant (FP32 arithmetic, adjoint and incremental fields held in
+FP16) is timed on the same inputs and reported in "precision_variant".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -44,6 +46,10 @@ def parse_args():
     ap.add_argument("--matvecs", type=int, default=20, help="matvecs in the matvec-only timing")
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-variant", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the timed region, run a fill and a multiply over 1 GiB (known "
+                         "traffic) as the reference for memory-traffic counters")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -115,6 +121,68 @@ def cpu_baseline(args):
     }
 
 
+OPTS = dict(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+
+
+def timed_solves(args, ctx, torch, warmup, steps):
+    """GN solves from v = 0: `warmup` untimed, then `steps` timed back to back."""
+    for w in range(warmup):
+        _, rep = ctx.gn_solve(**OPTS)
+        log(args, "warmup solve %d: %s" % (w, rep))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(steps):
+        _, rep = ctx.gn_solve(**OPTS)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for k, rep in enumerate(reps):
+        log(args, "timed solve %d: %s" % (k, rep))
+    return reps, wall
+
+
+def matvec_ms(args, ctx, torch, v, probe):
+    """Matvec-only time at velocity v with the probe direction (events on the
+    library stream)."""
+    ctx.set_velocity(v)
+    out = ctx.empty(3)
+    for _ in range(3):
+        ctx.hessian_matvec(probe, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    for _ in range(args.matvecs):
+        ctx.hessian_matvec(probe, out)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.matvecs
+    log(args, "matvec-only (%s): %.3f ms (%.1f matvecs/s)" % (ctx.dtype_name, ms, 1000.0 / ms))
+    return ms
+
+
+def precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, plain):
+    """The same workload with FP16 storage of the adjoint and incremental
+    fields: one warm-up and `steps` timed solves, the matvec-only rate, and
+    the final mismatch against the plain FP32 solve's."""
+    ctx = mireg.Context((n, n, n), nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3,
+                        beta_w=1.0, dtype="f32h16")
+    ctx.set_images(mT, mR)
+    reps, wall = timed_solves(args, ctx, torch, 1, args.steps)
+    ms = matvec_ms(args, ctx, torch, v_true, probe)
+    ctx.close()
+    rep = reps[-1]
+    return {
+        "dtype": "f32 compute, f16 storage of lambda, mt, lt",
+        "time_to_tol_s": round(wall / max(1, args.steps), 4),
+        "matvecs_per_s": round(sum(r["matvecs"] for r in reps) / wall, 3),
+        "matvec_only_per_s": round(1000.0 / ms, 2),
+        "matvec_ms": round(ms, 4),
+        "solve": {k: rep[k] for k in ("status", "gn_iters", "matvecs", "mismatch_rel", "gnorm_rel")},
+        "mismatch_rel_change_vs_plain": round(abs(rep["mismatch_rel"] - plain["mismatch_rel"])
+                                              / plain["mismatch_rel"], 6),
+    }
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -138,39 +206,19 @@ def main():
     ctx.set_images(mT, mR)
     torch.cuda.synchronize()
     log(args, "inputs ready in %.1f s" % (time.perf_counter() - t0))
+    if args.copy_calibration:
+        # fill: writes 1 GiB; multiply: reads 1 GiB and writes 1 GiB
+        a = torch.ones(1 << 28, dtype=torch.float32, device=ctx.device)
+        b = torch.empty_like(a)
+        torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
-    opts = dict(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
-    for w in range(args.warmup):
-        _, rep = ctx.gn_solve(**opts)
-        log(args, "warmup solve %d: %s" % (w, rep))
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = []
-    for k in range(args.steps):
-        _, rep = ctx.gn_solve(**opts)
-        reps.append(rep)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for k, rep in enumerate(reps):
-        log(args, "timed solve %d: %s" % (k, rep))
+    reps, wall = timed_solves(args, ctx, torch, args.warmup, args.steps)
     total_mv = sum(r["matvecs"] for r in reps)
     value = total_mv / wall
-
-    # matvec-only rate at the generating velocity with the probe direction
-    ctx.set_velocity(v_true)
+    mv_ms = matvec_ms(args, ctx, torch, v_true, probe)
     out = ctx.empty(3)
-    for _ in range(3):
-        ctx.hessian_matvec(probe, out)
-    stream = ctx.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.matvecs):
-        ctx.hessian_matvec(probe, out)
-    e1.record(stream)
-    e1.synchronize()
-    mv_ms = e0.elapsed_time(e1) / args.matvecs
-    log(args, "matvec-only: %.3f ms (%.1f matvecs/s)" % (mv_ms, 1000.0 / mv_ms))
 
     # per-kernel event timing over a separate run of matvecs
     ctx.kernel_stats(enable=True, reset=True)
@@ -205,6 +253,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5)}
 
+    prec = None
+    if not args.no_precision_variant:
+        log(args, "FP16-storage variant")
+        prec = precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, reps[-1])
+
     cpu = None
     if not args.no_cpu_baseline:
         log(args, "timing the CPU oracle sample")
@@ -236,6 +289,7 @@ def main():
         "interp_ms_per_matvec": round(sl_ms, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "precision_variant": prec,
         "kernels": kernels,
     }
     ctx.close()

@@ -13,7 +13,8 @@
  *  - Grid: n = (n1, n2, n3), each a power of two in [8, 512]; point
  *    (i1, i2, i3) sits at x_a = 2 pi i_a / n_a.  Scalar fields are dense
  *    C-ordered [n1][n2][n3] arrays (x3 fastest); vector fields are
- *    [3][n1][n2][n3].  Element type is the context dtype (float or double).
+ *    [3][n1][n2][n3].  Element type is the context's boundary type: float
+ *    for MIREG_F32 and MIREG_F32_H16, double for MIREG_F64.
  *  - Memory: every field pointer is a DEVICE pointer owned by the caller,
  *    borrowed for the duration of the call only.  Scalars (J, norms, counts)
  *    are HOST pointers.  mireg_set_images / mireg_set_velocity copy their
@@ -47,7 +48,14 @@ enum {
     MIREG_E_NONFINITE = -6  /* NaN or Inf in an input */
 };
 
-typedef enum { MIREG_F32 = 0, MIREG_F64 = 1 } mireg_dtype;
+/* Arithmetic and storage: F32 and F64 compute and store every field in that
+ * type; F32_H16 computes in FP32 and exchanges FP32 fields at the boundary,
+ * but holds the adjoint history lambda^j and the incremental fields mt, lt
+ * (the fields the Hessian matvec streams) in FP16.  The state history m^j
+ * stays FP32: lambda(1) = mR - m(1) is a small difference of O(1) values,
+ * so FP16 rounding of m would reach the gradient amplified by |m|/|lambda|.
+ * Reductions are FP64 always. */
+typedef enum { MIREG_F32 = 0, MIREG_F64 = 1, MIREG_F32_H16 = 2 } mireg_dtype;
 
 /* Regularisation operator A = B*B (Sec. 2.1): H1 seminorm B = grad gives
  * A = -Lap; H2 seminorm B = -Lap gives A = Lap^2. */

@@ -1,6 +1,7 @@
 // Shared device/host helpers of the mireg HIP library (gfx950).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,6 +38,29 @@ __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return make_cx(-a.im, a.re); }
 // multiply by -i
 template <typename T>
 __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return make_cx(a.im, -a.re); }
+
+// Storage conversions: fields may be held in a narrower type S than the
+// arithmetic type T (FP16 storage of transported fields, FP32 arithmetic).
+template <typename T, typename S>
+__device__ __forceinline__ T load_as(const S *p, long long i) {
+    return (T)p[i];
+}
+template <>
+__device__ __forceinline__ float load_as<float, __half>(const __half *p, long long i) {
+    return __half2float(p[i]);
+}
+template <>
+__device__ __forceinline__ double load_as<double, __half>(const __half *p, long long i) {
+    return (double)__half2float(p[i]);
+}
+template <typename S, typename T>
+__device__ __forceinline__ void store_as(S *p, long long i, T v) {
+    p[i] = (S)v;
+}
+template <>
+__device__ __forceinline__ void store_as<__half, float>(__half *p, long long i, float v) {
+    p[i] = __float2half_rn(v);
+}
 
 // Integer wavenumber of FFT index j on an axis of length n (the Nyquist
 // index n/2 maps to -n/2).

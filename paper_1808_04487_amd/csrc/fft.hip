@@ -35,9 +35,9 @@ __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtr
     const int t = threadIdx.x % TPC, c = threadIdx.x / TPC;
     const long long line = (long long)blockIdx.x * W + c;
     const bool ok = line < lines;
-    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * M;
     cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * (M + 1);
     cx<T> reg[EPT];
+    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * M;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) reg[e] = ok ? in[t + TPC * e] : make_cx<T>(0, 0);
     fft_line<T, M, 0, -1, Lay>(reg, t, c, tw, 2, lds);
@@ -332,7 +332,7 @@ static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
     {                                                                                                  \
         constexpr int W = FftShape<T, M, 0, kLineThreads>::W;                                          \
         dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);     \
+        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);          \
     }
     MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
 #undef MIREG_L
@@ -385,10 +385,10 @@ static void launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpCon
 }
 
 template <typename T>
-void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *in, T *const *out,
+void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *const *in, T *const *out,
                     cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
     FieldPtrs fin{}, fspec{}, fout{};
-    for (int i = 0; i < nin; ++i) fin.p[i] = const_cast<T *>(in[i]);
+    for (int i = 0; i < nin; ++i) fin.p[i] = const_cast<void *>(in[i]);
     for (int i = 0; i < 6; ++i) fspec.p[i] = spec + (long long)i * g.NS;
     for (int i = 0; i < nout; ++i) fout.p[i] = out[i];
 
@@ -423,10 +423,10 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *
     launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
 }
 
-template void spectral_apply<float>(const Grid &, int, int, int, const float *const *, float *const *,
+template void spectral_apply<float>(const Grid &, int, int, int, const void *const *, float *const *,
                                     cx<float> *, const Twiddles<float> &, const SpecParams &,
                                     hipStream_t);
-template void spectral_apply<double>(const Grid &, int, int, int, const double *const *,
+template void spectral_apply<double>(const Grid &, int, int, int, const void *const *,
                                      double *const *, cx<double> *, const Twiddles<double> &,
                                      const SpecParams &, hipStream_t);
 

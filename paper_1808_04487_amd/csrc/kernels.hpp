@@ -8,7 +8,7 @@ namespace mireg {
 // Kernel kinds for the per-launch statistics.
 enum KernelId {
     K_R2C = 0, K_C2C_FWD, K_C2C_INV, K_X1_SCALE, K_X1_GRAD, K_X1_DIV, K_X1_PROJ, K_X1_TAIL, K_C2R,
-    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
+    K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_ADJ_ACC, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
     K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
@@ -64,7 +64,7 @@ struct Twiddles {
 // 3D pipeline: R2C(x3) -> C2C(x2) -> [x1 forward, operator, x1 inverse]
 // -> C2C(x2 inverse) -> C2R(x3).  spec holds max(nin, nout) half spectra.
 template <typename T>
-void spectral_apply(const Grid &g, int kind, int nin, int nout, const T *const *in, T *const *out,
+void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *const *in, T *const *out,
                     cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
 
 // ---- semi-Lagrangian transport (transport.hip) ----
@@ -77,35 +77,35 @@ struct StepConst {
 // disp = sign dt/2 (v + I[v](x + sign dt v)) / h  (cell units)
 template <typename T>
 void departure(const Grid &g, int order, int sign, double dt, const T *v, T *disp, hipStream_t s);
-// out = I[f](x + disp)
-template <typename T>
-void interp_field(const Grid &g, int order, const T *f, const T *disp, T *out, hipStream_t s);
-// Adjoint final condition: lam = mR - m(1)
-template <typename T>
-void adjoint_init(const Grid &g, const T *mR, const T *m, T *lam, hipStream_t s);
+// out = I[f](x + disp); f and out in storage types SI, SO (arithmetic in T)
+template <typename T, typename SI, typename SO>
+void interp_field(const Grid &g, int order, const SI *f, const T *disp, SO *out, hipStream_t s);
+// Adjoint final condition: lam = mR - m(1)   (lam in storage type S)
+template <typename T, typename S>
+void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s);
 // One adjoint step: lam_out = L + dt/2 (S + (L + dt S) d), L = I[lam_in](Y), S = I[lam_in d](Y)
-template <typename T>
-void adjoint_step(const Grid &g, int order, double dt, const T *lam_in, const T *d, const T *Y,
-                  T *lam_out, hipStream_t s);
+template <typename T, typename S>
+void adjoint_step(const Grid &g, int order, double dt, const S *lam_in, const T *d, const T *Y,
+                  S *lam_out, hipStream_t s);
 // Last adjoint step fused with the time integral: lam^0 from lam^1 (in the
 // history), then b = sum_j a_j lam^j grad m^j (lam^0 is not stored)
-template <typename T>
-void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const T *lam, const T *d,
+template <typename T, typename S>
+void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const S *lam, const T *d,
                              const T *Y, const T *gradm, T *b, hipStream_t s);
 // Incremental state: q0 = -dt/2 grad m^0 . vt
-template <typename T>
-void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s);
+template <typename T, typename S>
+void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q, hipStream_t s);
 // q_out = sign (I[q_in](X) + coef f^{j+1}), f = -grad m^{j+1} . vt
-template <typename T>
-void incstate_step(const Grid &g, int order, double coef, double sign, const T *q_in, const T *X,
-                   const T *gradm_next, const T *vt, T *q_out, hipStream_t s);
+template <typename T, typename S>
+void incstate_step(const Grid &g, int order, double coef, double sign, const S *q_in, const T *X,
+                   const T *gradm_next, const T *vt, S *q_out, hipStream_t s);
 
 // ---- vector kernels and FP64 reductions (vec.hip) ----
 // result[k] (device doubles) for k < nres; see the individual descriptions.
 template <typename T>
 void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s);
-template <typename T>
-void sumsq_diff(const T *a, const T *b, long long n, double *partials, double *result,
+template <typename TA, typename TB>
+void sumsq_diff(const TA *a, const TB *b, long long n, double *partials, double *result,
                 hipStream_t s);
 // y = a x + b y
 template <typename T>

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -195,7 +196,7 @@ int readback(mireg_ctx *ctx, int nres) {
     return MIREG_OK;
 }
 
-template <typename T>
+template <typename T, typename S = T>
 SpecParams spec_params(const mireg_ctx *ctx) {
     SpecParams sp{};
     sp.reg = ctx->p.reg;
@@ -207,69 +208,69 @@ SpecParams spec_params(const mireg_ctx *ctx) {
     return sp;
 }
 
-template <typename T>
+template <typename T, typename S = T>
 Twiddles<T> twiddles(const mireg_ctx *ctx) {
     Twiddles<T> t;
     for (int a = 0; a < 3; ++a) t.t[a] = static_cast<const cx<T> *>(ctx->tw[a]);
     return t;
 }
 
-template <typename T>
-void spec(mireg_ctx *ctx, int kind, int nin, int nout, const T *const *in, T *const *out, const SpecParams &sp) {
+template <typename T, typename S = T>
+void spec(mireg_ctx *ctx, int kind, int nin, int nout, const void *const *in, T *const *out, const SpecParams &sp) {
     Phase ph(ctx, 0);
     spectral_apply<T>(ctx->g, kind, nin, nout, in, out, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp,
                       ctx->stream);
 }
 
 // ---- individual spectral operators ----
-template <typename T>
+template <typename T, typename S = T>
 void op_grad(mireg_ctx *ctx, const T *u, T *out) {
     const long long N = ctx->N();
-    const T *in[1] = {u};
+    const void *in[1] = {u};
     T *o[3] = {out, out + N, out + 2 * N};
-    spec<T>(ctx, SPEC_GRAD, 1, 3, in, o, spec_params<T>(ctx));
+    spec<T, S>(ctx, SPEC_GRAD, 1, 3, in, o, spec_params<T>(ctx));
 }
-template <typename T>
+template <typename T, typename S = T>
 void op_div(mireg_ctx *ctx, const T *v, T *out) {
     const long long N = ctx->N();
-    const T *in[3] = {v, v + N, v + 2 * N};
+    const void *in[3] = {v, v + N, v + 2 * N};
     T *o[1] = {out};
-    spec<T>(ctx, SPEC_DIV, 3, 1, in, o, spec_params<T>(ctx));
+    spec<T, S>(ctx, SPEC_DIV, 3, 1, in, o, spec_params<T>(ctx));
 }
-template <typename T>
+template <typename T, typename S = T>
 void op_scale(mireg_ctx *ctx, int sym, int nf, double alpha, double sigma, const T *u, T *out) {
     const long long N = ctx->N();
-    const T *in[3] = {u, u + N, u + 2 * N};
+    const void *in[3] = {u, u + N, u + 2 * N};
     T *o[3] = {out, out + N, out + 2 * N};
     SpecParams sp = spec_params<T>(ctx);
     sp.sym = sym;
     sp.nf = nf;
     sp.alpha = alpha;
     sp.sigma = sigma;
-    spec<T>(ctx, SPEC_SCALE, nf, nf, in, o, sp);
+    spec<T, S>(ctx, SPEC_SCALE, nf, nf, in, o, sp);
 }
-template <typename T>
+template <typename T, typename S = T>
 void op_proj(mireg_ctx *ctx, int div, const T *u, T *out) {
     const long long N = ctx->N();
-    const T *in[3] = {u, u + N, u + 2 * N};
+    const void *in[3] = {u, u + N, u + 2 * N};
     T *o[3] = {out, out + N, out + 2 * N};
     SpecParams sp = spec_params<T>(ctx);
     sp.div = div;
-    spec<T>(ctx, SPEC_PROJ, 3, 3, in, o, sp);
+    spec<T, S>(ctx, SPEC_PROJ, 3, 3, in, o, sp);
 }
 // out = alpha A u + K b
-template <typename T>
+template <typename T, typename S = T>
 void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
     const long long N = ctx->N();
-    const T *in[6] = {u, u + N, u + 2 * N, b, b + N, b + 2 * N};
+    const void *in[6] = {u, u + N, u + 2 * N, b, b + N, b + 2 * N};
     T *o[3] = {out, out + N, out + 2 * N};
     SpecParams sp = spec_params<T>(ctx);
     sp.alpha = alpha;
-    spec<T>(ctx, SPEC_TAIL, 6, 3, in, o, sp);
+    spec<T, S>(ctx, SPEC_TAIL, 6, 3, in, o, sp);
 }
 
 // ---- velocity-dependent caches ----
-template <typename T>
+template <typename T, typename S = T>
 void ensure_X(mireg_ctx *ctx) {
     if (ctx->have_X) return;
     Phase ph(ctx, 1);
@@ -277,7 +278,7 @@ void ensure_X(mireg_ctx *ctx) {
                  ctx->stream);
     ctx->have_X = true;
 }
-template <typename T>
+template <typename T, typename S = T>
 void ensure_Y(mireg_ctx *ctx) {
     if (ctx->have_Y) return;
     Phase ph(ctx, 1);
@@ -285,32 +286,36 @@ void ensure_Y(mireg_ctx *ctx) {
                  ctx->stream);
     ctx->have_Y = true;
 }
-// State equation forward in time: m^0 = mT, m^{j+1} = I[m^j](X).
-template <typename T>
+// State equation forward in time: m^0 = mT, m^{j+1} = I[m^j](X).  The state
+// history is held in T in every storage mode: lam(1) = mR - m(1) is a small
+// difference of O(1) values, so FP16 rounding of m would reach lam, and the
+// gradient, amplified by |m| / |lam|.
+template <typename T, typename S = T>
 void ensure_state(mireg_ctx *ctx) {
     if (ctx->have_state) return;
-    ensure_X<T>(ctx);
+    ensure_X<T, S>(ctx);
     const long long N = ctx->N();
     T *m = ctx->f<T>(ctx->m);
     hipMemcpyAsync(m, ctx->mT, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream);
     Phase ph(ctx, 1);
     for (int j = 0; j < ctx->p.nt; ++j)
-        interp_field<T>(ctx->g, ctx->p.interp_order, m + j * N, ctx->f<T>(ctx->X), m + (j + 1) * N, ctx->stream);
+        interp_field<T, T, T>(ctx->g, ctx->p.interp_order, m + j * N, ctx->f<T>(ctx->X), m + (j + 1) * N,
+                              ctx->stream);
     ctx->have_state = true;
 }
-template <typename T>
+template <typename T, typename S = T>
 void ensure_gradm(mireg_ctx *ctx) {
     if (ctx->have_gradm) return;
-    ensure_state<T>(ctx);
+    ensure_state<T, S>(ctx);
     const long long N = ctx->N();
     for (int j = 0; j <= ctx->p.nt; ++j)
-        op_grad<T>(ctx, ctx->f<T>(ctx->m) + j * N, ctx->f<T>(ctx->gradm) + 3 * j * N);
+        op_grad<T, S>(ctx, ctx->f<T>(ctx->m) + j * N, ctx->f<T>(ctx->gradm) + 3 * j * N);
     ctx->have_gradm = true;
 }
-template <typename T>
+template <typename T, typename S = T>
 void ensure_d(mireg_ctx *ctx) {
     if (ctx->have_d) return;
-    op_div<T>(ctx, ctx->f<T>(ctx->v), ctx->f<T>(ctx->d));
+    op_div<T, S>(ctx, ctx->f<T>(ctx->v), ctx->f<T>(ctx->d));
     ctx->have_d = true;
 }
 
@@ -318,20 +323,20 @@ void ensure_d(mireg_ctx *ctx) {
 // Backward sweep shared by the adjoint and the incremental adjoint: from
 // lam^nt in the history buffer, lam^j for j = nt-1..1, then the last step
 // fused with the time integral b = sum_j a_j lam^j grad m^j.
-template <typename T>
-void backward_sweep(mireg_ctx *ctx, T *lam, T *b) {
+template <typename T, typename S = T>
+void backward_sweep(mireg_ctx *ctx, S *lam, T *b) {
     const int nt = ctx->p.nt;
     const long long N = ctx->N();
     const double dt = 1.0 / nt;
     Phase ph(ctx, 1);
     for (int j = nt - 1; j >= 1; --j)
-        adjoint_step<T>(ctx->g, ctx->p.interp_order, dt, lam + (j + 1) * N, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
-                        lam + j * N, ctx->stream);
-    adjoint_step_accumulate<T>(ctx->g, ctx->p.interp_order, dt, nt, lam, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
+        adjoint_step<T, S>(ctx->g, ctx->p.interp_order, dt, lam + (j + 1) * N, ctx->f<T>(ctx->d),
+                           ctx->f<T>(ctx->Y), lam + j * N, ctx->stream);
+    adjoint_step_accumulate<T, S>(ctx->g, ctx->p.interp_order, dt, nt, lam, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
                                ctx->f<T>(ctx->gradm), b, ctx->stream);
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int dot_h(mireg_ctx *ctx, const T *a, const T *b, long long n, double *out) {
     dot<T>(a, b, n, ctx->partials, ctx->dres, ctx->stream);
     int rc = readback(ctx, 1);
@@ -341,27 +346,27 @@ int dot_h(mireg_ctx *ctx, const T *a, const T *b, long long n, double *out) {
 }
 
 // ---- objective ----
-template <typename T>
+template <typename T, typename S = T>
 int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    ensure_state<T>(ctx);
+    ensure_state<T, S>(ctx);
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
-    sumsq_diff<T>(ctx->f<T>(ctx->m) + nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    sumsq_diff<T, T>(ctx->f<T>(ctx->m) + nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
     int rc = readback(ctx, 1);
     if (rc) return rc;
     const double mis = 0.5 * ctx->cell() * ctx->hres[0];
     // beta_v/2 <A v, v>
     T *Av = ctx->vec<T>(7);
-    op_scale<T>(ctx, SYM_A, 3, 1.0, 0.0, ctx->f<T>(ctx->v), Av);
+    op_scale<T, S>(ctx, SYM_A, 3, 1.0, 0.0, ctx->f<T>(ctx->v), Av);
     double vAv = 0;
     if ((rc = dot_h<T>(ctx, Av, ctx->f<T>(ctx->v), 3 * N, &vAv))) return rc;
     double r = 0.5 * ctx->p.beta_v * vAv;
     if (ctx->p.div == MIREG_DIV_NEAR) {
         // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2)
-        ensure_d<T>(ctx);
+        ensure_d<T, S>(ctx);
         T *gw = ctx->vec<T>(7);
-        op_grad<T>(ctx, ctx->f<T>(ctx->d), gw);
+        op_grad<T, S>(ctx, ctx->f<T>(ctx->d), gw);
         double a = 0, c = 0;
         if ((rc = dot_h<T>(ctx, gw, gw, 3 * N, &a))) return rc;
         if ((rc = dot_h<T>(ctx, ctx->f<T>(ctx->d), ctx->f<T>(ctx->d), N, &c))) return rc;
@@ -374,22 +379,23 @@ int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
 }
 
 // ---- reduced gradient ----
-template <typename T>
+template <typename T, typename S = T>
 int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    ensure_state<T>(ctx);
-    ensure_gradm<T>(ctx);
-    ensure_d<T>(ctx);
-    ensure_Y<T>(ctx);
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
-    T *lam = ctx->f<T>(ctx->lam), *b = ctx->f<T>(ctx->b);
+    S *lam = ctx->f<S>(ctx->lam);
+    T *b = ctx->f<T>(ctx->b);
     {
         Phase ph(ctx, 2);
-        adjoint_init<T>(ctx->g, ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N, lam + nt * N, ctx->stream);
+        adjoint_init<T, S>(ctx->g, ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N, lam + nt * N, ctx->stream);
     }
-    backward_sweep<T>(ctx, lam, b);
-    op_tail<T>(ctx, ctx->p.beta_v, ctx->f<T>(ctx->v), b, g);
+    backward_sweep<T, S>(ctx, lam, b);
+    op_tail<T, S>(ctx, ctx->p.beta_v, ctx->f<T>(ctx->v), b, g);
     if (gnorm) {
         double gg = 0;
         int rc = dot_h<T>(ctx, g, g, 3 * N, &gg);
@@ -400,51 +406,52 @@ int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
 }
 
 // ---- Gauss-Newton Hessian matvec ----
-template <typename T>
+template <typename T, typename S = T>
 int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    ensure_state<T>(ctx);
-    ensure_gradm<T>(ctx);
-    ensure_d<T>(ctx);
-    ensure_Y<T>(ctx);
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
     const double dt = 1.0 / nt;
-    T *q0 = ctx->f<T>(ctx->q), *q1 = q0 + N, *lam = ctx->f<T>(ctx->lam), *b = ctx->f<T>(ctx->b);
+    S *q0 = ctx->f<S>(ctx->q), *q1 = q0 + N, *lam = ctx->f<S>(ctx->lam);
+    T *b = ctx->f<T>(ctx->b);
     const T *gm = ctx->f<T>(ctx->gradm);
     {
         Phase ph(ctx, 1);
         // incremental state: q^0 = mt^0 + dt/2 f^0 with mt^0 = 0
-        incstate_init<T>(ctx->g, dt, gm, vt, q0, ctx->stream);
-        T *cur = q0, *nxt = q1;
+        incstate_init<T, S>(ctx->g, dt, gm, vt, q0, ctx->stream);
+        S *cur = q0, *nxt = q1;
         for (int j = 0; j < nt; ++j) {
             if (j < nt - 1) {
                 // q^{j+1} = I[q^j](X) + dt f^{j+1}
-                incstate_step<T>(ctx->g, ctx->p.interp_order, dt, 1.0, cur, ctx->f<T>(ctx->X), gm + 3 * (j + 1) * N,
+                incstate_step<T, S>(ctx->g, ctx->p.interp_order, dt, 1.0, cur, ctx->f<T>(ctx->X), gm + 3 * (j + 1) * N,
                                  vt, nxt, ctx->stream);
-                T *t = cur;
+                S *t = cur;
                 cur = nxt;
                 nxt = t;
             } else {
                 // mt(1) = I[q](X) + dt/2 f^nt; the incremental adjoint starts at lt^nt = -mt(1)
-                incstate_step<T>(ctx->g, ctx->p.interp_order, 0.5 * dt, -1.0, cur, ctx->f<T>(ctx->X),
+                incstate_step<T, S>(ctx->g, ctx->p.interp_order, 0.5 * dt, -1.0, cur, ctx->f<T>(ctx->X),
                                  gm + 3 * nt * N, vt, lam + nt * N, ctx->stream);
             }
         }
     }
-    backward_sweep<T>(ctx, lam, b);
-    op_tail<T>(ctx, ctx->p.beta_v, vt, b, Hvt);
+    backward_sweep<T, S>(ctx, lam, b);
+    op_tail<T, S>(ctx, ctx->p.beta_v, vt, b, Hvt);
     return check_launch(ctx);
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int impl_precond(mireg_ctx *ctx, const T *r, T *z) {
-    op_scale<T>(ctx, SYM_AINV, 3, ctx->p.beta_v, 0.0, r, z);
+    op_scale<T, S>(ctx, SYM_AINV, 3, ctx->p.beta_v, 0.0, r, z);
     return check_launch(ctx);
 }
 
 // ---- PCG (Algorithm "inner iteration") ----
-template <typename T>
+template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
     const long long n = 3 * ctx->N();
     const double h3 = ctx->cell();
@@ -458,12 +465,12 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
     int it = 0;
     double rnorm = r0;
     if (r0 > 0) {
-        impl_precond<T>(ctx, r, z);
+        impl_precond<T, S>(ctx, r, z);
         HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
         double rz = 0;
         if ((rc = dot_h<T>(ctx, r, z, n, &rz))) return rc;
         while (it < maxit) {
-            if ((rc = impl_matvec<T>(ctx, s, Hs))) return rc;
+            if ((rc = impl_matvec<T, S>(ctx, s, Hs))) return rc;
             double sHs = 0;
             if ((rc = dot_h<T>(ctx, s, Hs, n, &sHs))) return rc;
             if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate
@@ -476,7 +483,7 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[0]);
             if (rnorm <= rtol * r0) break;
-            impl_precond<T>(ctx, r, z);
+            impl_precond<T, S>(ctx, r, z);
             double rz_new = 0;
             if ((rc = dot_h<T>(ctx, r, z, n, &rz_new))) return rc;
             const double mu = rz_new / rz;
@@ -489,11 +496,11 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
     return check_launch(ctx);
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int impl_set_velocity(mireg_ctx *ctx, const T *v);
 
 // ---- GN (Algorithm "outer iteration") ----
-template <typename T>
+template <typename T, typename S = T>
 int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *rep) {
     auto t0 = std::chrono::steady_clock::now();
     const long long n = 3 * ctx->N();
@@ -502,13 +509,13 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     // vectors 0..3 belong to PCG; 4: g, 5: vt, 6: accepted v
     T *g = ctx->vec<T>(4), *vt = ctx->vec<T>(5), *vk = ctx->vec<T>(6);
     int rc;
-    if ((rc = impl_set_velocity<T>(ctx, v_io))) return rc;
+    if ((rc = impl_set_velocity<T, S>(ctx, v_io))) return rc;
     HIP_OK(hipMemcpyAsync(vk, v_io, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     double J = 0;
-    if ((rc = impl_objective<T>(ctx, &J, nullptr, nullptr))) return rc;
+    if ((rc = impl_objective<T, S>(ctx, &J, nullptr, nullptr))) return rc;
     R.pde_solves += 1;
     double gn = 0;
-    if ((rc = impl_gradient<T>(ctx, g, &gn))) return rc;
+    if ((rc = impl_gradient<T, S>(ctx, g, &gn))) return rc;
     R.pde_solves += 1;
     const double g0 = gn;
     R.J0 = J;
@@ -534,7 +541,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
         T *rhs = ctx->vec<T>(7);
         affine<T>(n, g, -1.0, 0.0, rhs, ctx->stream);
         int its = 0;
-        if ((rc = impl_pcg<T>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr))) return rc;
+        if ((rc = impl_pcg<T, S>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr))) return rc;
         R.matvecs += its;
         R.pcg_iters += its;
         R.pde_solves += 2 * its;
@@ -546,7 +553,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
             // trial velocity v = vk + alpha vt, written into the context velocity
             xpay<T>(n, vk, alpha, vt, ctx->f<T>(ctx->v), ctx->stream);
             ctx->invalidate();
-            if ((rc = impl_objective<T>(ctx, &Jt, nullptr, nullptr))) return rc;
+            if ((rc = impl_objective<T, S>(ctx, &Jt, nullptr, nullptr))) return rc;
             R.ls_trials += 1;
             R.pde_solves += 1;
             if (Jt <= J + o->armijo_c1 * alpha * slope) {
@@ -563,7 +570,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
         }
         HIP_OK(hipMemcpyAsync(vk, ctx->v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
         J = Jt;
-        if ((rc = impl_gradient<T>(ctx, g, &gn))) return rc;
+        if ((rc = impl_gradient<T, S>(ctx, g, &gn))) return rc;
         R.pde_solves += 1;
         ++k;
     }
@@ -572,12 +579,13 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     R.gnorm = gn;
     R.gnorm_rel = g0 > 0 ? gn / g0 : 0.0;
     // mismatch_rel = ||m(1) - mR||^2 / ||mT - mR||^2
-    ensure_state<T>(ctx);
+    ensure_state<T, S>(ctx);
     const long long N = ctx->N();
-    sumsq_diff<T>(ctx->f<T>(ctx->m) + ctx->p.nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    sumsq_diff<T, T>(ctx->f<T>(ctx->m) + ctx->p.nt * N, ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres,
+                     ctx->stream);
     if ((rc = readback(ctx, 1))) return rc;
     const double num = ctx->hres[0];
-    sumsq_diff<T>(ctx->f<T>(ctx->mT), ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
+    sumsq_diff<T, T>(ctx->f<T>(ctx->mT), ctx->f<T>(ctx->mR), N, ctx->partials, ctx->dres, ctx->stream);
     if ((rc = readback(ctx, 1))) return rc;
     R.mismatch_rel = ctx->hres[0] > 0 ? num / ctx->hres[0] : 0.0;
     HIP_OK(hipMemcpyAsync(v_io, vk, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
@@ -588,7 +596,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     return check_launch(ctx);
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int check_finite(mireg_ctx *ctx, const T *a, long long n, const char *what) {
     minmax_nonfinite<T>(a, n, ctx->partials, ctx->dres, ctx->stream);
     int rc = readback(ctx, 3);
@@ -597,12 +605,12 @@ int check_finite(mireg_ctx *ctx, const T *a, long long n, const char *what) {
     return MIREG_OK;
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int impl_set_images(mireg_ctx *ctx, const T *mT, const T *mR) {
     const long long N = ctx->N();
     int rc;
-    if ((rc = check_finite<T>(ctx, mT, N, "mT"))) return rc;
-    if ((rc = check_finite<T>(ctx, mR, N, "mR"))) return rc;
+    if ((rc = check_finite<T, S>(ctx, mT, N, "mT"))) return rc;
+    if ((rc = check_finite<T, S>(ctx, mR, N, "mR"))) return rc;
     HIP_OK(hipMemcpyAsync(ctx->mT, mT, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->mR, mR, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     ctx->have_images = true;
@@ -610,30 +618,30 @@ int impl_set_images(mireg_ctx *ctx, const T *mT, const T *mR) {
     return MIREG_OK;
 }
 
-template <typename T>
+template <typename T, typename S>
 int impl_set_velocity(mireg_ctx *ctx, const T *v) {
     const long long n = 3 * ctx->N();
     int rc;
-    if ((rc = check_finite<T>(ctx, v, n, "v"))) return rc;
+    if ((rc = check_finite<T, S>(ctx, v, n, "v"))) return rc;
     if (v != ctx->v) HIP_OK(hipMemcpyAsync(ctx->v, v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     ctx->invalidate();
     return MIREG_OK;
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
     const long long N = ctx->N();
     switch (opcode) {
-        case MIREG_OP_GRAD: op_grad<T>(ctx, in, out); break;
-        case MIREG_OP_DIV: op_div<T>(ctx, in, out); break;
-        case MIREG_OP_LAPLACE: op_scale<T>(ctx, SYM_LAP, 1, 1.0, 0.0, in, out); break;
-        case MIREG_OP_APPLY_A: op_scale<T>(ctx, SYM_A, 3, 1.0, 0.0, in, out); break;
-        case MIREG_OP_APPLY_K: op_proj<T>(ctx, ctx->p.div, in, out); break;
-        case MIREG_OP_LERAY: op_proj<T>(ctx, MIREG_DIV_LERAY, in, out); break;
-        case MIREG_OP_PRECOND: impl_precond<T>(ctx, in, out); break;
+        case MIREG_OP_GRAD: op_grad<T, S>(ctx, in, out); break;
+        case MIREG_OP_DIV: op_div<T, S>(ctx, in, out); break;
+        case MIREG_OP_LAPLACE: op_scale<T, S>(ctx, SYM_LAP, 1, 1.0, 0.0, in, out); break;
+        case MIREG_OP_APPLY_A: op_scale<T, S>(ctx, SYM_A, 3, 1.0, 0.0, in, out); break;
+        case MIREG_OP_APPLY_K: op_proj<T, S>(ctx, ctx->p.div, in, out); break;
+        case MIREG_OP_LERAY: op_proj<T, S>(ctx, MIREG_DIV_LERAY, in, out); break;
+        case MIREG_OP_PRECOND: impl_precond<T, S>(ctx, in, out); break;
         case MIREG_OP_GAUSS:
             if (!(arg >= 0)) return ctx->fail(MIREG_E_ARG, "Gaussian width must be >= 0");
-            op_scale<T>(ctx, SYM_GAUSS, 1, 1.0, arg, in, out);
+            op_scale<T, S>(ctx, SYM_GAUSS, 1, 1.0, arg, in, out);
             break;
         case MIREG_OP_DEPARTURE_X:
         case MIREG_OP_DEPARTURE_Y: {
@@ -643,20 +651,28 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
             break;
         }
         case MIREG_OP_TRANSPORT_STATE: {
-            ensure_X<T>(ctx);
-            T *a = ctx->f<T>(ctx->q), *b = a + N;
+            ensure_X<T, S>(ctx);
+            // intermediate slices in T, as the state history is held
+            T *a = ctx->vec<T>(7), *b = a + N;
+            const T *X = ctx->f<T>(ctx->X);
+            const int nt = ctx->p.nt, ord = ctx->p.interp_order;
             Phase ph(ctx, 1);
-            const T *src = in;
-            for (int j = 0; j < ctx->p.nt; ++j) {
-                T *dst = (j == ctx->p.nt - 1) ? out : ((j & 1) ? b : a);
-                interp_field<T>(ctx->g, ctx->p.interp_order, src, ctx->f<T>(ctx->X), dst, ctx->stream);
-                src = dst;
+            if (nt == 1) {
+                interp_field<T, T, T>(ctx->g, ord, in, X, out, ctx->stream);
+            } else {
+                // step 0 writes a; step j in 1..nt-2 reads the previous output
+                // and writes b for odd j, a for even j; step nt-1 writes out
+                interp_field<T, T, T>(ctx->g, ord, in, X, a, ctx->stream);
+                for (int j = 1; j < nt - 1; ++j) {
+                    interp_field<T, T, T>(ctx->g, ord, (j & 1) ? a : b, X, (j & 1) ? b : a, ctx->stream);
+                }
+                interp_field<T, T, T>(ctx->g, ord, ((nt - 2) & 1) ? b : a, X, out, ctx->stream);
             }
             break;
         }
         case MIREG_OP_INTERP: {
             Phase ph(ctx, 1);
-            interp_field<T>(ctx->g, ctx->p.interp_order, in, in + N, out, ctx->stream);
+            interp_field<T, T, T>(ctx->g, ctx->p.interp_order, in, in + N, out, ctx->stream);
             break;
         }
         case MIREG_OP_RESCALE01: {
@@ -682,7 +698,7 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
     return check_launch(ctx);
 }
 
-template <typename T>
+template <typename T, typename S = T>
 int make_twiddles(mireg_ctx *ctx) {
     const int n[3] = {ctx->g.n1, ctx->g.n2, ctx->g.n3};
     for (int a = 0; a < 3; ++a) {
@@ -711,8 +727,16 @@ struct HookGuard {
     ~HookGuard() { mireg::g_hook = nullptr; }
 };
 
-#define DISPATCH(ctx, CALL_F, CALL_D) \
-    (HookGuard{ctx}, ((ctx)->p.dtype == MIREG_F64 ? (CALL_D) : (CALL_F)))
+// Typed dispatch: F32 -> <float, float>, F64 -> <double, double>,
+// F32 with FP16 storage of the transported fields -> <float, __half>.
+// CALL is an expression in the type aliases T (arithmetic and boundary type)
+// and S (storage of the transported fields).
+#define DISPATCH(ctx, CALL)                                                                            \
+    (HookGuard{ctx},                                                                                   \
+     ((ctx)->p.dtype == MIREG_F64                                                                      \
+          ? [&] { using T = double; using S = double; return CALL; }()                                 \
+          : (ctx)->p.dtype == MIREG_F32_H16 ? [&] { using T = float; using S = __half; return CALL; }() \
+                                            : [&] { using T = float; using S = float; return CALL; }()))
 
 }  // namespace
 
@@ -753,7 +777,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (p->nt < 1 || p->nt > 64 || (p->interp_order != 1 && p->interp_order != 3) ||
         (p->reg != MIREG_H1 && p->reg != MIREG_H2) || p->div < 0 || p->div > 2 || !(p->beta_v > 0) ||
         !(p->beta_w >= 0) || (p->div == MIREG_DIV_NEAR && !(p->beta_w > 0)) ||
-        (p->dtype != MIREG_F32 && p->dtype != MIREG_F64))
+        (p->dtype != MIREG_F32 && p->dtype != MIREG_F64 && p->dtype != MIREG_F32_H16))
         return MIREG_E_ARG;
     mireg_ctx *ctx = new (std::nothrow) mireg_ctx;
     if (!ctx) return MIREG_E_NOMEM;
@@ -778,6 +802,8 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     }
     ctx->elem = p->dtype == MIREG_F64 ? 8 : 4;
     const size_t F = (size_t)ctx->g.N * ctx->elem;
+    // adjoint history and incremental fields: FP16 in the F32_H16 mode
+    const size_t FS = (size_t)ctx->g.N * (p->dtype == MIREG_F32_H16 ? 2 : ctx->elem);
     const int nt = p->nt;
     int rc = MIREG_OK;
     if (!rc) rc = alloc(ctx, &ctx->mT, F);
@@ -788,8 +814,8 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, &ctx->m, (size_t)(nt + 1) * F);
     if (!rc) rc = alloc(ctx, &ctx->gradm, (size_t)(nt + 1) * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->d, F);
-    if (!rc) rc = alloc(ctx, &ctx->lam, (size_t)(nt + 1) * F);
-    if (!rc) rc = alloc(ctx, &ctx->q, 2 * F);
+    if (!rc) rc = alloc(ctx, &ctx->lam, (size_t)(nt + 1) * FS);
+    if (!rc) rc = alloc(ctx, &ctx->q, 2 * FS);
     if (!rc) rc = alloc(ctx, &ctx->b, 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->vecs, (size_t)mireg_ctx::kVecs * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);
@@ -798,7 +824,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, (void **)&ctx->dres, 8 * sizeof(double));
     if (!rc && hipHostMalloc((void **)&ctx->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         rc = ctx->fail(MIREG_E_NOMEM, "hipHostMalloc failed");
-    if (!rc) rc = DISPATCH(ctx, make_twiddles<float>(ctx), make_twiddles<double>(ctx));
+    if (!rc) rc = DISPATCH(ctx, (make_twiddles<T, S>(ctx)));
     if (!rc && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
         rc = ctx->fail(MIREG_E_HIP, "hipEventCreate failed");
     if (!rc) {
@@ -834,14 +860,12 @@ size_t mireg_workspace_bytes(const mireg_ctx *ctx) { return ctx ? ctx->bytes : 0
 
 int mireg_set_images(mireg_ctx *ctx, const void *mT, const void *mR) {
     if (!ctx || !mT || !mR) return ctx ? ctx->fail(MIREG_E_ARG, "null image pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, impl_set_images<float>(ctx, (const float *)mT, (const float *)mR),
-                    impl_set_images<double>(ctx, (const double *)mT, (const double *)mR));
+    return DISPATCH(ctx, (impl_set_images<T, S>(ctx, (const T *)mT, (const T *)mR)));
 }
 
 int mireg_set_velocity(mireg_ctx *ctx, const void *v) {
     if (!ctx || !v) return ctx ? ctx->fail(MIREG_E_ARG, "null velocity pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, impl_set_velocity<float>(ctx, (const float *)v),
-                    impl_set_velocity<double>(ctx, (const double *)v));
+    return DISPATCH(ctx, (impl_set_velocity<T, S>(ctx, (const T *)v)));
 }
 
 int mireg_get_velocity(mireg_ctx *ctx, void *v) {
@@ -852,25 +876,23 @@ int mireg_get_velocity(mireg_ctx *ctx, void *v) {
 
 int mireg_objective(mireg_ctx *ctx, double *J, double *mismatch, double *reg) {
     if (!ctx) return MIREG_E_ARG;
-    return DISPATCH(ctx, impl_objective<float>(ctx, J, mismatch, reg), impl_objective<double>(ctx, J, mismatch, reg));
+    return DISPATCH(ctx, (impl_objective<T, S>(ctx, J, mismatch, reg)));
 }
 
 int mireg_gradient(mireg_ctx *ctx, void *g, double *gnorm) {
     if (!ctx || !g) return ctx ? ctx->fail(MIREG_E_ARG, "null gradient pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, impl_gradient<float>(ctx, (float *)g, gnorm), impl_gradient<double>(ctx, (double *)g, gnorm));
+    return DISPATCH(ctx, (impl_gradient<T, S>(ctx, (T *)g, gnorm)));
 }
 
 int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt) {
     if (!ctx || !vt || !Hvt) return ctx ? ctx->fail(MIREG_E_ARG, "null matvec pointer") : MIREG_E_ARG;
     if (vt == Hvt) return ctx->fail(MIREG_E_ARG, "vt and Hvt must not alias");
-    return DISPATCH(ctx, impl_matvec<float>(ctx, (const float *)vt, (float *)Hvt),
-                    impl_matvec<double>(ctx, (const double *)vt, (double *)Hvt));
+    return DISPATCH(ctx, (impl_matvec<T, S>(ctx, (const T *)vt, (T *)Hvt)));
 }
 
 int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
     if (!ctx || !r || !z) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, impl_precond<float>(ctx, (const float *)r, (float *)z),
-                    impl_precond<double>(ctx, (const double *)r, (double *)z));
+    return DISPATCH(ctx, (impl_precond<T, S>(ctx, (const T *)r, (T *)z)));
 }
 
 int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit, int *iters,
@@ -878,8 +900,7 @@ int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int m
     if (!ctx || !rhs || !x) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
     if (maxit < 0 || !(rtol >= 0)) return ctx->fail(MIREG_E_ARG, "invalid rtol/maxit");
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    return DISPATCH(ctx, impl_pcg<float>(ctx, (const float *)rhs, (float *)x, rtol, maxit, iters, relres),
-                    impl_pcg<double>(ctx, (const double *)rhs, (double *)x, rtol, maxit, iters, relres));
+    return DISPATCH(ctx, (impl_pcg<T, S>(ctx, (const T *)rhs, (T *)x, rtol, maxit, iters, relres)));
 }
 
 int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts, mireg_report *rep) {
@@ -889,13 +910,12 @@ int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts, 
     mireg_default_solve_opts(&o);
     if (opts) o = *opts;
     if (o.max_gn < 0 || o.max_pcg < 0 || o.max_ls < 0) return ctx->fail(MIREG_E_ARG, "negative iteration cap");
-    return DISPATCH(ctx, impl_gn<float>(ctx, (float *)v_inout, &o, rep), impl_gn<double>(ctx, (double *)v_inout, &o, rep));
+    return DISPATCH(ctx, (impl_gn<T, S>(ctx, (T *)v_inout, &o, rep)));
 }
 
 int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg) {
     if (!ctx || !in || !out) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, impl_op<float>(ctx, opcode, (const float *)in, (float *)out, arg),
-                    impl_op<double>(ctx, opcode, (const double *)in, (double *)out, arg));
+    return DISPATCH(ctx, (impl_op<T, S>(ctx, opcode, (const T *)in, (T *)out, arg)));
 }
 
 int mireg_kernel_stats_enable(mireg_ctx *ctx, int on) {

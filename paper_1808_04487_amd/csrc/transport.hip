@@ -404,32 +404,32 @@ struct DepartureOp {
     }
 };
 
-// out = I[f](x + disp)
-template <typename T>
+// out = I[f](x + disp); f and out in storage types SI, SO
+template <typename T, typename SI, typename SO>
 struct InterpOp {
-    const T *__restrict__ f;
+    const SI *__restrict__ f;
     const T *__restrict__ D;
-    T *__restrict__ out;
+    SO *__restrict__ out;
     int N;
     __device__ void disp(int i, T *d) const {
         d[0] = D[i];
         d[1] = D[N + i];
         d[2] = D[2 * N + i];
     }
-    __device__ void stage(int i, T *x) const { x[0] = f[i]; }
+    __device__ void stage(int i, T *x) const { x[0] = load_as<T>(f, i); }
     struct Pre {};
     __device__ Pre pre(int) const { return Pre{}; }
-    __device__ void finish(int i, const Pre &, const T *a) const { out[i] = a[0]; }
+    __device__ void finish(int i, const Pre &, const T *a) const { store_as(out, i, a[0]); }
 };
 
 // Adjoint step: lambda^j = L + dt/2 (S + (L + dt S) d), L = I[lambda^{j+1}](Y),
 // S = I[lambda^{j+1} d](Y).
-template <typename T>
+template <typename T, typename SL>
 struct AdjointOp {
-    const T *__restrict__ lin;
+    const SL *__restrict__ lin;
     const T *__restrict__ dv;
     const T *__restrict__ Y;
-    T *__restrict__ lout;
+    SL *__restrict__ lout;
     int N;
     T dt;
     __device__ void disp(int i, T *d) const {
@@ -438,7 +438,7 @@ struct AdjointOp {
         d[2] = Y[2 * N + i];
     }
     __device__ void stage(int i, T *x) const {
-        const T l = lin[i];
+        const T l = load_as<T>(lin, i);
         x[0] = l;
         x[1] = l * dv[i];
     }
@@ -448,24 +448,24 @@ struct AdjointOp {
     __device__ Pre pre(int i) const { return Pre{dv[i]}; }
     __device__ void finish(int i, const Pre &p, const T *a) const {
         const T L = a[0], S = a[1];
-        lout[i] = L + (T)0.5 * dt * (S + (L + dt * S) * p.d);
+        store_as(lout, i, L + (T)0.5 * dt * (S + (L + dt * S) * p.d));
     }
 };
 
 // Last adjoint step (j = 0) fused with the time integral: lambda^0 as above,
 // then b = sum_j a_j lambda^j grad m^j from lambda^0 (in registers) and the
 // stored lambda^1..nt; the history reads overlap the gather-bound step.
-template <typename T>
+template <typename T, typename SL>
 struct AdjointAccumOp {
-    AdjointOp<T> step;
-    const T *__restrict__ lam;  // history [nt+1][N]
+    AdjointOp<T, SL> step;
+    const SL *__restrict__ lam;  // history [nt+1][N]
     const T *__restrict__ gm;   // [nt+1][3][N]
     T *__restrict__ b;
     int nt;
     T a_end, a_mid;
     __device__ void disp(int i, T *d) const { step.disp(i, d); }
     __device__ void stage(int i, T *x) const { step.stage(i, x); }
-    using Pre = typename AdjointOp<T>::Pre;
+    using Pre = typename AdjointOp<T, SL>::Pre;
     __device__ Pre pre(int i) const { return step.pre(i); }
     __device__ void finish(int i, const Pre &p, const T *a) const {
         const int N = step.N;
@@ -474,7 +474,7 @@ struct AdjointAccumOp {
         T al = a_end * l0;
         T b1 = al * gm[i], b2 = al * gm[N + i], b3 = al * gm[2 * N + i];
         for (int j = 1; j <= nt; ++j) {
-            al = (j == nt ? a_end : a_mid) * lam[j * N + i];
+            al = (j == nt ? a_end : a_mid) * load_as<T>(lam, (long long)j * N + i);
             const T *g = gm + 3 * j * N;
             b1 += al * g[i];
             b2 += al * g[N + i];
@@ -489,13 +489,13 @@ struct AdjointAccumOp {
 // Incremental state: q^{j+1} = I[q^j](X) + coef f^{j+1}, f = -grad m^{j+1} . vt;
 // on the last step (coef = dt/2) the output is -mt(1), the final condition
 // of the incremental adjoint.
-template <typename T>
+template <typename T, typename SQ>
 struct IncStateOp {
-    const T *__restrict__ qin;
+    const SQ *__restrict__ qin;
     const T *__restrict__ X;
     const T *__restrict__ gm;
     const T *__restrict__ vt;
-    T *__restrict__ qout;
+    SQ *__restrict__ qout;
     int N;
     T coef, sign;
     __device__ void disp(int i, T *d) const {
@@ -503,32 +503,32 @@ struct IncStateOp {
         d[1] = X[N + i];
         d[2] = X[2 * N + i];
     }
-    __device__ void stage(int i, T *x) const { x[0] = qin[i]; }
+    __device__ void stage(int i, T *x) const { x[0] = load_as<T>(qin, i); }
     struct Pre {
         T f;
     };
     __device__ Pre pre(int i) const {
         return Pre{-(gm[i] * vt[i] + gm[N + i] * vt[N + i] + gm[2 * N + i] * vt[2 * N + i])};
     }
-    __device__ void finish(int i, const Pre &p, const T *a) const { qout[i] = sign * (a[0] + coef * p.f); }
+    __device__ void finish(int i, const Pre &p, const T *a) const { store_as(qout, i, sign * (a[0] + coef * p.f)); }
 };
 
 // Final condition of the adjoint: lambda(1) = mR - m(1).
-template <typename T>
+template <typename T, typename S>
 __global__ __launch_bounds__(kSlThreads) void k_adjoint_init(long long N, const T *__restrict__ mR,
-                                                             const T *__restrict__ m, T *__restrict__ lam) {
+                                                             const T *__restrict__ m, S *__restrict__ lam) {
     const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
     if (idx >= N) return;
-    lam[idx] = mR[idx] - m[idx];
+    store_as(lam, idx, mR[idx] - m[idx]);
 }
 
-template <typename T>
+template <typename T, typename S>
 __global__ __launch_bounds__(kSlThreads) void k_incstate_init(long long N, T hdt, const T *__restrict__ gm,
-                                                              const T *__restrict__ vt, T *__restrict__ q) {
+                                                              const T *__restrict__ vt, S *__restrict__ q) {
     const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
     if (idx >= N) return;
     const T f = -(gm[idx] * vt[idx] + gm[N + idx] * vt[N + idx] + gm[2 * N + idx] * vt[2 * N + idx]);
-    q[idx] = hdt * f;
+    store_as(q, idx, hdt * f);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,69 +561,71 @@ void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *di
     launch_sl<T, 3>(g, order, op, s);
 }
 
-template <typename T>
-void interp_field(const Grid &gg, int order, const T *f, const T *disp, T *out, hipStream_t s) {
+template <typename T, typename SI, typename SO>
+void interp_field(const Grid &gg, int order, const SI *f, const T *disp, SO *out, hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_INTERP, 5.0 * g.N * sizeof(T));
-    InterpOp<T> op{f, disp, out, (int)g.N};
+    HookScope hs(K_INTERP, (3.0 * sizeof(T) + sizeof(SI) + sizeof(SO)) * g.N);
+    InterpOp<T, SI, SO> op{f, disp, out, (int)g.N};
     launch_sl<T, 1>(g, order, op, s);
 }
 
-template <typename T>
-void adjoint_init(const Grid &g, const T *mR, const T *m, T *lam, hipStream_t s) {
-    HookScope hs(K_ADJ_INIT, 3.0 * g.N * sizeof(T));
-    hipLaunchKernelGGL((k_adjoint_init<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, mR, m, lam);
+template <typename T, typename S>
+void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s) {
+    HookScope hs(K_ADJ_INIT, (2.0 * sizeof(T) + sizeof(S)) * g.N);
+    hipLaunchKernelGGL((k_adjoint_init<T, S>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, mR, m, lam);
 }
 
-template <typename T>
-void adjoint_step(const Grid &gg, int order, double dt, const T *lam_in, const T *d, const T *Y, T *lam_out,
+template <typename T, typename S>
+void adjoint_step(const Grid &gg, int order, double dt, const S *lam_in, const T *d, const T *Y, S *lam_out,
                   hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_ADJ_STEP, 6.0 * g.N * sizeof(T));
-    AdjointOp<T> op{lam_in, d, Y, lam_out, (int)g.N, (T)dt};
+    HookScope hs(K_ADJ_STEP, (4.0 * sizeof(T) + 2.0 * sizeof(S)) * g.N);
+    AdjointOp<T, S> op{lam_in, d, Y, lam_out, (int)g.N, (T)dt};
     launch_sl<T, 2>(g, order, op, s);
 }
 
-template <typename T>
-void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const T *lam, const T *d,
+template <typename T, typename S>
+void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const S *lam, const T *d,
                              const T *Y, const T *gradm, T *b, hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_ADJ_STEP, (6.0 - 1.0 + 4.0 * nt + 3.0 + 3.0) * g.N * sizeof(T));
+    HookScope hs(K_ADJ_ACC, ((4.0 + 3.0 * (nt + 1) + 3.0) * sizeof(T) + (double)nt * sizeof(S)) * g.N);
     const long long N = g.N;
-    AdjointOp<T> step{lam + N, d, Y, nullptr, (int)N, (T)dt};
-    AdjointAccumOp<T> op{step, lam, gradm, b, nt, (T)(0.5 * dt), (T)dt};
+    AdjointOp<T, S> step{lam + N, d, Y, nullptr, (int)N, (T)dt};
+    AdjointAccumOp<T, S> op{step, lam, gradm, b, nt, (T)(0.5 * dt), (T)dt};
     launch_sl<T, 2>(g, order, op, s);
 }
 
-template <typename T>
-void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, T *q, hipStream_t s) {
-    HookScope hs(K_INC_INIT, 7.0 * g.N * sizeof(T));
-    hipLaunchKernelGGL((k_incstate_init<T>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N,
+template <typename T, typename S>
+void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q, hipStream_t s) {
+    HookScope hs(K_INC_INIT, 6.0 * sizeof(T) * g.N + sizeof(S) * g.N);
+    hipLaunchKernelGGL((k_incstate_init<T, S>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N,
                        (T)(0.5 * dt), gradm0, vt, q);
 }
 
-template <typename T>
-void incstate_step(const Grid &gg, int order, double coef, double sign, const T *q_in, const T *X,
-                   const T *gradm_next, const T *vt, T *q_out, hipStream_t s) {
+template <typename T, typename S>
+void incstate_step(const Grid &gg, int order, double coef, double sign, const S *q_in, const T *X,
+                   const T *gradm_next, const T *vt, S *q_out, hipStream_t s) {
     const PGrid g = pgrid(gg);
-    HookScope hs(K_INC_STEP, 11.0 * g.N * sizeof(T));
-    IncStateOp<T> op{q_in, X, gradm_next, vt, q_out, (int)g.N, (T)coef, (T)sign};
+    HookScope hs(K_INC_STEP, 9.0 * sizeof(T) * g.N + 2.0 * sizeof(S) * g.N);
+    IncStateOp<T, S> op{q_in, X, gradm_next, vt, q_out, (int)g.N, (T)coef, (T)sign};
     launch_sl<T, 1>(g, order, op, s);
 }
 
-#define MIREG_INST(T)                                                                                   \
-    template void departure<T>(const Grid &, int, int, double, const T *, T *, hipStream_t);            \
-    template void interp_field<T>(const Grid &, int, const T *, const T *, T *, hipStream_t);           \
-    template void adjoint_init<T>(const Grid &, const T *, const T *, T *, hipStream_t);               \
-    template void adjoint_step<T>(const Grid &, int, double, const T *, const T *, const T *, T *,      \
-                                  hipStream_t);                                                         \
-    template void adjoint_step_accumulate<T>(const Grid &, int, double, int, const T *, const T *,     \
-                                             const T *, const T *, T *, hipStream_t);               \
-    template void incstate_init<T>(const Grid &, double, const T *, const T *, T *, hipStream_t);      \
-    template void incstate_step<T>(const Grid &, int, double, double, const T *, const T *, const T *, \
-                                   const T *, T *, hipStream_t);
-MIREG_INST(float)
-MIREG_INST(double)
+template void departure<float>(const Grid &, int, int, double, const float *, float *, hipStream_t);
+template void departure<double>(const Grid &, int, int, double, const double *, double *, hipStream_t);
+#define MIREG_INST(T, S)                                                                                  \
+    template void interp_field<T, S, S>(const Grid &, int, const S *, const T *, S *, hipStream_t);       \
+    template void adjoint_init<T, S>(const Grid &, const T *, const T *, S *, hipStream_t);              \
+    template void adjoint_step<T, S>(const Grid &, int, double, const S *, const T *, const T *, S *,    \
+                                     hipStream_t);                                                        \
+    template void adjoint_step_accumulate<T, S>(const Grid &, int, double, int, const S *, const T *,    \
+                                                const T *, const T *, T *, hipStream_t);                 \
+    template void incstate_init<T, S>(const Grid &, double, const T *, const T *, S *, hipStream_t);     \
+    template void incstate_step<T, S>(const Grid &, int, double, double, const S *, const T *, const T *, \
+                                      const T *, S *, hipStream_t);
+MIREG_INST(float, float)
+MIREG_INST(double, double)
+MIREG_INST(float, __half)
 #undef MIREG_INST
 
 }  // namespace mireg

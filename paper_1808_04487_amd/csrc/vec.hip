@@ -47,13 +47,13 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const T *__restrict__ a, co
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_sumsq_diff(const T *__restrict__ a, const T *__restrict__ b,
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kRedThreads) void k_sumsq_diff(const TA *__restrict__ a, const TB *__restrict__ b,
                                                             long long n, double *__restrict__ part) {
     double v[1] = {0.0};
     for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
          i += (long long)gridDim.x * kRedThreads) {
-        const double d = (double)a[i] - (double)b[i];
+        const double d = load_as<double>(a, i) - load_as<double>(b, i);
         v[0] += d * d;
     }
     block_sum<1>(v);
@@ -211,7 +211,7 @@ thread_local KernelHook *g_hook = nullptr;
 const char *const kKernelNames[K_COUNT] = {
     "fft_r2c_x3", "fft_c2c_x2_fwd", "fft_c2c_x2_inv", "fft_x1_scale", "fft_x1_grad", "fft_x1_div",
     "fft_x1_proj", "fft_x1_tail", "fft_c2r_x3", "sl_departure", "sl_interp", "sl_adjoint_init",
-    "sl_adjoint_step", "sl_incstate_init", "sl_incstate_step", "reduce", "vector"};
+    "sl_adjoint_step", "sl_adjoint_accum", "sl_incstate_init", "sl_incstate_step", "reduce", "vector"};
 
 template <typename T>
 void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
@@ -219,10 +219,10 @@ void dot(const T *a, const T *b, long long n, double *partials, double *result, 
     hipLaunchKernelGGL((k_dot<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
-template <typename T>
-void sumsq_diff(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
-    HookScope hs(K_REDUCE, 2.0 * n * sizeof(T));
-    hipLaunchKernelGGL((k_sumsq_diff<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
+template <typename TA, typename TB>
+void sumsq_diff(const TA *a, const TB *b, long long n, double *partials, double *result, hipStream_t s) {
+    HookScope hs(K_REDUCE, (double)n * (sizeof(TA) + sizeof(TB)));
+    hipLaunchKernelGGL((k_sumsq_diff<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
@@ -268,7 +268,7 @@ void fill(long long n, T val, T *y, hipStream_t s) {
 
 #define MIREG_INST(T)                                                                                 \
     template void dot<T>(const T *, const T *, long long, double *, double *, hipStream_t);           \
-    template void sumsq_diff<T>(const T *, const T *, long long, double *, double *, hipStream_t);    \
+    template void sumsq_diff<T, T>(const T *, const T *, long long, double *, double *, hipStream_t); \
     template void pcg_update<T>(long long, double, const T *, const T *, T *, T *, double *, double *, \
                                 hipStream_t);                                                         \
     template void minmax_nonfinite<T>(const T *, long long, double *, double *, hipStream_t);         \

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmireg.so")
 
 OK, E_ARG, E_SHAPE, E_STATE, E_HIP, E_NOMEM, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
-F32, F64 = 0, 1
+F32, F64, F32_H16 = 0, 1, 2
 H1, H2 = 1, 2
 DIV_NONE, DIV_NEAR, DIV_LERAY = 0, 1, 2
 CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL = 1, 2, 3, 4
@@ -119,11 +119,15 @@ def load_library(path=LIB_PATH):
 
 
 def _torch_dtype(dtype):
+    """(boundary torch dtype, library code); "f32h16" is FP32 arithmetic with
+    FP16 storage of the adjoint history and the incremental fields."""
     if dtype in (torch.float32, "f32", "float32", F32):
         return torch.float32, F32
     if dtype in (torch.float64, "f64", "float64", F64):
         return torch.float64, F64
-    raise ValueError("dtype must be float32 or float64")
+    if dtype in ("f32h16", F32_H16):
+        return torch.float32, F32_H16
+    raise ValueError("dtype must be float32, float64 or 'f32h16'")
 
 
 class Context:
@@ -141,6 +145,7 @@ class Context:
             raise MiregError(E_STATE, "no HIP device available")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.dtype, code = _torch_dtype(dtype)
+        self.dtype_name = {F32: "f32", F64: "f64", F32_H16: "f32h16"}[code]
         self.n = tuple(int(x) for x in n)
         p = Params()
         self.lib.mireg_default_params(ctypes.byref(p))

@@ -144,3 +144,26 @@ def test_tile_shapes_agree_bitwise(monkeypatch):
     for m, h in outs[1:]:
         assert torch.equal(m, outs[0][0])
         assert torch.equal(h, outs[0][1])
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 5])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, "f32h16"])
+def test_transport_state_time_steps(nt, dtype):
+    """The state transport alternates two slice buffers; every parity of the
+    step count ends on the last slice (m at t = 1, Sec. 3.4)."""
+    need_gpu()
+    n = (16, 32, 16)
+    g = core.Grid(n)
+    tdt = torch.float32 if dtype == "f32h16" else dtype
+    ctx = mireg.Context(n, nt=nt, dtype=dtype)
+    v_t, v = as_input(smooth_vector(g, 71, amp=1.0, sigma=1.5), tdt)
+    f_t, f = as_input(smooth_scalar(g, 72), tdt)
+    ctx.set_velocity(v_t)
+    m1 = ctx.op("transport_state", f_t)
+    ref = prep.transport(g, f, v, nt=nt, order=3)
+    if dtype == "f32h16":
+        # nt - 1 stored slices, each rounded to FP16 (unit roundoff 2^-11)
+        assert np.abs(m1.double().cpu().numpy() - ref).max() <= 2.0 ** -11 * nt * np.abs(ref).max()
+    else:
+        assert_close(m1, ref, dtype, factor=4, what="state m(1) nt=%d" % nt)
+    ctx.close()
