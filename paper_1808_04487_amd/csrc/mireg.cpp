@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -125,6 +126,7 @@ struct mireg_ctx {
 
     bool have_images = false;
     bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
+    int box_X = 0, box_Y = 0;  // largest stencil box (nodes) of X and Y
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool stats_on = false;
@@ -270,20 +272,46 @@ void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
 }
 
 // ---- velocity-dependent caches ----
+// Largest stencil box of the displacement (a D_a) b_a over the transport
+// tiles, read back to the host (synchronises the stream); it sizes the LDS
+// of the transport launches that use D.  0 when staging is switched off.
+template <typename T>
+int measure_box(mireg_ctx *ctx, const T *D, double a, const double b[3]) {
+    if (ctx->g.lds_cap == 0) return 0;
+    unsigned *dev = reinterpret_cast<unsigned *>(ctx->dres);
+    sl_box_volume<T>(ctx->g, ctx->p.interp_order, D, a, b, dev, ctx->stream);
+    if (readback(ctx, 1) != MIREG_OK) return INT_MAX;  // every tile then takes the largest LDS
+    unsigned v = 0;
+    memcpy(&v, ctx->hres, sizeof v);
+    return v > (unsigned)INT_MAX ? INT_MAX : (int)v;
+}
+template <typename T>
+int box_of_displacement(mireg_ctx *ctx, const T *D) {
+    const double one[3] = {1.0, 1.0, 1.0};
+    return measure_box<T>(ctx, D, 1.0, one);
+}
+// Characteristic feet of one step (sign -1: X, +1: Y) from velocity v.
+template <typename T>
+void compute_departure(mireg_ctx *ctx, int sign, const T *v, T *out) {
+    const double two_pi = 6.283185307179586476925;
+    const double ih[3] = {ctx->g.n1 / two_pi, ctx->g.n2 / two_pi, ctx->g.n3 / two_pi};
+    const double dt = 1.0 / ctx->p.nt;
+    const int box = measure_box<T>(ctx, v, sign * dt, ih);  // predictor displacement
+    Phase ph(ctx, 1);
+    departure<T>(ctx->g, ctx->p.interp_order, sign, dt, v, out, box, ctx->stream);
+}
 template <typename T, typename S = T>
 void ensure_X(mireg_ctx *ctx) {
     if (ctx->have_X) return;
-    Phase ph(ctx, 1);
-    departure<T>(ctx->g, ctx->p.interp_order, -1, 1.0 / ctx->p.nt, ctx->f<T>(ctx->v), ctx->f<T>(ctx->X),
-                 ctx->stream);
+    compute_departure<T>(ctx, -1, ctx->f<T>(ctx->v), ctx->f<T>(ctx->X));
+    ctx->box_X = box_of_displacement<T>(ctx, ctx->f<T>(ctx->X));
     ctx->have_X = true;
 }
 template <typename T, typename S = T>
 void ensure_Y(mireg_ctx *ctx) {
     if (ctx->have_Y) return;
-    Phase ph(ctx, 1);
-    departure<T>(ctx->g, ctx->p.interp_order, +1, 1.0 / ctx->p.nt, ctx->f<T>(ctx->v), ctx->f<T>(ctx->Y),
-                 ctx->stream);
+    compute_departure<T>(ctx, +1, ctx->f<T>(ctx->v), ctx->f<T>(ctx->Y));
+    ctx->box_Y = box_of_displacement<T>(ctx, ctx->f<T>(ctx->Y));
     ctx->have_Y = true;
 }
 // State equation forward in time: m^0 = mT, m^{j+1} = I[m^j](X).  The state
@@ -300,7 +328,7 @@ void ensure_state(mireg_ctx *ctx) {
     Phase ph(ctx, 1);
     for (int j = 0; j < ctx->p.nt; ++j)
         interp_field<T, T, T>(ctx->g, ctx->p.interp_order, m + j * N, ctx->f<T>(ctx->X), m + (j + 1) * N,
-                              ctx->stream);
+                              ctx->box_X, ctx->stream);
     ctx->have_state = true;
 }
 template <typename T, typename S = T>
@@ -331,9 +359,9 @@ void backward_sweep(mireg_ctx *ctx, S *lam, T *b) {
     Phase ph(ctx, 1);
     for (int j = nt - 1; j >= 1; --j)
         adjoint_step<T, S>(ctx->g, ctx->p.interp_order, dt, lam + (j + 1) * N, ctx->f<T>(ctx->d),
-                           ctx->f<T>(ctx->Y), lam + j * N, ctx->stream);
+                           ctx->f<T>(ctx->Y), lam + j * N, ctx->box_Y, ctx->stream);
     adjoint_step_accumulate<T, S>(ctx->g, ctx->p.interp_order, dt, nt, lam, ctx->f<T>(ctx->d), ctx->f<T>(ctx->Y),
-                               ctx->f<T>(ctx->gradm), b, ctx->stream);
+                               ctx->f<T>(ctx->gradm), b, ctx->box_Y, ctx->stream);
 }
 
 template <typename T, typename S = T>
@@ -428,14 +456,14 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
             if (j < nt - 1) {
                 // q^{j+1} = I[q^j](X) + dt f^{j+1}
                 incstate_step<T, S>(ctx->g, ctx->p.interp_order, dt, 1.0, cur, ctx->f<T>(ctx->X), gm + 3 * (j + 1) * N,
-                                 vt, nxt, ctx->stream);
+                                 vt, nxt, ctx->box_X, ctx->stream);
                 S *t = cur;
                 cur = nxt;
                 nxt = t;
             } else {
                 // mt(1) = I[q](X) + dt/2 f^nt; the incremental adjoint starts at lt^nt = -mt(1)
                 incstate_step<T, S>(ctx->g, ctx->p.interp_order, 0.5 * dt, -1.0, cur, ctx->f<T>(ctx->X),
-                                 gm + 3 * nt * N, vt, lam + nt * N, ctx->stream);
+                                 gm + 3 * nt * N, vt, lam + nt * N, ctx->box_X, ctx->stream);
             }
         }
     }
@@ -644,35 +672,33 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
             op_scale<T, S>(ctx, SYM_GAUSS, 1, 1.0, arg, in, out);
             break;
         case MIREG_OP_DEPARTURE_X:
-        case MIREG_OP_DEPARTURE_Y: {
-            Phase ph(ctx, 1);
-            departure<T>(ctx->g, ctx->p.interp_order, opcode == MIREG_OP_DEPARTURE_X ? -1 : +1, 1.0 / ctx->p.nt, in,
-                         out, ctx->stream);
+        case MIREG_OP_DEPARTURE_Y:
+            compute_departure<T>(ctx, opcode == MIREG_OP_DEPARTURE_X ? -1 : +1, in, out);
             break;
-        }
         case MIREG_OP_TRANSPORT_STATE: {
             ensure_X<T, S>(ctx);
             // intermediate slices in T, as the state history is held
             T *a = ctx->vec<T>(7), *b = a + N;
             const T *X = ctx->f<T>(ctx->X);
-            const int nt = ctx->p.nt, ord = ctx->p.interp_order;
+            const int nt = ctx->p.nt, ord = ctx->p.interp_order, box = ctx->box_X;
             Phase ph(ctx, 1);
             if (nt == 1) {
-                interp_field<T, T, T>(ctx->g, ord, in, X, out, ctx->stream);
+                interp_field<T, T, T>(ctx->g, ord, in, X, out, box, ctx->stream);
             } else {
                 // step 0 writes a; step j in 1..nt-2 reads the previous output
                 // and writes b for odd j, a for even j; step nt-1 writes out
-                interp_field<T, T, T>(ctx->g, ord, in, X, a, ctx->stream);
+                interp_field<T, T, T>(ctx->g, ord, in, X, a, box, ctx->stream);
                 for (int j = 1; j < nt - 1; ++j) {
-                    interp_field<T, T, T>(ctx->g, ord, (j & 1) ? a : b, X, (j & 1) ? b : a, ctx->stream);
+                    interp_field<T, T, T>(ctx->g, ord, (j & 1) ? a : b, X, (j & 1) ? b : a, box, ctx->stream);
                 }
-                interp_field<T, T, T>(ctx->g, ord, ((nt - 2) & 1) ? b : a, X, out, ctx->stream);
+                interp_field<T, T, T>(ctx->g, ord, ((nt - 2) & 1) ? b : a, X, out, box, ctx->stream);
             }
             break;
         }
         case MIREG_OP_INTERP: {
+            const int box = box_of_displacement<T>(ctx, in + N);
             Phase ph(ctx, 1);
-            interp_field<T, T, T>(ctx->g, ctx->p.interp_order, in, in + N, out, ctx->stream);
+            interp_field<T, T, T>(ctx->g, ctx->p.interp_order, in, in + N, out, box, ctx->stream);
             break;
         }
         case MIREG_OP_RESCALE01: {
@@ -793,7 +819,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     // memory (the path taken by tiles whose stencil box exceeds LDS).
     {
         const char *e = getenv("MIREG_LDS_STENCIL");
-        ctx->g.lds_cap = (e && atoi(e) == 0) ? 0 : 1 << 30;
+        ctx->g.lds_cap = (e && atoi(e) == 0) ? 0 : INT_MAX;
         // MIREG_SL_TILE selects the tile shape of the transport kernels:
         // 0: 4x8x32, 1: 8x8x16, 2: 8x16x16 (x1 x x2 x x3).
         const char *t = getenv("MIREG_SL_TILE");

@@ -30,7 +30,7 @@ struct PGrid {
     int s3, s23;  // log2(n3), log2(n2 n3)
     long long N;
     int tx, ty, tz;  // tiles per axis
-    int lds_cap;     // largest box (points) staged in LDS; 0 disables staging
+    int lds_cap;     // largest box (nodes) staged in LDS in this launch; 0 disables staging
     int shape;       // tile shape (SlTile)
 };
 
@@ -52,13 +52,13 @@ struct TileDims<TILE_8x16x16> {
 };
 
 constexpr int kSlThreads = 256;
-constexpr int kBoxCap = 6144;                       // LDS box capacity in points
-constexpr int kStageU = 8;                          // staging loads in flight per thread
+constexpr int kStageU = 8;        // staging loads in flight per thread
+constexpr int kLdsBytes = 65536;  // largest LDS allocation of one workgroup
 
-// Box capacity of one instantiation: at most 64 KB of LDS per workgroup.
-template <typename T, int NF>
-constexpr int box_cap() {
-    return (int)(65536 / (NF * sizeof(T))) < kBoxCap ? (int)(65536 / (NF * sizeof(T))) : kBoxCap;
+// Cells per unit length on axis a (the grid spans 2 pi).
+static double departure_ih(const Grid &g, int a) {
+    const double two_pi = 6.283185307179586476925;
+    return (a == 0 ? g.n1 : a == 1 ? g.n2 : g.n3) / two_pi;
 }
 
 static PGrid pgrid(const Grid &g) {
@@ -75,11 +75,12 @@ static PGrid pgrid(const Grid &g) {
     p.tx = (g.n3 + TX - 1) / TX;
     p.ty = (g.n2 + TY - 1) / TY;
     p.tz = (g.n1 + TZ - 1) / TZ;
-    p.lds_cap = g.lds_cap < kBoxCap ? g.lds_cap : kBoxCap;
+    p.lds_cap = g.lds_cap;
     return p;
 }
 
-// Node weights of one axis and the node below the position.
+// Node weights of one axis (from the fractional position t in [0, 1)) and
+// the node below the position.
 template <typename T, int ORDER>
 struct AxisW {
     static constexpr int NP = ORDER == 3 ? 4 : 2;
@@ -89,18 +90,17 @@ struct AxisW {
 };
 
 template <typename T, int ORDER>
-__device__ __forceinline__ AxisW<T, ORDER> axis_weights(int i, T d) {
+__device__ __forceinline__ AxisW<T, ORDER> axis_weights(int base, T t) {
     AxisW<T, ORDER> a;
-    const T fl = floor(d);
-    const T t = d - fl;
-    a.base = i + (int)fl;
+    a.base = base;
     if constexpr (ORDER == 3) {
         // cubic Lagrange basis on the nodes -1, 0, 1, 2
         const T tm1 = t - (T)1, tm2 = t - (T)2, tp1 = t + (T)1;
-        a.w[0] = -t * tm1 * tm2 * (T)(1.0 / 6.0);
-        a.w[1] = tp1 * tm1 * tm2 * (T)0.5;
-        a.w[2] = -tp1 * t * tm2 * (T)0.5;
-        a.w[3] = tp1 * t * tm1 * (T)(1.0 / 6.0);
+        const T u = t * tm1, w = tp1 * tm2;
+        a.w[0] = u * (tm2 * (T)(-1.0 / 6.0));
+        a.w[1] = w * (tm1 * (T)0.5);
+        a.w[2] = w * (t * (T)(-0.5));
+        a.w[3] = u * (tp1 * (T)(1.0 / 6.0));
     } else {
         a.w[0] = (T)1 - t;
         a.w[1] = t;
@@ -108,8 +108,30 @@ __device__ __forceinline__ AxisW<T, ORDER> axis_weights(int i, T d) {
     return a;
 }
 
+// t = d - floor(d) as a separately rounded subtraction.  Contracted with the
+// product that formed d into one fused operation, t would describe the
+// unrounded displacement, could leave [0, 1), and an integer displacement
+// would no longer give exact 0/1 weights.
+template <typename T>
+__device__ __forceinline__ T frac_part(T d, T fl) {
+#pragma clang fp contract(off)
+    return d - fl;
+}
+
+// Element i of an array through a 32-bit unsigned byte offset (every field
+// here is below 4 GiB), so loads and stores take the scalar-base plus
+// vector-offset address form; S is the storage type, T the arithmetic type.
+template <typename T, typename S>
+__device__ __forceinline__ T ld(const S *p, unsigned i) {
+    return load_as<T>(reinterpret_cast<const S *>(reinterpret_cast<const char *>(p) + i * (unsigned)sizeof(S)), 0);
+}
+template <typename S, typename T>
+__device__ __forceinline__ void st(S *p, unsigned i, T v) {
+    store_as(reinterpret_cast<S *>(reinterpret_cast<char *>(p) + i * (unsigned)sizeof(S)), 0, v);
+}
+
 template <int NP>
-using NodeOff = int[NP];
+using NodeOff = unsigned[NP];
 
 // Tensor-product contraction of NF quantities; get(offset, v) reads the NF
 // values at the combined node offset o1[p] + o2[q] + o3[r].
@@ -128,7 +150,7 @@ __device__ __forceinline__ void contract(const AxisW<T, ORDER> &a1, const AxisW<
         for (int f = 0; f < NF; ++f) ap[f] = 0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int row = o1[p] + o2[q];
+            const unsigned row = o1[p] + o2[q];
             T s[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) s[f] = 0;
@@ -191,13 +213,9 @@ __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const Ax
 // LDS layout of the staged box: NF <= 2 interleaved (the NF values of a node
 // are adjacent, one 4/8/16-byte read), NF = 3 one array per quantity.
 template <int NF>
-struct BoxLayout {
-    static constexpr bool AOS = NF <= 2;
-    template <int CAP>
-    static __device__ __forceinline__ int at(int k, int f) {
-        return AOS ? k * NF + f : f * CAP + k;
-    }
-};
+__device__ __forceinline__ int box_at(int k, int f, int cap) {
+    return NF <= 2 ? k * NF + f : f * cap + k;
+}
 
 // Workgroup index -> tile index, contiguous runs of tiles per XCD (workgroups
 // are dispatched round-robin over the 8 XCDs).
@@ -218,58 +236,31 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Generic tiled semi-Lagrangian sweep.  Op provides:
-//   void disp(int idx, T *d)            displacement of point idx (cells, 3 values)
-//   void stage(int gidx, T *v)          the NF gathered quantities at grid index gidx
-//   Pre pre(int idx)                    operands of the point update, loaded early
-//   void finish(int idx, const Pre &, const T *acc)  output of point idx
-template <typename T, int ORDER, int NF, int SHAPE, class Op>
-__global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
-    constexpr int kTZ = TileDims<SHAPE>::TZ, kTY = TileDims<SHAPE>::TY, kTX = TileDims<SHAPE>::TX;
-    constexpr int kPPT = kTX * kTY * kTZ / kSlThreads;  // points per thread
-    using A = AxisW<T, ORDER>;
-    constexpr int NP = A::NP, FIRST = A::FIRST;
-    constexpr int CAP = box_cap<T, NF>();
-    __shared__ __align__(16) T lds[NF * CAP];
-    __shared__ int box[6];
-    const int nb = g.tx * g.ty * g.tz;
-    const int tile = xcd_tile(blockIdx.x, nb);
-    const int bx = tile % g.tx, by = (tile / g.tx) % g.ty, bz = tile / (g.tx * g.ty);
-    // point p of this thread: tile-local linear index tid + 256 p, x3 fastest
-    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz0 = threadIdx.x / (kTX * kTY);
-    constexpr int kZStep = kSlThreads / (kTX * kTY);
-    const int i3 = bx * kTX + lx, i2 = by * kTY + ly;
-    if (threadIdx.x == 0) {
-        box[0] = box[1] = box[2] = INT_MAX;
-        box[3] = box[4] = box[5] = INT_MIN;
+// Point p of a thread in its tile: tile-local linear index tid + 256 p, x3
+// fastest.  Shared by the transport kernels and the box measurement, so both
+// see the same tiles.
+template <int SHAPE>
+struct TilePoints {
+    static constexpr int TZ = TileDims<SHAPE>::TZ, TY = TileDims<SHAPE>::TY, TX = TileDims<SHAPE>::TX;
+    static constexpr int PPT = TX * TY * TZ / kSlThreads;  // points per thread
+    static constexpr int ZSTEP = kSlThreads / (TX * TY);
+    int i1_0, i2, i3;  // grid index of point 0 (i1 advances by ZSTEP per point)
+    __device__ TilePoints(const PGrid &g, int tile) {
+        const int bx = tile % g.tx, by = (tile / g.tx) % g.ty, bz = tile / (g.tx * g.ty);
+        i3 = bx * TX + (int)threadIdx.x % TX;
+        i2 = by * TY + ((int)threadIdx.x / TX) % TY;
+        i1_0 = bz * TZ + (int)threadIdx.x / (TX * TY);
     }
-    // 1. displacements and weights of this thread's points; the operands of
-    //    the point update are loaded now so their latency hides under staging
-    A a1[kPPT], a2[kPPT], a3[kPPT];
-    typename Op::Pre pre[kPPT];
-    bool ok[kPPT];
-    int mn1 = INT_MAX, mn2 = INT_MAX, mn3 = INT_MAX, mx1 = INT_MIN, mx2 = INT_MIN, mx3 = INT_MIN;
-#pragma unroll
-    for (int p = 0; p < kPPT; ++p) {
-        const int i1 = bz * kTZ + lz0 + p * kZStep;
-        ok[p] = (i1 < g.n1) && (i2 < g.n2) && (i3 < g.n3);
-        if (ok[p]) {
-            const int idx = (i1 << g.s23) + (i2 << g.s3) + i3;
-            T d[3];
-            op.disp(idx, d);
-            pre[p] = op.pre(idx);
-            a1[p] = axis_weights<T, ORDER>(i1, d[0]);
-            a2[p] = axis_weights<T, ORDER>(i2, d[1]);
-            a3[p] = axis_weights<T, ORDER>(i3, d[2]);
-            mn1 = min(mn1, a1[p].base);
-            mx1 = max(mx1, a1[p].base);
-            mn2 = min(mn2, a2[p].base);
-            mx2 = max(mx2, a2[p].base);
-            mn3 = min(mn3, a3[p].base);
-            mx3 = max(mx3, a3[p].base);
-        }
+    __device__ int i1(int p) const { return i1_0 + p * ZSTEP; }
+    __device__ bool ok(const PGrid &g, int p) const { return i1(p) < g.n1 && i2 < g.n2 && i3 < g.n3; }
+    __device__ unsigned idx(const PGrid &g, int p) const {
+        return ((unsigned)i1(p) << g.s23) + ((unsigned)i2 << g.s3) + (unsigned)i3;
     }
-    __syncthreads();  // box initialised
+};
+
+// Block-wide bounding box of the base nodes (min, max per axis) into box[6];
+// returns false when the tile has no point inside the grid (uniform).
+__device__ __forceinline__ bool block_box(int *box, int mn1, int mn2, int mn3, int mx1, int mx2, int mx3) {
     mn1 = wave_min(mn1);
     mn2 = wave_min(mn2);
     mn3 = wave_min(mn3);
@@ -285,14 +276,70 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
         atomicMax(&box[5], mx3);
     }
     __syncthreads();
-    if (box[0] == INT_MAX) return;  // tile outside the grid (uniform across the block)
+    return box[0] != INT_MAX;
+}
+
+// Generic tiled semi-Lagrangian sweep.  Op provides:
+//   void disp(unsigned idx, T *d)       displacement of point idx (cells, 3 values)
+//   void stage(unsigned gidx, T *v)     the NF gathered quantities at grid index gidx
+//   Pre pre(unsigned idx)               operands of the point update, loaded early
+//   void finish(unsigned idx, const Pre &, const T *acc)  output of point idx
+// g.lds_cap is the dynamic LDS size of the launch in box nodes: tiles whose
+// stencil box is larger gather from global memory.  Only the fractional
+// positions and base nodes live across the staging phase; the weights are
+// formed point by point afterwards, which keeps the register count low.
+template <typename T, int ORDER, int NF, int SHAPE, class Op>
+__global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
+    using TP = TilePoints<SHAPE>;
+    constexpr int kPPT = TP::PPT;
+    using A = AxisW<T, ORDER>;
+    constexpr int NP = A::NP, FIRST = A::FIRST;
+    extern __shared__ __align__(16) unsigned char sl_smem[];
+    T *lds = reinterpret_cast<T *>(sl_smem);
+    __shared__ int box[6];
+    const TP tp(g, xcd_tile(blockIdx.x, g.tx * g.ty * g.tz));
+    if (threadIdx.x == 0) {
+        box[0] = box[1] = box[2] = INT_MAX;
+        box[3] = box[4] = box[5] = INT_MIN;
+    }
+    // 1. displacements -> base node and fractional position per axis; the
+    //    operands of the point update are loaded now so their latency hides
+    //    under the staging
+    T t1[kPPT], t2[kPPT], t3[kPPT];
+    int b1[kPPT], b2[kPPT], b3[kPPT];
+    typename Op::Pre pre[kPPT];
+    int mn1 = INT_MAX, mn2 = INT_MAX, mn3 = INT_MAX, mx1 = INT_MIN, mx2 = INT_MIN, mx3 = INT_MIN;
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+        if (tp.ok(g, p)) {
+            const unsigned idx = tp.idx(g, p);
+            T d[3];
+            op.disp(idx, d);
+            pre[p] = op.pre(idx);
+            const T f1 = floor(d[0]), f2 = floor(d[1]), f3 = floor(d[2]);
+            t1[p] = frac_part(d[0], f1);
+            t2[p] = frac_part(d[1], f2);
+            t3[p] = frac_part(d[2], f3);
+            b1[p] = tp.i1(p) + (int)f1;
+            b2[p] = tp.i2 + (int)f2;
+            b3[p] = tp.i3 + (int)f3;
+            mn1 = min(mn1, b1[p]);
+            mx1 = max(mx1, b1[p]);
+            mn2 = min(mn2, b2[p]);
+            mx2 = max(mx2, b2[p]);
+            mn3 = min(mn3, b3[p]);
+            mx3 = max(mx3, b3[p]);
+        }
+    }
+    __syncthreads();  // box initialised
+    if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
     // box of every stencil node, in unwrapped grid coordinates
     const int lo1 = box[0] + FIRST, lo2 = box[1] + FIRST, lo3 = box[2] + FIRST;
     const long long e1 = (long long)box[3] - box[0] + NP, e2 = (long long)box[4] - box[1] + NP,
                     e3 = (long long)box[5] - box[2] + NP;
     const long long vol = e1 * e2 * e3;
-    const bool staged = vol <= (long long)(g.lds_cap < CAP ? g.lds_cap : CAP);  // uniform across the block
-    if (staged) {
+    const int cap = g.lds_cap;
+    if (vol <= (long long)cap) {  // uniform across the block
         // 2. copy the box into LDS: flat index k = (z E2 + y) E3 + x; each thread
         //    walks k = tid, tid + 256, ... with (z, y, x) carried incrementally,
         //    kStageU loads in flight before the LDS stores
@@ -300,13 +347,14 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
         const int dz = kSlThreads / E23, rest = kSlThreads - dz * E23, dy = rest / E3, dx = rest - dy * E3;
         int z = (int)threadIdx.x / E23, y = ((int)threadIdx.x - z * E23) / E3;
         int x = (int)threadIdx.x - z * E23 - y * E3;
-        const int m1 = g.n1 - 1, m2 = g.n2 - 1, m3 = g.n3 - 1;
+        const unsigned m1 = g.n1 - 1, m2 = g.n2 - 1, m3 = g.n3 - 1;
         for (int k0 = threadIdx.x; k0 < V; k0 += kSlThreads * kStageU) {
             T v[kStageU][NF];
 #pragma unroll
             for (int u = 0; u < kStageU; ++u) {
                 if (k0 + u * kSlThreads < V) {
-                    const int gi = (((lo1 + z) & m1) << g.s23) + (((lo2 + y) & m2) << g.s3) + ((lo3 + x) & m3);
+                    const unsigned gi = (((unsigned)(lo1 + z) & m1) << g.s23) + (((unsigned)(lo2 + y) & m2) << g.s3) +
+                                        ((unsigned)(lo3 + x) & m3);
                     op.stage(gi, v[u]);
                 }
                 // advance (z, y, x) by kSlThreads elements
@@ -327,7 +375,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
                 const int k = k0 + u * kSlThreads;
                 if (k < V) {
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) lds[BoxLayout<NF>::template at<CAP>(k, f)] = v[u][f];
+                    for (int f = 0; f < NF; ++f) lds[box_at<NF>(k, f, cap)] = v[u][f];
                 }
             }
         }
@@ -335,39 +383,86 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
         // 3. stencils from LDS
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
-            if (!ok[p]) continue;
-            const int base = ((a1[p].base + FIRST - lo1) * E2 + (a2[p].base + FIRST - lo2)) * E3 +
-                             (a3[p].base + FIRST - lo3);
+            if (!tp.ok(g, p)) continue;
+            const A a1 = axis_weights<T, ORDER>(b1[p], t1[p]);
+            const A a2 = axis_weights<T, ORDER>(b2[p], t2[p]);
+            const A a3 = axis_weights<T, ORDER>(b3[p], t3[p]);
+            const int base = ((b1[p] + FIRST - lo1) * E2 + (b2[p] + FIRST - lo2)) * E3 + (b3[p] + FIRST - lo3);
             T acc[NF];
             contract_box<T, ORDER, NF>(
-                a1[p], a2[p], a3[p], base, E23, E3,
+                a1, a2, a3, base, E23, E3,
                 [&](int row, int r, T *v) {
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) v[f] = lds[BoxLayout<NF>::template at<CAP>(row + r, f)];
+                    for (int f = 0; f < NF; ++f) v[f] = lds[box_at<NF>(row + r, f, cap)];
                 },
                 acc);
-            const int idx = ((bz * kTZ + lz0 + p * kZStep) << g.s23) + (i2 << g.s3) + i3;
-            op.finish(idx, pre[p], acc);
+            op.finish(tp.idx(g, p), pre[p], acc);
         }
     } else {
-        // 3'. box too large for LDS: stencils straight from global memory
+        // 3'. box larger than the launch's LDS: stencils straight from global memory
 #pragma unroll
         for (int p = 0; p < kPPT; ++p) {
-            if (!ok[p]) continue;
-            int o1[NP], o2[NP], o3[NP];
+            if (!tp.ok(g, p)) continue;
+            const A a1 = axis_weights<T, ORDER>(b1[p], t1[p]);
+            const A a2 = axis_weights<T, ORDER>(b2[p], t2[p]);
+            const A a3 = axis_weights<T, ORDER>(b3[p], t3[p]);
+            unsigned o1[NP], o2[NP], o3[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                o1[k] = ((a1[p].base + FIRST + k) & (g.n1 - 1)) << g.s23;
-                o2[k] = ((a2[p].base + FIRST + k) & (g.n2 - 1)) << g.s3;
-                o3[k] = (a3[p].base + FIRST + k) & (g.n3 - 1);
+                o1[k] = ((unsigned)(b1[p] + FIRST + k) & (unsigned)(g.n1 - 1)) << g.s23;
+                o2[k] = ((unsigned)(b2[p] + FIRST + k) & (unsigned)(g.n2 - 1)) << g.s3;
+                o3[k] = (unsigned)(b3[p] + FIRST + k) & (unsigned)(g.n3 - 1);
             }
             T acc[NF];
             contract<T, ORDER, NF>(
-                a1[p], a2[p], a3[p], o1, o2, o3, [&](int off, T *v) { op.stage(off, v); }, acc);
-            const int idx = ((bz * kTZ + lz0 + p * kZStep) << g.s23) + (i2 << g.s3) + i3;
-            op.finish(idx, pre[p], acc);
+                a1, a2, a3, o1, o2, o3, [&](unsigned off, T *v) { op.stage(off, v); }, acc);
+            op.finish(tp.idx(g, p), pre[p], acc);
         }
     }
+}
+
+// Largest stencil box (nodes) over the tiles of k_sl for the displacement
+// d_a = (a_a D_a) b_a, the same expression the step operators evaluate:
+// one block per tile, atomic maximum into *out.
+template <typename T, int ORDER, int SHAPE>
+__global__ __launch_bounds__(kSlThreads) void k_box(PGrid g, const T *__restrict__ D, T a, T b1, T b2, T b3,
+                                                    unsigned *__restrict__ out) {
+    using TP = TilePoints<SHAPE>;
+    constexpr int NP = AxisW<T, ORDER>::NP;
+    __shared__ int box[6];
+    const TP tp(g, xcd_tile(blockIdx.x, g.tx * g.ty * g.tz));
+    if (threadIdx.x == 0) {
+        box[0] = box[1] = box[2] = INT_MAX;
+        box[3] = box[4] = box[5] = INT_MIN;
+    }
+    const unsigned N = (unsigned)g.N;
+    int mn1 = INT_MAX, mn2 = INT_MAX, mn3 = INT_MAX, mx1 = INT_MIN, mx2 = INT_MIN, mx3 = INT_MIN;
+#pragma unroll
+    for (int p = 0; p < TP::PPT; ++p) {
+        if (tp.ok(g, p)) {
+            const unsigned idx = tp.idx(g, p);
+            const int c1 = tp.i1(p) + (int)floor(a * ld<T>(D, idx) * b1);
+            const int c2 = tp.i2 + (int)floor(a * ld<T>(D, N + idx) * b2);
+            const int c3 = tp.i3 + (int)floor(a * ld<T>(D, 2 * N + idx) * b3);
+            mn1 = min(mn1, c1);
+            mx1 = max(mx1, c1);
+            mn2 = min(mn2, c2);
+            mx2 = max(mx2, c2);
+            mn3 = min(mn3, c3);
+            mx3 = max(mx3, c3);
+        }
+    }
+    __syncthreads();
+    if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
+    if (threadIdx.x == 0) {
+        const long long vol = ((long long)box[3] - box[0] + NP) * ((long long)box[4] - box[1] + NP) *
+                              ((long long)box[5] - box[2] + NP);
+        atomicMax(out, (unsigned)(vol < (long long)UINT_MAX ? vol : (long long)UINT_MAX));
+    }
+}
+
+__global__ void k_set_u32(unsigned *p, unsigned v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,27 +475,27 @@ template <typename T>
 struct DepartureOp {
     const T *__restrict__ v;
     T *__restrict__ out;
-    int N;
+    unsigned N;
     T sdt, ih1, ih2, ih3;
-    __device__ void disp(int i, T *d) const {
-        d[0] = sdt * v[i] * ih1;
-        d[1] = sdt * v[N + i] * ih2;
-        d[2] = sdt * v[2 * N + i] * ih3;
+    __device__ void disp(unsigned i, T *d) const {
+        d[0] = sdt * ld<T>(v, i) * ih1;
+        d[1] = sdt * ld<T>(v, N + i) * ih2;
+        d[2] = sdt * ld<T>(v, 2 * N + i) * ih3;
     }
-    __device__ void stage(int i, T *x) const {
-        x[0] = v[i];
-        x[1] = v[N + i];
-        x[2] = v[2 * N + i];
+    __device__ void stage(unsigned i, T *x) const {
+        x[0] = ld<T>(v, i);
+        x[1] = ld<T>(v, N + i);
+        x[2] = ld<T>(v, 2 * N + i);
     }
     struct Pre {
         T v1, v2, v3;
     };
-    __device__ Pre pre(int i) const { return Pre{v[i], v[N + i], v[2 * N + i]}; }
-    __device__ void finish(int i, const Pre &p, const T *a) const {
+    __device__ Pre pre(unsigned i) const { return Pre{ld<T>(v, i), ld<T>(v, N + i), ld<T>(v, 2 * N + i)}; }
+    __device__ void finish(unsigned i, const Pre &p, const T *a) const {
         const T h = (T)0.5 * sdt;
-        out[i] = h * (p.v1 + a[0]) * ih1;
-        out[N + i] = h * (p.v2 + a[1]) * ih2;
-        out[2 * N + i] = h * (p.v3 + a[2]) * ih3;
+        st(out, i, h * (p.v1 + a[0]) * ih1);
+        st(out, N + i, h * (p.v2 + a[1]) * ih2);
+        st(out, 2 * N + i, h * (p.v3 + a[2]) * ih3);
     }
 };
 
@@ -410,16 +505,16 @@ struct InterpOp {
     const SI *__restrict__ f;
     const T *__restrict__ D;
     SO *__restrict__ out;
-    int N;
-    __device__ void disp(int i, T *d) const {
-        d[0] = D[i];
-        d[1] = D[N + i];
-        d[2] = D[2 * N + i];
+    unsigned N;
+    __device__ void disp(unsigned i, T *d) const {
+        d[0] = ld<T>(D, i);
+        d[1] = ld<T>(D, N + i);
+        d[2] = ld<T>(D, 2 * N + i);
     }
-    __device__ void stage(int i, T *x) const { x[0] = load_as<T>(f, i); }
+    __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(f, i); }
     struct Pre {};
-    __device__ Pre pre(int) const { return Pre{}; }
-    __device__ void finish(int i, const Pre &, const T *a) const { store_as(out, i, a[0]); }
+    __device__ Pre pre(unsigned) const { return Pre{}; }
+    __device__ void finish(unsigned i, const Pre &, const T *a) const { st(out, i, a[0]); }
 };
 
 // Adjoint step: lambda^j = L + dt/2 (S + (L + dt S) d), L = I[lambda^{j+1}](Y),
@@ -430,31 +525,33 @@ struct AdjointOp {
     const T *__restrict__ dv;
     const T *__restrict__ Y;
     SL *__restrict__ lout;
-    int N;
+    unsigned N;
     T dt;
-    __device__ void disp(int i, T *d) const {
-        d[0] = Y[i];
-        d[1] = Y[N + i];
-        d[2] = Y[2 * N + i];
+    __device__ void disp(unsigned i, T *d) const {
+        d[0] = ld<T>(Y, i);
+        d[1] = ld<T>(Y, N + i);
+        d[2] = ld<T>(Y, 2 * N + i);
     }
-    __device__ void stage(int i, T *x) const {
-        const T l = load_as<T>(lin, i);
+    __device__ void stage(unsigned i, T *x) const {
+        const T l = ld<T>(lin, i);
         x[0] = l;
-        x[1] = l * dv[i];
+        x[1] = l * ld<T>(dv, i);
     }
     struct Pre {
         T d;
     };
-    __device__ Pre pre(int i) const { return Pre{dv[i]}; }
-    __device__ void finish(int i, const Pre &p, const T *a) const {
+    __device__ Pre pre(unsigned i) const { return Pre{ld<T>(dv, i)}; }
+    __device__ T value(const Pre &p, const T *a) const {
         const T L = a[0], S = a[1];
-        store_as(lout, i, L + (T)0.5 * dt * (S + (L + dt * S) * p.d));
+        return L + (T)0.5 * dt * (S + (L + dt * S) * p.d);
     }
+    __device__ void finish(unsigned i, const Pre &p, const T *a) const { st(lout, i, value(p, a)); }
 };
 
 // Last adjoint step (j = 0) fused with the time integral: lambda^0 as above,
 // then b = sum_j a_j lambda^j grad m^j from lambda^0 (in registers) and the
 // stored lambda^1..nt; the history reads overlap the gather-bound step.
+// lam and gm point at slice 0; slice j starts j N (j 3N) elements further.
 template <typename T, typename SL>
 struct AdjointAccumOp {
     AdjointOp<T, SL> step;
@@ -463,26 +560,27 @@ struct AdjointAccumOp {
     T *__restrict__ b;
     int nt;
     T a_end, a_mid;
-    __device__ void disp(int i, T *d) const { step.disp(i, d); }
-    __device__ void stage(int i, T *x) const { step.stage(i, x); }
+    __device__ void disp(unsigned i, T *d) const { step.disp(i, d); }
+    __device__ void stage(unsigned i, T *x) const { step.stage(i, x); }
     using Pre = typename AdjointOp<T, SL>::Pre;
-    __device__ Pre pre(int i) const { return step.pre(i); }
-    __device__ void finish(int i, const Pre &p, const T *a) const {
-        const int N = step.N;
-        const T L = a[0], S = a[1];
-        const T l0 = L + (T)0.5 * step.dt * (S + (L + step.dt * S) * p.d);
-        T al = a_end * l0;
-        T b1 = al * gm[i], b2 = al * gm[N + i], b3 = al * gm[2 * N + i];
+    __device__ Pre pre(unsigned i) const { return step.pre(i); }
+    __device__ void finish(unsigned i, const Pre &p, const T *a) const {
+        const unsigned N = step.N;
+        T al = a_end * step.value(p, a);
+        T b1 = al * ld<T>(gm, i), b2 = al * ld<T>(gm, N + i), b3 = al * ld<T>(gm, 2 * N + i);
+        const SL *l = lam;
+        const T *g = gm;
         for (int j = 1; j <= nt; ++j) {
-            al = (j == nt ? a_end : a_mid) * load_as<T>(lam, (long long)j * N + i);
-            const T *g = gm + 3 * j * N;
-            b1 += al * g[i];
-            b2 += al * g[N + i];
-            b3 += al * g[2 * N + i];
+            l += N;
+            g += 3 * (size_t)N;
+            al = (j == nt ? a_end : a_mid) * ld<T>(l, i);
+            b1 += al * ld<T>(g, i);
+            b2 += al * ld<T>(g, N + i);
+            b3 += al * ld<T>(g, 2 * N + i);
         }
-        b[i] = b1;
-        b[N + i] = b2;
-        b[2 * N + i] = b3;
+        st(b, i, b1);
+        st(b, N + i, b2);
+        st(b, 2 * N + i, b3);
     }
 };
 
@@ -496,21 +594,22 @@ struct IncStateOp {
     const T *__restrict__ gm;
     const T *__restrict__ vt;
     SQ *__restrict__ qout;
-    int N;
+    unsigned N;
     T coef, sign;
-    __device__ void disp(int i, T *d) const {
-        d[0] = X[i];
-        d[1] = X[N + i];
-        d[2] = X[2 * N + i];
+    __device__ void disp(unsigned i, T *d) const {
+        d[0] = ld<T>(X, i);
+        d[1] = ld<T>(X, N + i);
+        d[2] = ld<T>(X, 2 * N + i);
     }
-    __device__ void stage(int i, T *x) const { x[0] = load_as<T>(qin, i); }
+    __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(qin, i); }
     struct Pre {
         T f;
     };
-    __device__ Pre pre(int i) const {
-        return Pre{-(gm[i] * vt[i] + gm[N + i] * vt[N + i] + gm[2 * N + i] * vt[2 * N + i])};
+    __device__ Pre pre(unsigned i) const {
+        return Pre{-(ld<T>(gm, i) * ld<T>(vt, i) + ld<T>(gm, N + i) * ld<T>(vt, N + i) +
+                     ld<T>(gm, 2 * N + i) * ld<T>(vt, 2 * N + i))};
     }
-    __device__ void finish(int i, const Pre &p, const T *a) const { store_as(qout, i, sign * (a[0] + coef * p.f)); }
+    __device__ void finish(unsigned i, const Pre &p, const T *a) const { st(qout, i, sign * (a[0] + coef * p.f)); }
 };
 
 // Final condition of the adjoint: lambda(1) = mR - m(1).
@@ -534,17 +633,28 @@ __global__ __launch_bounds__(kSlThreads) void k_incstate_init(long long N, T hdt
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n) { return (unsigned)((n + kSlThreads - 1) / kSlThreads); }
 
+// LDS nodes of one launch: the largest box of the displacement field (box),
+// at most 64 KB, and none when staging is switched off (g.lds_cap = 0).
+template <typename T, int NF>
+static int launch_cap(const PGrid &g, int box) {
+    const int hard = kLdsBytes / (NF * (int)sizeof(T));
+    int cap = box < hard ? box : hard;
+    return cap < g.lds_cap ? cap : g.lds_cap;
+}
+
 template <typename T, int NF, int SHAPE, class Op>
 static void launch_sl_shape(const PGrid &g, int order, const Op &op, hipStream_t s) {
     const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
+    const size_t lds = (size_t)g.lds_cap * NF * sizeof(T);
     if (order == 3)
-        hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), 0, s, g, op);
+        hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op);
     else
-        hipLaunchKernelGGL((k_sl<T, 1, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), 0, s, g, op);
+        hipLaunchKernelGGL((k_sl<T, 1, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op);
 }
 
 template <typename T, int NF, class Op>
-static void launch_sl(const PGrid &g, int order, const Op &op, hipStream_t s) {
+static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) {
+    g.lds_cap = launch_cap<T, NF>(g, box);
     switch (g.shape) {
         case TILE_8x8x16: launch_sl_shape<T, NF, TILE_8x8x16>(g, order, op, s); break;
         case TILE_8x16x16: launch_sl_shape<T, NF, TILE_8x16x16>(g, order, op, s); break;
@@ -553,20 +663,46 @@ static void launch_sl(const PGrid &g, int order, const Op &op, hipStream_t s) {
 }
 
 template <typename T>
-void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *disp, hipStream_t s) {
+void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double b[3], unsigned *out,
+                   hipStream_t s) {
+    const PGrid g = pgrid(gg);
+    HookScope hs(K_VECTOR, 3.0 * sizeof(T) * g.N);
+    const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, out, 0u);
+#define MIREG_BOX(ORD, SH)                                                                                     \
+    hipLaunchKernelGGL((k_box<T, ORD, SH>), dim3(nb), dim3(kSlThreads), 0, s, g, D, (T)a, (T)b[0], (T)b[1], \
+                       (T)b[2], out)
+    if (order == 3) {
+        switch (g.shape) {
+            case TILE_8x8x16: MIREG_BOX(3, TILE_8x8x16); break;
+            case TILE_8x16x16: MIREG_BOX(3, TILE_8x16x16); break;
+            default: MIREG_BOX(3, TILE_4x8x32); break;
+        }
+    } else {
+        switch (g.shape) {
+            case TILE_8x8x16: MIREG_BOX(1, TILE_8x8x16); break;
+            case TILE_8x16x16: MIREG_BOX(1, TILE_8x16x16); break;
+            default: MIREG_BOX(1, TILE_4x8x32); break;
+        }
+    }
+#undef MIREG_BOX
+}
+
+template <typename T>
+void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *disp, int box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_DEPARTURE, 6.0 * g.N * sizeof(T));
-    const double two_pi = 6.283185307179586476925;
-    DepartureOp<T> op{v, disp, (int)g.N, (T)(sign * dt), (T)(g.n1 / two_pi), (T)(g.n2 / two_pi), (T)(g.n3 / two_pi)};
-    launch_sl<T, 3>(g, order, op, s);
+    DepartureOp<T> op{v, disp, (unsigned)g.N, (T)(sign * dt), (T)departure_ih(gg, 0), (T)departure_ih(gg, 1),
+                      (T)departure_ih(gg, 2)};
+    launch_sl<T, 3>(g, order, box, op, s);
 }
 
 template <typename T, typename SI, typename SO>
-void interp_field(const Grid &gg, int order, const SI *f, const T *disp, SO *out, hipStream_t s) {
+void interp_field(const Grid &gg, int order, const SI *f, const T *disp, SO *out, int box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_INTERP, (3.0 * sizeof(T) + sizeof(SI) + sizeof(SO)) * g.N);
-    InterpOp<T, SI, SO> op{f, disp, out, (int)g.N};
-    launch_sl<T, 1>(g, order, op, s);
+    InterpOp<T, SI, SO> op{f, disp, out, (unsigned)g.N};
+    launch_sl<T, 1>(g, order, box, op, s);
 }
 
 template <typename T, typename S>
@@ -577,22 +713,22 @@ void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s)
 
 template <typename T, typename S>
 void adjoint_step(const Grid &gg, int order, double dt, const S *lam_in, const T *d, const T *Y, S *lam_out,
-                  hipStream_t s) {
+                  int box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_ADJ_STEP, (4.0 * sizeof(T) + 2.0 * sizeof(S)) * g.N);
-    AdjointOp<T, S> op{lam_in, d, Y, lam_out, (int)g.N, (T)dt};
-    launch_sl<T, 2>(g, order, op, s);
+    AdjointOp<T, S> op{lam_in, d, Y, lam_out, (unsigned)g.N, (T)dt};
+    launch_sl<T, 2>(g, order, box, op, s);
 }
 
 template <typename T, typename S>
 void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const S *lam, const T *d,
-                             const T *Y, const T *gradm, T *b, hipStream_t s) {
+                             const T *Y, const T *gradm, T *b, int box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_ADJ_ACC, ((4.0 + 3.0 * (nt + 1) + 3.0) * sizeof(T) + (double)nt * sizeof(S)) * g.N);
-    const long long N = g.N;
-    AdjointOp<T, S> step{lam + N, d, Y, nullptr, (int)N, (T)dt};
+    const unsigned N = (unsigned)g.N;
+    AdjointOp<T, S> step{lam + N, d, Y, nullptr, N, (T)dt};
     AdjointAccumOp<T, S> op{step, lam, gradm, b, nt, (T)(0.5 * dt), (T)dt};
-    launch_sl<T, 2>(g, order, op, s);
+    launch_sl<T, 2>(g, order, box, op, s);
 }
 
 template <typename T, typename S>
@@ -604,28 +740,33 @@ void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q,
 
 template <typename T, typename S>
 void incstate_step(const Grid &gg, int order, double coef, double sign, const S *q_in, const T *X,
-                   const T *gradm_next, const T *vt, S *q_out, hipStream_t s) {
+                   const T *gradm_next, const T *vt, S *q_out, int box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_INC_STEP, 9.0 * sizeof(T) * g.N + 2.0 * sizeof(S) * g.N);
-    IncStateOp<T, S> op{q_in, X, gradm_next, vt, q_out, (int)g.N, (T)coef, (T)sign};
-    launch_sl<T, 1>(g, order, op, s);
+    IncStateOp<T, S> op{q_in, X, gradm_next, vt, q_out, (unsigned)g.N, (T)coef, (T)sign};
+    launch_sl<T, 1>(g, order, box, op, s);
 }
 
-template void departure<float>(const Grid &, int, int, double, const float *, float *, hipStream_t);
-template void departure<double>(const Grid &, int, int, double, const double *, double *, hipStream_t);
+#define MIREG_INST_T(T)                                                                                   \
+    template void departure<T>(const Grid &, int, int, double, const T *, T *, int, hipStream_t);        \
+    template void interp_field<T, T, T>(const Grid &, int, const T *, const T *, T *, int, hipStream_t); \
+    template void sl_box_volume<T>(const Grid &, int, const T *, double, const double *, unsigned *,     \
+                                   hipStream_t);
 #define MIREG_INST(T, S)                                                                                  \
-    template void interp_field<T, S, S>(const Grid &, int, const S *, const T *, S *, hipStream_t);       \
     template void adjoint_init<T, S>(const Grid &, const T *, const T *, S *, hipStream_t);              \
     template void adjoint_step<T, S>(const Grid &, int, double, const S *, const T *, const T *, S *,    \
-                                     hipStream_t);                                                        \
+                                     int, hipStream_t);                                                   \
     template void adjoint_step_accumulate<T, S>(const Grid &, int, double, int, const S *, const T *,    \
-                                                const T *, const T *, T *, hipStream_t);                 \
+                                                const T *, const T *, T *, int, hipStream_t);            \
     template void incstate_init<T, S>(const Grid &, double, const T *, const T *, S *, hipStream_t);     \
     template void incstate_step<T, S>(const Grid &, int, double, double, const S *, const T *, const T *, \
-                                      const T *, S *, hipStream_t);
+                                      const T *, S *, int, hipStream_t);
+MIREG_INST_T(float)
+MIREG_INST_T(double)
 MIREG_INST(float, float)
 MIREG_INST(double, double)
 MIREG_INST(float, __half)
 #undef MIREG_INST
+#undef MIREG_INST_T
 
 }  // namespace mireg
