@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmireg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["fft.hip", "transport.hip", "vec.hip", "mireg.cpp"]
+SOURCES = ["fft.hip", "transport.hip", "vec.hip", "net.hip", "mireg.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MIREG_ARCH", "gfx950")
 

@@ -1,5 +1,5 @@
-"""The C-ABI library loads and exports every function include/mireg.h
-declares (no GPU needed: nothing is called)."""
+"""The C-ABI library loads and exports every function include/mireg.h and
+include/mireg_net.h declare (no GPU needed: nothing is called)."""
 import ctypes
 import os
 import re
@@ -8,11 +8,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mireg.h")
+NET_HEADER = os.path.join(ROOT, "include", "mireg_net.h")
 LIB = os.path.join(ROOT, "paper_1808_04487_amd", "libmireg.so")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(mireg_[a-z0-9_]+)\s*\(", text)))
 
@@ -30,10 +31,17 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
         pytest.skip("libmireg.so not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(LIB)
-    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    missing = [n for n in declared_functions() + declared_functions(NET_HEADER) if not hasattr(lib, n)]
     assert not missing, missing
 
 
 def test_binding_signatures_cover_the_header():
     from paper_1808_04487_amd import mireg
     assert sorted(mireg.SIGNATURES) == declared_functions()
+
+
+def test_network_binding_signatures_cover_its_header():
+    from paper_1808_04487_amd import warmstart
+    names = declared_functions(NET_HEADER)
+    assert "mireg_net_train_step" in names and "mireg_net_forward" in names
+    assert sorted(warmstart.SIGNATURES) == names
