@@ -19,6 +19,9 @@ kernel's HBM roofline are reported beside it, and the FP64 CPU oracle is
 timed on a bounded sample of the same recipe as the CPU baseline.  The
 FP16-storage variant (FP32 arithmetic, adjoint and incremental fields held in
 FP16) is timed on the same inputs and reported in "precision_variant".
+"warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
+trained network's prediction (paper_1808_04487_amd/weights) to the same
+absolute gradient tolerance.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -47,6 +50,8 @@ def parse_args():
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-variant", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--warm-pairs", type=int, default=16, help="held-out pairs of the warm-start comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, run a fill and a multiply over 1 GiB (known "
                          "traffic) as the reference for memory-traffic counters")
@@ -183,6 +188,45 @@ def precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, plain):
     }
 
 
+def warm_start_eval(args, torch):
+    """Plain vs warm-started GN-Krylov solves of held-out 128^3 pairs (seeds
+    3000000 on, disjoint from training and from the recorded evaluation)."""
+    from paper_1808_04487_amd import warmstart
+
+    path = os.path.join(warmstart.WEIGHTS_DIR, "warmstart_128.npz")
+    net = warmstart.WarmStartNet.load(path)
+    ctx = warmstart.registration_context(net.n)
+    mT, mR, _, _, _ = warmstart.make_pair(net, ctx, 2999999, solve=False)
+    warmstart.solve_pair(ctx, mT, mR, net)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    for _ in range(5):
+        net.forward(mT, mR)
+    e1.record(net.stream)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    rows = []
+    for s in range(3000000, 3000000 + args.warm_pairs):
+        mT, mR, _, _, _ = warmstart.make_pair(net, ctx, s, solve=False)
+        r = warmstart.solve_pair(ctx, mT, mR, net)
+        (p, tp), (w, tw, used) = r["plain"], r["warm"]
+        rows.append((p["gn_iters"], w["gn_iters"], p["matvecs"], w["matvecs"], tp, tw, p["mismatch_rel"],
+                     w["mismatch_rel"], float(used)))
+    ctx.close()
+    net.close()
+    import numpy as np
+    a = np.array(rows)
+    m = a.mean(axis=0)
+    log(args, "warm start: plain %.2f GN %.1f ms, warm %.2f GN %.1f ms" % (m[0], 1e3 * m[4], m[1], 1e3 * m[5]))
+    return {"workload": "held-out 128^3 Voronoi pairs, velocity amplitude U[0.05, 0.15] 2 pi, H1-div "
+                        "beta_v=5e-3, same absolute gradient tolerance (5e-2 |g(0)|)",
+            "pairs": len(rows), "plain_time_to_tol_s": round(m[4], 5), "warm_time_to_tol_s": round(m[5], 5),
+            "speedup": round(m[4] / m[5], 3), "plain_gn_iters": round(m[0], 3), "warm_gn_iters": round(m[1], 3),
+            "plain_matvecs": round(m[2], 2), "warm_matvecs": round(m[3], 2),
+            "plain_mismatch_rel": round(m[6], 6), "warm_mismatch_rel": round(m[7], 6),
+            "prediction_used_fraction": round(m[8], 3), "network_forward_ms": round(fwd_ms, 3)}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -253,6 +297,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5)}
 
+    warm = None
+    if not args.no_warm_start:
+        log(args, "warm-start comparison")
+        warm = warm_start_eval(args, torch)
+
     prec = None
     if not args.no_precision_variant:
         log(args, "FP16-storage variant")
@@ -290,6 +339,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "precision_variant": prec,
+        "warm_start": warm,
         "kernels": kernels,
     }
     ctx.close()
