@@ -72,18 +72,22 @@ class Report:
         self.mismatch_rel = 0.0
         self.gnorm0 = self.gnorm = self.gnorm_rel = 0.0
         self.seconds = 0.0
+        self.coarse_matvecs = 0
         self.history = []
 
     def as_dict(self):
         return {k: getattr(self, k) for k in (
             "status", "gn_iters", "matvecs", "pde_solves", "pcg_iters", "ls_trials", "J0", "J",
-            "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel", "seconds")}
+            "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel", "seconds", "coarse_matvecs")}
 
 
 def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
-             armijo_c1=1e-4, max_ls=10):
+             armijo_c1=1e-4, max_ls=10, precond=None):
     """Inexact GN-Krylov solve for the registration problem ``reg``
-    (an ``oracle.core.Registration``) from the initial velocity v0."""
+    (an ``oracle.core.Registration``) from the initial velocity v0.
+    ``precond``: None for the spectral preconditioner, else an object with
+    ``apply(r, eps_h)`` (and a ``coarse_matvecs`` count) such as
+    ``oracle.twolevel.TwoLevel``, applied at the current velocity."""
     t0 = time.perf_counter()
     g_ = reg.g
     inner = g_.inner
@@ -110,7 +114,8 @@ def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
             rep.status = MAXIT
             break
         eps_h = min(0.5, math.sqrt(gnorm / g0))
-        vt, its, _ = pcg(reg.hessian_matvec, reg.precond, -grad, eps_h, max_pcg, inner)
+        minv = reg.precond if precond is None else (lambda r, e=eps_h: precond.apply(r, e))
+        vt, its, _ = pcg(reg.hessian_matvec, minv, -grad, eps_h, max_pcg, inner)
         rep.matvecs += its
         rep.pcg_iters += its
         rep.pde_solves += 2 * its
@@ -136,6 +141,7 @@ def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
         rep.pde_solves += 1
         k += 1
     rep.gn_iters = k
+    rep.coarse_matvecs = precond.coarse_matvecs if precond is not None else 0
     rep.J = J
     rep.gnorm = math.sqrt(inner(grad, grad))
     rep.gnorm_rel = rep.gnorm / g0 if g0 > 0 else 0.0
