@@ -19,6 +19,8 @@ kernel's HBM roofline are reported beside it, and the FP64 CPU oracle is
 timed on a bounded sample of the same recipe as the CPU baseline.  The
 FP16-storage variant (FP32 arithmetic, adjoint and incremental fields held in
 FP16) is timed on the same inputs and reported in "precision_variant".
+"two_level" repeats the timed solves with the two-level coarse-grid
+preconditioner (coarse grid 128^3, nested CG to 0.1 times the PCG tolerance).
 "warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
 trained network's prediction (paper_1808_04487_amd/weights) to the same
 absolute gradient tolerance.
@@ -51,6 +53,7 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-variant", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--no-two-level", action="store_true")
     ap.add_argument("--warm-pairs", type=int, default=16, help="held-out pairs of the warm-start comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, run a fill and a multiply over 1 GiB (known "
@@ -297,6 +300,19 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5)}
 
+    two = None
+    if not args.no_two_level:
+        log(args, "two-level preconditioner")
+        ctx.set_velocity(torch.zeros_like(v_true))
+        ctx.set_precond("two_level", kappa=0.1, max_inner=50)
+        treps, twall = timed_solves(args, ctx, torch, 1, args.steps)
+        ctx.set_precond("spectral")
+        tr = treps[-1]
+        two = {"kappa": 0.1, "coarse_grid": [n // 2] * 3, "time_to_tol_s": round(twall / max(1, args.steps), 4),
+               "speedup_vs_spectral": round(wall / twall, 3),
+               "solve": {k: tr[k] for k in ("status", "gn_iters", "matvecs", "coarse_matvecs", "mismatch_rel",
+                                            "gnorm_rel")}}
+
     warm = None
     if not args.no_warm_start:
         log(args, "warm-start comparison")
@@ -339,6 +355,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "precision_variant": prec,
+        "two_level": two,
         "warm_start": warm,
         "kernels": kernels,
     }

@@ -106,6 +106,7 @@ typedef struct {
     double mismatch_rel;/* ||m(1) - mR||^2 / ||mT - mR||^2 at the final velocity */
     double gnorm0, gnorm, gnorm_rel;
     double seconds;     /* wall time of the solve */
+    int coarse_matvecs; /* coarse-grid Hessian matvecs of the two-level preconditioner */
 } mireg_report;
 
 typedef struct mireg_ctx mireg_ctx;
@@ -150,9 +151,25 @@ int mireg_gradient(mireg_ctx *ctx, void *g, double *gnorm);
  * synchronisation. */
 int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt);
 
-/* Spectral preconditioner z = (beta_v A)^{-1} r with the zero singular value
- * of the regulariser set to one (Sec. 2.3.3).  r and z may alias. */
+/* Preconditioner z = M^{-1} r (see mireg_set_precond; by default the
+ * spectral (beta_v A)^{-1} with the zero singular value of the regulariser
+ * set to one, Sec. 2.3.3).  r and z may alias. */
 int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z);
+
+/* Preconditioner of PCG and of mireg_precond_apply (Sec. 2.3.3):
+ *  MIREG_PC_SPECTRAL: M^{-1} = (beta_v A)^{-1} (the default);
+ *  MIREG_PC_TWO_LEVEL: M^{-1} = Hreg^{-1/2} P^{-1} Hreg^{-1/2}, Hreg = beta_v A
+ *    (symbol 1 at k = 0), where P approximates Hreg^{-1/2} H Hreg^{-1/2}: the
+ *    modes with |k_a| < n_a/4 (F_L) are restricted spectrally to the n/2 grid
+ *    (Q_R), solved there with CG to the relative tolerance kappa * eps_H on
+ *    the coarse operator built from the restricted images and velocity
+ *    (direct, non-Galerkin), and prolongated back (Q_P); the other modes
+ *    (F_H) pass unchanged.  eps_H is the tolerance of the enclosing PCG (1
+ *    for mireg_precond_apply); max_inner caps the coarse iterations.  The
+ *    coarse context (n/2 per axis, every axis >= 16) is created on first use.
+ * kappa in (0, 1) (the paper: 0.1).  MIREG_E_SHAPE if the grid is too small. */
+typedef enum { MIREG_PC_SPECTRAL = 0, MIREG_PC_TWO_LEVEL = 1 } mireg_precond_kind;
+int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
 
 /* PCG (Algorithm "inner iteration") for H x = rhs at the current v, x0 = 0;
  * stops when ||r|| <= rtol ||rhs||, after maxit iterations, or on

@@ -163,6 +163,14 @@ __device__ __forceinline__ T scalar_symbol(const Mode<T> &m, const OpConst<T> &o
         case SYM_LAP: return -ksq(m);
         case SYM_GAUSS:
             return exp(-(oc.gs1 * m.k1 * m.k1 + oc.gs2 * m.k2 * m.k2 + oc.gs3 * m.k3 * m.k3));
+        case SYM_AINV_SQRT: {
+            const T s = oc.alpha * reg_symbol(m, oc.reg);
+            return ksq(m) == (T)0 ? (T)1 : (T)1 / sqrt(s);
+        }
+        case SYM_HIGHPASS: {
+            const bool low = 4 * fabs(m.k1) < (T)oc.n1 && 4 * fabs(m.k2) < (T)oc.n2 && 4 * fabs(m.k3) < (T)oc.n3;
+            return low ? (T)0 : (T)1;
+        }
         default: return (T)1;
     }
 }
@@ -422,6 +430,73 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
     launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
     launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
 }
+
+// Destination half spectrum from the source one (both x1, x2, x3
+// transformed): kept modes |k_a| < c_a scaled by `scale`, zero elsewhere.
+template <typename T>
+__global__ void k_mode_copy(int n1s, int n2s, int k3s, int n1d, int n2d, int k3d, int c1, int c2, int c3,
+                            long long NSs, long long NSd, T factor, const cx<T> *__restrict__ src,
+                            cx<T> *__restrict__ dst) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NSd) return;
+    const int f = blockIdx.y;
+    const int i3 = (int)(j % k3d), i2 = (int)((j / k3d) % n2d), i1 = (int)(j / ((long long)k3d * n2d));
+    const int w1 = wavenumber(i1, n1d), w2 = wavenumber(i2, n2d), w3 = i3;
+    cx<T> v = make_cx<T>(0, 0);
+    if (abs(w1) < c1 && abs(w2) < c2 && w3 < c3) {
+        const int s1 = w1 >= 0 ? w1 : w1 + n1s, s2 = w2 >= 0 ? w2 : w2 + n2s;
+        v = scale(src[(long long)f * NSs + ((long long)s1 * n2s + s2) * k3s + w3], factor);
+    }
+    dst[(long long)f * NSd + j] = v;
+}
+
+// Full x1 transform of nf half spectra in place (a strided column pass).
+template <typename T, int DIR>
+static void launch_x1_fft(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipStream_t s) {
+    const long long Q = (long long)g.n2 * g.k3;
+    HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
+#define MIREG_L(L)                                                                                          \
+    {                                                                                                       \
+        constexpr int W = FftShape<T, L, 0, kColThreads>::W;                                                \
+        dim3 grid((unsigned)((Q + W - 1) / W), nf);                                                         \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kColThreads), 0, s, f, Q, Q, 0LL, Q, tw);  \
+    }
+    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T>
+void spectral_resample(const Grid &gs, const Grid &gd, int nf, const T *const *in, T *const *out, cx<T> *spec_s,
+                       cx<T> *spec_d, const Twiddles<T> &tws, const Twiddles<T> &twd, hipStream_t s) {
+    FieldPtrs fin{}, fs{}, fd{}, fout{};
+    for (int i = 0; i < nf; ++i) {
+        fin.p[i] = const_cast<T *>(in[i]);
+        fs.p[i] = spec_s + (long long)i * gs.NS;
+        fd.p[i] = spec_d + (long long)i * gd.NS;
+        fout.p[i] = out[i];
+    }
+    launch_r2c<T>(gs, fin, fs, nf, tws.t[2], s);
+    launch_x2<T, -1>(gs, fs, nf, tws.t[1], s);
+    launch_x1_fft<T, -1>(gs, fs, nf, tws.t[0], s);
+    const int c1 = (gs.n1 < gd.n1 ? gs.n1 : gd.n1) / 2, c2 = (gs.n2 < gd.n2 ? gs.n2 : gd.n2) / 2,
+              c3 = (gs.n3 < gd.n3 ? gs.n3 : gd.n3) / 2;
+    const T scale = (T)(1.0 / ((double)gs.n1 * gs.n2 * gs.n3));
+    {
+        HookScope hs(K_VECTOR, (double)nf * 2.0 * sizeof(T) * 2 * gd.NS);
+        dim3 grid((unsigned)((gd.NS + 255) / 256), nf);
+        hipLaunchKernelGGL((k_mode_copy<T>), grid, dim3(256), 0, s, gs.n1, gs.n2, gs.k3, gd.n1, gd.n2, gd.k3, c1, c2, c3,
+                           gs.NS, gd.NS, scale, spec_s, spec_d);
+    }
+    launch_x1_fft<T, +1>(gd, fd, nf, twd.t[0], s);
+    launch_x2<T, +1>(gd, fd, nf, twd.t[1], s);
+    launch_c2r<T>(gd, fd, fout, nf, twd.t[2], s);
+}
+template void spectral_resample<float>(const Grid &, const Grid &, int, const float *const *, float *const *,
+                                       cx<float> *, cx<float> *, const Twiddles<float> &, const Twiddles<float> &,
+                                       hipStream_t);
+template void spectral_resample<double>(const Grid &, const Grid &, int, const double *const *, double *const *,
+                                        cx<double> *, cx<double> *, const Twiddles<double> &,
+                                        const Twiddles<double> &, hipStream_t);
 
 template void spectral_apply<float>(const Grid &, int, int, int, const void *const *, float *const *,
                                     cx<float> *, const Twiddles<float> &, const SpecParams &,

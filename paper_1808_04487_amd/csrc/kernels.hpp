@@ -43,7 +43,10 @@ enum SpecKind {
     SPEC_PROJ = 3,   // 3 -> 3, K
     SPEC_TAIL = 4    // 6 -> 3, alpha A u + K b (u in slots 0..2, b in 3..5)
 };
-enum SymKind { SYM_ID = 0, SYM_A = 1, SYM_AINV = 2, SYM_LAP = 3, SYM_GAUSS = 4 };
+// SYM_AINV_SQRT: (alpha a(k))^(-1/2), 1 at k = 0; SYM_HIGHPASS: 0 on the modes
+// a grid of half the size resolves below its Nyquist (|k_a| < n_a / 4 on every
+// axis), 1 elsewhere.
+enum SymKind { SYM_ID = 0, SYM_A = 1, SYM_AINV = 2, SYM_LAP = 3, SYM_GAUSS = 4, SYM_AINV_SQRT = 5, SYM_HIGHPASS = 6 };
 
 struct SpecParams {
     int sym;        // SymKind for SPEC_SCALE
@@ -66,6 +69,15 @@ struct Twiddles {
 template <typename T>
 void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *const *in, T *const *out,
                     cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+
+// Spectral resampling between two grids (each axis the same or half/double
+// the size): out = the trigonometric interpolant of in, truncated to the
+// modes both grids resolve below their Nyquist (|k_a| < min(n_a, m_a) / 2),
+// sampled on the destination grid.  spec_s / spec_d hold nf half spectra of
+// the source / destination grid; tws / twd are their twiddle tables.
+template <typename T>
+void spectral_resample(const Grid &gs, const Grid &gd, int nf, const T *const *in, T *const *out, cx<T> *spec_s,
+                       cx<T> *spec_d, const Twiddles<T> &tws, const Twiddles<T> &twd, hipStream_t s);
 
 // ---- semi-Lagrangian transport (transport.hip) ----
 // Every step kernel takes `box`: the largest stencil box (nodes) of its

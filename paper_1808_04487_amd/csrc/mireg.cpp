@@ -127,6 +127,14 @@ struct mireg_ctx {
     bool have_images = false;
     bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
     int box_X = 0, box_Y = 0;  // largest stencil box (nodes) of X and Y
+    // two-level preconditioner: the n/2 context, its freshness, counters
+    int pc_kind = MIREG_PC_SPECTRAL;
+    double pc_kappa = 0.1;
+    int pc_max_inner = 50;
+    mireg_ctx *coarse = nullptr;
+    long long vel_version = 0, coarse_vel_version = -1;
+    bool coarse_images = false;
+    long long coarse_matvecs = 0;
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool stats_on = false;
@@ -143,7 +151,12 @@ struct mireg_ctx {
         err = buf;
         return code;
     }
-    void invalidate() { have_X = have_Y = have_state = have_gradm = have_d = false; }
+    // every change of the velocity goes through here (the coarse problem of
+    // the two-level preconditioner follows the version)
+    void invalidate() {
+        have_X = have_Y = have_state = have_gradm = have_d = false;
+        vel_version += 1;
+    }
     long long N() const { return g.N; }
     double cell() const {
         const double two_pi = 6.283185307179586476925;
@@ -478,6 +491,80 @@ int impl_precond(mireg_ctx *ctx, const T *r, T *z) {
     return check_launch(ctx);
 }
 
+// out = spectral resampling of the vector field in (grid gs of ctx a) to
+// grid gd of ctx b, through the two contexts' spectrum buffers.
+template <typename T>
+void resample3(mireg_ctx *a, mireg_ctx *b, const T *in, T *out, int nf) {
+    const long long Na = a->N(), Nb = b->N();
+    const T *ip[3] = {in, in + Na, in + 2 * Na};
+    T *op[3] = {out, out + Nb, out + 2 * Nb};
+    Phase ph(a, 0);
+    spectral_resample<T>(a->g, b->g, nf, ip, op, static_cast<cx<T> *>(a->spec), static_cast<cx<T> *>(b->spec),
+                         twiddles<T>(a), twiddles<T>(b), a->stream);
+}
+
+// Two-level preconditioner (Sec. 2.3.3): z = Hreg^{-1/2} (Q_P u + F_H t),
+// t = Hreg^{-1/2} r, u ~ (Hreg_c^{-1/2} H_c Hreg_c^{-1/2})^{-1} Q_R t by CG on
+// the coarse context to kappa * eps_h.
+template <typename T, typename S = T>
+int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
+    mireg_ctx *c = ctx->coarse;
+    const long long n = 3 * ctx->N(), nc = 3 * c->N();
+    int rc;
+    if (!ctx->coarse_images) {
+        resample3<T>(ctx, c, ctx->f<T>(ctx->mT), c->f<T>(c->mT), 1);
+        resample3<T>(ctx, c, ctx->f<T>(ctx->mR), c->f<T>(c->mR), 1);
+        c->have_images = true;
+        c->have_state = c->have_gradm = false;
+        ctx->coarse_images = true;
+    }
+    if (ctx->coarse_vel_version != ctx->vel_version) {
+        resample3<T>(ctx, c, ctx->f<T>(ctx->v), c->f<T>(c->v), 3);
+        c->invalidate();
+        ctx->coarse_vel_version = ctx->vel_version;
+    }
+    T *t = ctx->vec<T>(7);
+    op_scale<T, S>(ctx, SYM_AINV_SQRT, 3, ctx->p.beta_v, 0.0, r, t);
+    T *b = c->vec<T>(4), *u = c->vec<T>(5), *w = c->vec<T>(6), *y = c->vec<T>(7);
+    T *cr = c->vec<T>(0), *cp = c->vec<T>(1), *cq = c->vec<T>(2);
+    resample3<T>(ctx, c, t, b, 3);
+    // CG on S u = b, S = Hreg_c^{-1/2} H_c Hreg_c^{-1/2}, u0 = 0
+    fill<T>(nc, (T)0, u, c->stream);
+    HIP_OK(hipMemcpyAsync(cr, b, nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(cp, b, nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    double rr = 0;
+    if ((rc = dot_h<T>(c, cr, cr, nc, &rr))) return rc;
+    const double r0 = std::sqrt(rr), tol = ctx->pc_kappa * eps_h * r0;
+    for (int it = 0; it < ctx->pc_max_inner && std::sqrt(rr) > tol; ++it) {
+        op_scale<T, S>(c, SYM_AINV_SQRT, 3, c->p.beta_v, 0.0, cp, w);
+        if ((rc = impl_matvec<T, S>(c, w, y))) return rc;
+        ctx->coarse_matvecs += 1;
+        op_scale<T, S>(c, SYM_AINV_SQRT, 3, c->p.beta_v, 0.0, y, cq);
+        double pq = 0;
+        if ((rc = dot_h<T>(c, cp, cq, nc, &pq))) return rc;
+        if (!(pq > 0)) break;
+        const double alpha = rr / pq;
+        pcg_update<T>(nc, alpha, cp, cq, u, cr, c->partials, c->dres, c->stream);
+        if ((rc = readback(c, 1))) return rc;
+        const double rr_new = c->cell() * c->hres[0];
+        if (std::sqrt(rr_new) <= tol) break;
+        xpay<T>(nc, cr, rr_new / rr, cp, cp, c->stream);  // p = r + beta p
+        rr = rr_new;
+    }
+    op_scale<T, S>(ctx, SYM_HIGHPASS, 3, 1.0, 0.0, t, z);
+    resample3<T>(c, ctx, u, t, 3);
+    axpby<T>(n, (T)1, t, (T)1, z, ctx->stream);  // z = F_H t + Q_P u
+    op_scale<T, S>(ctx, SYM_AINV_SQRT, 3, ctx->p.beta_v, 0.0, z, z);
+    return check_launch(ctx);
+}
+
+// The preconditioner PCG uses, with the PCG's relative tolerance eps_h.
+template <typename T, typename S = T>
+int apply_precond(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
+    if (ctx->pc_kind == MIREG_PC_TWO_LEVEL) return two_level_apply<T, S>(ctx, r, z, eps_h);
+    return impl_precond<T, S>(ctx, r, z);
+}
+
 // ---- PCG (Algorithm "inner iteration") ----
 template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
@@ -493,7 +580,7 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
     int it = 0;
     double rnorm = r0;
     if (r0 > 0) {
-        impl_precond<T, S>(ctx, r, z);
+        if ((rc = apply_precond<T, S>(ctx, r, z, rtol))) return rc;
         HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
         double rz = 0;
         if ((rc = dot_h<T>(ctx, r, z, n, &rz))) return rc;
@@ -511,7 +598,7 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[0]);
             if (rnorm <= rtol * r0) break;
-            impl_precond<T, S>(ctx, r, z);
+            if ((rc = apply_precond<T, S>(ctx, r, z, rtol))) return rc;
             double rz_new = 0;
             if ((rc = dot_h<T>(ctx, r, z, n, &rz_new))) return rc;
             const double mu = rz_new / rz;
@@ -534,6 +621,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     const long long n = 3 * ctx->N();
     const double h3 = ctx->cell();
     mireg_report R{};
+    const long long coarse0 = ctx->coarse_matvecs;
     // vectors 0..3 belong to PCG; 4: g, 5: vt, 6: accepted v
     T *g = ctx->vec<T>(4), *vt = ctx->vec<T>(5), *vk = ctx->vec<T>(6);
     int rc;
@@ -619,6 +707,7 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     HIP_OK(hipMemcpyAsync(v_io, vk, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    R.coarse_matvecs = (int)(ctx->coarse_matvecs - coarse0);
     (void)h3;
     if (rep) *rep = R;
     return check_launch(ctx);
@@ -643,6 +732,7 @@ int impl_set_images(mireg_ctx *ctx, const T *mT, const T *mR) {
     HIP_OK(hipMemcpyAsync(ctx->mR, mR, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     ctx->have_images = true;
     ctx->have_state = ctx->have_gradm = false;
+    ctx->coarse_images = false;
     return MIREG_OK;
 }
 
@@ -872,6 +962,7 @@ int mireg_destroy(mireg_ctx *ctx) {
     if (!ctx) return MIREG_E_ARG;
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
+    if (ctx->coarse) mireg_destroy(ctx->coarse);
     for (void *p : ctx->allocs) hipFree(p);
     if (ctx->hres) hipHostFree(ctx->hres);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
@@ -918,7 +1009,31 @@ int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt) {
 
 int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
     if (!ctx || !r || !z) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
-    return DISPATCH(ctx, (impl_precond<T, S>(ctx, (const T *)r, (T *)z)));
+    if (ctx->pc_kind == MIREG_PC_TWO_LEVEL && !ctx->have_images)
+        return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    return DISPATCH(ctx, (apply_precond<T, S>(ctx, (const T *)r, (T *)z, 1.0)));
+}
+
+int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner) {
+    if (!ctx) return MIREG_E_ARG;
+    if (kind != MIREG_PC_SPECTRAL && kind != MIREG_PC_TWO_LEVEL) return ctx->fail(MIREG_E_ARG, "unknown preconditioner");
+    if (!(kappa > 0 && kappa < 1) || max_inner < 1) return ctx->fail(MIREG_E_ARG, "kappa must be in (0, 1), max_inner >= 1");
+    if (kind == MIREG_PC_TWO_LEVEL && !ctx->coarse) {
+        if (ctx->g.n1 < 16 || ctx->g.n2 < 16 || ctx->g.n3 < 16)
+            return ctx->fail(MIREG_E_SHAPE, "the two-level preconditioner needs at least 16 points per axis");
+        mireg_params p = ctx->p;
+        p.n[0] = ctx->g.n1 / 2;
+        p.n[1] = ctx->g.n2 / 2;
+        p.n[2] = ctx->g.n3 / 2;
+        int rc = mireg_create(&p, ctx->stream, &ctx->coarse);
+        if (rc) return ctx->fail(rc, "creating the coarse context failed");
+        ctx->coarse_images = false;
+        ctx->coarse_vel_version = -1;
+    }
+    ctx->pc_kind = kind;
+    ctx->pc_kappa = kappa;
+    ctx->pc_max_inner = max_inner;
+    return MIREG_OK;
 }
 
 int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit, int *iters,

@@ -18,6 +18,7 @@ F32, F64, F32_H16 = 0, 1, 2
 H1, H2 = 1, 2
 DIV_NONE, DIV_NEAR, DIV_LERAY = 0, 1, 2
 CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL = 1, 2, 3, 4
+PC_SPECTRAL, PC_TWO_LEVEL = 0, 1
 
 OPS = {
     "grad": 1, "div": 2, "laplace": 3, "apply_A": 4, "apply_K": 5, "leray": 6, "precond": 7,
@@ -58,7 +59,7 @@ class Report(ctypes.Structure):
                 ("ls_trials", ctypes.c_int), ("J0", ctypes.c_double), ("J", ctypes.c_double),
                 ("mismatch_rel", ctypes.c_double), ("gnorm0", ctypes.c_double),
                 ("gnorm", ctypes.c_double), ("gnorm_rel", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("coarse_matvecs", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -93,6 +94,7 @@ SIGNATURES = {
     "mireg_pcg_solve": ([_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp], ctypes.c_int),
     "mireg_gn_solve": ([_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)], ctypes.c_int),
     "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
+    "mireg_set_precond": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
@@ -228,6 +230,11 @@ class Context:
         out = self.empty(3) if out is None else out
         self._check(self.lib.mireg_hessian_matvec(self.h, self._arg(vt, 3, "vt"), self._arg(out, 3, "Hvt")))
         return out
+
+    def set_precond(self, kind, kappa=0.1, max_inner=50):
+        """PC_SPECTRAL or PC_TWO_LEVEL (coarse CG to kappa times the PCG tolerance)."""
+        k = {"spectral": PC_SPECTRAL, "two_level": PC_TWO_LEVEL}.get(kind, kind)
+        self._check(self.lib.mireg_set_precond(self.h, int(k), float(kappa), int(max_inner)))
 
     def precond(self, r, out=None):
         out = self.empty(3) if out is None else out
