@@ -22,6 +22,9 @@ FP16) is timed on the same inputs and reported in "precision_variant".
 "two_level" repeats the timed solves with the two-level coarse-grid
 preconditioner (coarse grid 128^3, nested CG to kappa times the PCG
 tolerance; kappa 0.1 as in the paper, and 0.5).
+"batched" solves 16 pairs at 64^3 and 12 at 128^3 (the power-of-two members
+of the uneven batch) with four concurrent streams, graph-captured matvecs and
+autotuned tiles, against one stream without either.
 "warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
 trained network's prediction (paper_1808_04487_amd/weights) to the same
 absolute gradient tolerance.
@@ -55,6 +58,7 @@ def parse_args():
     ap.add_argument("--no-precision-variant", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-two-level", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--warm-pairs", type=int, default=16, help="held-out pairs of the warm-start comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, run a fill and a multiply over 1 GiB (known "
@@ -192,6 +196,31 @@ def precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, plain):
     }
 
 
+def batched_eval(args, torch):
+    """Uneven batch: sequential (one stream, eager) vs batched (4 streams,
+    graphs, autotuner); each configuration runs once untimed first."""
+    from paper_1808_04487_amd import batch
+
+    sizes = [64] * 16 + [128] * 12
+    pairs = batch.make_pairs(sizes)
+    out = {"workload": "16 pairs at 64^3 + 12 at 128^3, seeds (100+2p, 101+2p), amplitude U[0.05, 0.2] 2 pi; "
+                       "H1-div beta_v=5e-3, eps_g=5e-2", "pairs": len(sizes),
+           "points": int(sum(n ** 3 for n in sizes))}
+    for key, kw in (("sequential", dict(workers=1, graphs=False, autotune=False)),
+                    ("batched", dict(workers=4, graphs=True, autotune=True))):
+        bs = batch.BatchSolver(**kw)
+        bs.solve(pairs, grad_rtol=5e-2)
+        res, wall = bs.solve(pairs, grad_rtol=5e-2)
+        bs.close()
+        mv = sum(r[1]["matvecs"] for r in res)
+        out[key] = {"wall_s": round(wall, 4), "pairs_per_s": round(len(sizes) / wall, 2),
+                    "matvecs": mv, "points_matvecs_per_s": round(sum(r[1]["matvecs"] * p[0].numel()
+                                                                   for r, p in zip(res, pairs)) / wall, 1)}
+        log(args, "%s: %.3f s for %d pairs" % (key, wall, len(sizes)))
+    out["speedup"] = round(out["sequential"]["wall_s"] / out["batched"]["wall_s"], 3)
+    return out
+
+
 def warm_start_eval(args, torch):
     """Plain vs warm-started GN-Krylov solves of held-out 128^3 pairs (seeds
     3000000 on, disjoint from training and from the recorded evaluation)."""
@@ -315,6 +344,11 @@ def main():
                                                      "mismatch_rel", "gnorm_rel")}}
         ctx.set_precond("spectral")
 
+    bat = None
+    if not args.no_batched:
+        log(args, "batched uneven solves")
+        bat = batched_eval(args, torch)
+
     warm = None
     if not args.no_warm_start:
         log(args, "warm-start comparison")
@@ -358,6 +392,7 @@ def main():
         "cpu_baseline": cpu,
         "precision_variant": prec,
         "two_level": two,
+        "batched": bat,
         "warm_start": warm,
         "kernels": kernels,
     }

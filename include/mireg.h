@@ -171,6 +171,20 @@ int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z);
 typedef enum { MIREG_PC_SPECTRAL = 0, MIREG_PC_TWO_LEVEL = 1 } mireg_precond_kind;
 int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
 
+/* Launch-overhead and tuning controls (not in the paper; for many small
+ * problems and for each grid size):
+ * mireg_set_graphs: on != 0 makes PCG replay its Hessian matvec from a
+ *   captured HIP graph (captured on a private stream, launched on the
+ *   context's stream; re-captured when the velocity changes); off while
+ *   timers or kernel statistics are enabled.  Results are identical.
+ * mireg_autotune: times `reps` matvecs at the current velocity with each
+ *   tile shape of the transport kernels (0: 4x8x32, 1: 8x8x16, 2: 8x16x16
+ *   points in x1 x x2 x x3) and keeps the fastest; ms (host, 3 values, may
+ *   be NULL) receives the mean times, *shape (may be NULL) the choice.  The
+ *   shapes compute identical bits.  Needs set_images; synchronises. */
+int mireg_set_graphs(mireg_ctx *ctx, int on);
+int mireg_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape);
+
 /* PCG (Algorithm "inner iteration") for H x = rhs at the current v, x0 = 0;
  * stops when ||r|| <= rtol ||rhs||, after maxit iterations, or on
  * non-positive curvature.  *iters and *relres (host, may be NULL). */

@@ -135,6 +135,13 @@ struct mireg_ctx {
     long long vel_version = 0, coarse_vel_version = -1;
     bool coarse_images = false;
     long long coarse_matvecs = 0;
+    // PCG's matvec replayed from a captured graph (per velocity and buffers)
+    bool use_graphs = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t mv_exec = nullptr;
+    const void *mv_in = nullptr;
+    void *mv_out = nullptr;
+    long long mv_version = -1;
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool stats_on = false;
@@ -485,6 +492,49 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
     return check_launch(ctx);
 }
 
+// Hvt = H vt through a captured graph of the whole matvec (kernels only: no
+// host synchronisation, no memset), re-captured when the velocity or the
+// buffers change; the caches it reads are built eagerly first.  Used when
+// graphs are on and neither timers nor kernel statistics are.
+template <typename T, typename S = T>
+int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
+    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return impl_matvec<T, S>(ctx, vt, Hvt);
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
+    if (!ctx->mv_exec || ctx->mv_version != ctx->vel_version || ctx->mv_in != vt || ctx->mv_out != Hvt) {
+        if (ctx->mv_exec) {
+            hipGraphExecDestroy(ctx->mv_exec);
+            ctx->mv_exec = nullptr;
+        }
+        if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        // the capture stream must see the work already queued on the context's stream
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        hipStream_t own = ctx->stream;
+        ctx->stream = ctx->cap_stream;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        int rc = MIREG_OK;
+        if (e == hipSuccess) {
+            rc = impl_matvec<T, S>(ctx, vt, Hvt);
+            e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        }
+        ctx->stream = own;
+        if (rc) return rc;
+        if (e != hipSuccess) return ctx->fail(MIREG_E_HIP, "matvec capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&ctx->mv_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return ctx->fail(MIREG_E_HIP, "graph instantiation: %s", hipGetErrorString(e));
+        ctx->mv_version = ctx->vel_version;
+        ctx->mv_in = vt;
+        ctx->mv_out = Hvt;
+    }
+    HIP_OK(hipGraphLaunch(ctx->mv_exec, ctx->stream));
+    return check_launch(ctx);
+}
+
 template <typename T, typename S = T>
 int impl_precond(mireg_ctx *ctx, const T *r, T *z) {
     op_scale<T, S>(ctx, SYM_AINV, 3, ctx->p.beta_v, 0.0, r, z);
@@ -558,6 +608,60 @@ int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
     return check_launch(ctx);
 }
 
+// Tile shape of the transport kernels; the stencil boxes (measured per tile)
+// and any captured matvec depend on it.
+template <typename T, typename S = T>
+void set_tile(mireg_ctx *ctx, int shape) {
+    ctx->g.sl_tile = shape;
+    if (ctx->have_X) ctx->box_X = box_of_displacement<T>(ctx, ctx->f<T>(ctx->X));
+    if (ctx->have_Y) ctx->box_Y = box_of_displacement<T>(ctx, ctx->f<T>(ctx->Y));
+    if (ctx->mv_exec) {
+        hipGraphExecDestroy(ctx->mv_exec);
+        ctx->mv_exec = nullptr;
+    }
+}
+
+// Autotuner: mean time of `reps` matvecs at the current velocity per tile
+// shape; keeps the fastest (every shape gives the same bits).
+template <typename T, typename S = T>
+int impl_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
+    const long long n = 3 * ctx->N();
+    T *in = ctx->vec<T>(2), *out = ctx->vec<T>(3);
+    HIP_OK(hipMemcpyAsync(in, ctx->v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_shape = ctx->g.sl_tile, rc = MIREG_OK;
+    for (int sh = 0; sh < 3 && !rc; ++sh) {
+        set_tile<T, S>(ctx, sh);
+        rc = impl_matvec<T, S>(ctx, in, out);  // warm-up
+        hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && !rc; ++r) rc = impl_matvec<T, S>(ctx, in, out);
+        hipEventRecord(e1, ctx->stream);
+        hipEventSynchronize(e1);
+        float t = 0;
+        hipEventElapsedTime(&t, e0, e1);
+        const double m = (double)t / reps;
+        if (ms) ms[sh] = m;
+        if (m < best) {
+            best = m;
+            best_shape = sh;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    set_tile<T, S>(ctx, best_shape);
+    if (shape) *shape = best_shape;
+    return check_launch(ctx);
+}
+
 // The preconditioner PCG uses, with the PCG's relative tolerance eps_h.
 template <typename T, typename S = T>
 int apply_precond(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
@@ -585,7 +689,7 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
         double rz = 0;
         if ((rc = dot_h<T>(ctx, r, z, n, &rz))) return rc;
         while (it < maxit) {
-            if ((rc = impl_matvec<T, S>(ctx, s, Hs))) return rc;
+            if ((rc = matvec_graph<T, S>(ctx, s, Hs))) return rc;
             double sHs = 0;
             if ((rc = dot_h<T>(ctx, s, Hs, n, &sHs))) return rc;
             if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate
@@ -963,6 +1067,8 @@ int mireg_destroy(mireg_ctx *ctx) {
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
     if (ctx->coarse) mireg_destroy(ctx->coarse);
+    if (ctx->mv_exec) hipGraphExecDestroy(ctx->mv_exec);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     for (void *p : ctx->allocs) hipFree(p);
     if (ctx->hres) hipHostFree(ctx->hres);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
@@ -1012,6 +1118,26 @@ int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
     if (ctx->pc_kind == MIREG_PC_TWO_LEVEL && !ctx->have_images)
         return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     return DISPATCH(ctx, (apply_precond<T, S>(ctx, (const T *)r, (T *)z, 1.0)));
+}
+
+int mireg_set_graphs(mireg_ctx *ctx, int on) {
+    if (!ctx) return MIREG_E_ARG;
+    ctx->use_graphs = on != 0;
+    if (!ctx->use_graphs && ctx->mv_exec) {
+        hipGraphExecDestroy(ctx->mv_exec);
+        ctx->mv_exec = nullptr;
+    }
+    return MIREG_OK;
+}
+
+int mireg_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape) {
+    if (!ctx) return MIREG_E_ARG;
+    if (reps < 1) return ctx->fail(MIREG_E_ARG, "reps must be >= 1");
+    if (ctx->g.lds_cap == 0) {  // staging switched off: every shape gathers globally
+        if (shape) *shape = ctx->g.sl_tile;
+        return MIREG_OK;
+    }
+    return DISPATCH(ctx, (impl_autotune<T, S>(ctx, reps, ms, shape)));
 }
 
 int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner) {

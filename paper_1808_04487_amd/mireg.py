@@ -95,6 +95,8 @@ SIGNATURES = {
     "mireg_gn_solve": ([_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)], ctypes.c_int),
     "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
     "mireg_set_precond": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "mireg_set_graphs": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mireg_autotune": ([_vp, ctypes.c_int, _dp, _ip], ctypes.c_int),
     "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
@@ -230,6 +232,16 @@ class Context:
         out = self.empty(3) if out is None else out
         self._check(self.lib.mireg_hessian_matvec(self.h, self._arg(vt, 3, "vt"), self._arg(out, 3, "Hvt")))
         return out
+
+    def set_graphs(self, on=True):
+        self._check(self.lib.mireg_set_graphs(self.h, int(bool(on))))
+
+    def autotune(self, reps=3):
+        """Pick the fastest transport tile shape; returns (shape, ms per shape)."""
+        ms = (ctypes.c_double * 3)()
+        sh = ctypes.c_int()
+        self._check(self.lib.mireg_autotune(self.h, int(reps), ms, ctypes.byref(sh)))
+        return sh.value, list(ms)
 
     def set_precond(self, kind, kappa=0.1, max_inner=50):
         """PC_SPECTRAL or PC_TWO_LEVEL (coarse CG to kappa times the PCG tolerance)."""
