@@ -176,7 +176,11 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
  * mireg_set_graphs: on != 0 makes PCG replay its Hessian matvec from a
  *   captured HIP graph (captured on a private stream, launched on the
  *   context's stream; re-captured when the velocity changes); off while
- *   timers or kernel statistics are enabled.  Results are identical.
+ *   timers or kernel statistics are enabled.  Results are identical.  HIP
+ *   invalidates a running capture when any thread uses the legacy (null)
+ *   stream: with graphs on in one thread, other threads must keep their
+ *   work off the null stream (mireg_create with a null stream uses it), or
+ *   the capturing call fails with MIREG_E_HIP.
  * mireg_autotune: times `reps` matvecs at the current velocity with each
  *   tile shape of the transport kernels (0: 4x8x32, 1: 8x8x16, 2: 8x16x16
  *   points in x1 x x2 x x3) and keeps the fastest; ms (host, 3 values, may

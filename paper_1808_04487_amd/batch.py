@@ -63,9 +63,11 @@ class BatchSolver:
         self.tuned = {}
 
     def _context(self, w, n):
+        """Worker w's context for grid n, created on worker w's stream."""
         c = self.ctxs[w].get(n)
         if c is None:
-            c = mireg.Context(n, dtype=torch.float32, device=self.device, **self.solver)
+            with torch.cuda.device(self.device), torch.cuda.stream(self.streams[w]):
+                c = mireg.Context(n, dtype=torch.float32, device=self.device, **self.solver)
             c.set_graphs(self.graphs)
             self.ctxs[w][n] = c
         return c
@@ -79,6 +81,12 @@ class BatchSolver:
             todo.put(i)
         errors = []
         producer = torch.cuda.current_stream(self.device)
+        # Every context exists before the workers start: creating one (device
+        # allocations, uploads) while another worker captures its matvec graph
+        # could invalidate that capture.
+        for n in sorted({tuple(p[0].shape) for p in pairs}):
+            for w in range(self.workers):
+                self._context(w, n)
 
         def work(w):
             try:
@@ -92,7 +100,7 @@ class BatchSolver:
                             return
                         mT, mR = pairs[i]
                         n = tuple(mT.shape)
-                        ctx = self._context(w, n)
+                        ctx = self.ctxs[w][n]
                         ctx.set_images(mT, mR)
                         v, rep = ctx.gn_solve(**gn_opts)
                         if self.tune and (w, n) not in self.tuned:

@@ -136,6 +136,7 @@ struct OpConst {
     T alpha, beta_v, beta_w;
     T gs1, gs2, gs3;  // Gaussian: (2 pi sigma / n_a)^2 / 2
     T norm;           // 1 / (n1 n2 n3)
+    double *red;      // per-workgroup partials of sum_x in out, or null
 };
 
 template <typename T>
@@ -240,12 +241,23 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
         }
     };
     cx<T> reg[EPT];
+    // Parseval: sum_x in out = sum over the half spectrum of w Re(conj(in^) out^ / N),
+    // w = 1 on the k3 = 0 and Nyquist planes, 2 elsewhere
+    double dacc = 0;
+    const double wk3 = (i3 == 0 || 2 * i3 == oc.n3) ? 1.0 : 2.0;
+    auto dot_mode = [&](const cx<T> &a, const cx<T> &b) {
+        dacc += wk3 * ((double)a.re * (double)b.re + (double)a.im * (double)b.im);
+    };
     if constexpr (KIND == SPEC_SCALE) {
         for (int fi = 0; fi < oc.nf; ++fi) {
             load(fi, reg);
             fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], scalar_symbol(mode(e), oc) * oc.norm);
+            for (int e = 0; e < EPT; ++e) {
+                const cx<T> in = reg[e];
+                reg[e] = scale(in, scalar_symbol(mode(e), oc) * oc.norm);
+                if (oc.red && ok) dot_mode(in, reg[e]);
+            }
             fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
             store(fi, reg);
         }
@@ -303,7 +315,9 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
                     const T s = oc.alpha * reg_symbol(mode(e), oc.reg);
-                    reg[e] = scale(scale(reg[e], s) + ba[e], oc.norm);
+                    const cx<T> in = reg[e];
+                    reg[e] = scale(scale(in, s) + ba[e], oc.norm);
+                    if (oc.red && ok) dot_mode(in, reg[e]);
                 }
             } else {
 #pragma unroll
@@ -313,6 +327,32 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
             store(a, reg);
         }
     }
+    if constexpr (KIND == SPEC_SCALE || KIND == SPEC_TAIL) {
+        if (oc.red) {
+            __shared__ double red_sh[kColThreads / 64];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
+            if ((threadIdx.x & 63) == 0) red_sh[threadIdx.x >> 6] = dacc;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double tot = 0;
+                for (int w = 0; w < kColThreads / 64; ++w) tot += red_sh[w];
+                oc.red[blockIdx.x] = tot;
+            }
+        }
+    }
+}
+
+// out[0] = sum of n partials in a fixed order (one workgroup)
+__global__ __launch_bounds__(256) void k_sum_partials(int n, const double *__restrict__ part, double *__restrict__ out) {
+    __shared__ double sh[4];
+    double s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,18 +418,21 @@ static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipSt
 }
 
 template <typename T, int KIND>
-static void launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpConst<T> &oc,
-                      const cx<T> *tw, hipStream_t s) {
+static int launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpConst<T> &oc,
+                     const cx<T> *tw, hipStream_t s) {
     const long long Q = (long long)g.n2 * g.k3;
     HookScope hs(K_X1_SCALE + KIND, (double)(nin + nout) * sizeof(T) * 2.0 * g.NS);
+    int blocks = 0;
 #define MIREG_L(L)                                                                              \
     {                                                                                           \
         constexpr int W = FftShape<T, L, x1_variant<KIND>(), kColThreads>::W;                   \
         dim3 grid((unsigned)((Q + W - 1) / W));                                                 \
+        blocks = (int)grid.x;                                                                   \
         hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(kColThreads), 0, s, f, Q, oc, tw); \
     }
     MIREG_SWITCH_POW2(g.n1, MIREG_L)
 #undef MIREG_L
+    return blocks;
 }
 
 template <typename T>
@@ -417,15 +460,21 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
     oc.gs2 = (T)(0.5 * (two_pi * sp.sigma / g.n2) * (two_pi * sp.sigma / g.n2));
     oc.gs3 = (T)(0.5 * (two_pi * sp.sigma / g.n3) * (two_pi * sp.sigma / g.n3));
     oc.norm = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+    oc.red = (kind == SPEC_SCALE || kind == SPEC_TAIL) ? sp.red : nullptr;
 
     launch_r2c<T>(g, fin, fspec, nin, tw.t[2], s);
     launch_x2<T, -1>(g, fspec, nin, tw.t[1], s);
+    int blocks = 0;
     switch (kind) {
-        case SPEC_SCALE: launch_x1<T, SPEC_SCALE>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        case SPEC_SCALE: blocks = launch_x1<T, SPEC_SCALE>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         case SPEC_GRAD: launch_x1<T, SPEC_GRAD>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         case SPEC_DIV: launch_x1<T, SPEC_DIV>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         case SPEC_PROJ: launch_x1<T, SPEC_PROJ>(g, fspec, nin, nout, oc, tw.t[0], s); break;
-        default: launch_x1<T, SPEC_TAIL>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        default: blocks = launch_x1<T, SPEC_TAIL>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+    }
+    if (oc.red) {
+        HookScope hs(K_REDUCE, 8.0 * blocks);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
     }
     launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
     launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);

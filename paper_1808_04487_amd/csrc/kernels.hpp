@@ -56,6 +56,10 @@ struct SpecParams {
     double alpha;   // factor of A (SYM_A, SYM_AINV, SPEC_TAIL)
     double beta_v, beta_w;
     double sigma;   // Gaussian width in cells
+    // Optional fused reduction (SPEC_SCALE, SPEC_TAIL): *red_out = sum_x in(x) out(x)
+    // over all fields, from the spectra (Parseval); red holds one partial per
+    // x1 workgroup (at most n2 (n3/2+1) / 8 + 1 doubles).
+    double *red = nullptr, *red_out = nullptr;
 };
 
 // Device twiddle tables exp(-2 pi i j / n_a), j < n_a, for the three axes.

@@ -122,6 +122,7 @@ struct mireg_ctx {
     void *spec = nullptr;   // 6 half spectra
     void *tw[3] = {nullptr, nullptr, nullptr};
     double *partials = nullptr, *dres = nullptr;  // device reduction buffers
+    double *xpart = nullptr;                      // partials of the fused spectral dot products
     double *hres = nullptr;                       // pinned host mirror of dres
 
     bool have_images = false;
@@ -282,12 +283,16 @@ void op_proj(mireg_ctx *ctx, int div, const T *u, T *out) {
 }
 // out = alpha A u + K b
 template <typename T, typename S = T>
-void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
+void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out, bool dot = false) {
     const long long N = ctx->N();
     const void *in[6] = {u, u + N, u + 2 * N, b, b + N, b + 2 * N};
     T *o[3] = {out, out + N, out + 2 * N};
     SpecParams sp = spec_params<T>(ctx);
     sp.alpha = alpha;
+    if (dot) {  // dres[0] = sum_x u . out (Parseval, in the x1 pass)
+        sp.red = ctx->xpart;
+        sp.red_out = ctx->dres;
+    }
     spec<T, S>(ctx, SPEC_TAIL, 6, 3, in, o, sp);
 }
 
@@ -404,11 +409,22 @@ int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
     int rc = readback(ctx, 1);
     if (rc) return rc;
     const double mis = 0.5 * ctx->cell() * ctx->hres[0];
-    // beta_v/2 <A v, v>
+    // beta_v/2 <A v, v>, the product taken from the spectra of the A pass
     T *Av = ctx->vec<T>(7);
-    op_scale<T, S>(ctx, SYM_A, 3, 1.0, 0.0, ctx->f<T>(ctx->v), Av);
-    double vAv = 0;
-    if ((rc = dot_h<T>(ctx, Av, ctx->f<T>(ctx->v), 3 * N, &vAv))) return rc;
+    {
+        const T *v = ctx->f<T>(ctx->v);
+        const void *in[3] = {v, v + N, v + 2 * N};
+        T *o[3] = {Av, Av + N, Av + 2 * N};
+        SpecParams sp = spec_params<T>(ctx);
+        sp.sym = SYM_A;
+        sp.nf = 3;
+        sp.alpha = 1.0;
+        sp.red = ctx->xpart;
+        sp.red_out = ctx->dres;
+        spec<T, S>(ctx, SPEC_SCALE, 3, 3, in, o, sp);
+    }
+    if ((rc = readback(ctx, 1))) return rc;
+    const double vAv = ctx->cell() * ctx->hres[0];
     double r = 0.5 * ctx->p.beta_v * vAv;
     if (ctx->p.div == MIREG_DIV_NEAR) {
         // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2)
@@ -454,8 +470,9 @@ int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
 }
 
 // ---- Gauss-Newton Hessian matvec ----
+// dot: also leave sum_x vt . Hvt in dres[0] (from the spectra of the last pass)
 template <typename T, typename S = T>
-int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
+int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
@@ -488,17 +505,18 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
         }
     }
     backward_sweep<T, S>(ctx, lam, b);
-    op_tail<T, S>(ctx, ctx->p.beta_v, vt, b, Hvt);
+    op_tail<T, S>(ctx, ctx->p.beta_v, vt, b, Hvt, dot);
     return check_launch(ctx);
 }
 
-// Hvt = H vt through a captured graph of the whole matvec (kernels only: no
+// Hvt = H vt and dres[0] = sum_x vt . Hvt, through a captured graph of the
+// whole matvec when graphs are on (kernels only: no
 // host synchronisation, no memset), re-captured when the velocity or the
 // buffers change; the caches it reads are built eagerly first.  Used when
 // graphs are on and neither timers nor kernel statistics are.
 template <typename T, typename S = T>
 int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
-    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return impl_matvec<T, S>(ctx, vt, Hvt);
+    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return impl_matvec<T, S>(ctx, vt, Hvt, true);
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
@@ -518,7 +536,7 @@ int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         int rc = MIREG_OK;
         if (e == hipSuccess) {
-            rc = impl_matvec<T, S>(ctx, vt, Hvt);
+            rc = impl_matvec<T, S>(ctx, vt, Hvt, true);
             e = hipStreamEndCapture(ctx->cap_stream, &graph);
         }
         ctx->stream = own;
@@ -669,6 +687,30 @@ int apply_precond(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
     return impl_precond<T, S>(ctx, r, z);
 }
 
+// z = M^{-1} r and *rz = <r, z> (grid inner product); the spectral
+// preconditioner gets the product from its own spectra.
+template <typename T, typename S = T>
+int precond_dot(mireg_ctx *ctx, const T *r, T *z, double eps_h, double *rz) {
+    if (ctx->pc_kind == MIREG_PC_TWO_LEVEL) {
+        int rc = two_level_apply<T, S>(ctx, r, z, eps_h);
+        return rc ? rc : dot_h<T>(ctx, r, z, 3 * ctx->N(), rz);
+    }
+    const long long N = ctx->N();
+    const void *in[3] = {r, r + N, r + 2 * N};
+    T *o[3] = {z, z + N, z + 2 * N};
+    SpecParams sp = spec_params<T>(ctx);
+    sp.sym = SYM_AINV;
+    sp.nf = 3;
+    sp.alpha = ctx->p.beta_v;
+    sp.red = ctx->xpart;
+    sp.red_out = ctx->dres;
+    spec<T, S>(ctx, SPEC_SCALE, 3, 3, in, o, sp);
+    int rc = readback(ctx, 1);
+    if (rc) return rc;
+    *rz = ctx->cell() * ctx->hres[0];
+    return check_launch(ctx);
+}
+
 // ---- PCG (Algorithm "inner iteration") ----
 template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
@@ -684,14 +726,13 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
     int it = 0;
     double rnorm = r0;
     if (r0 > 0) {
-        if ((rc = apply_precond<T, S>(ctx, r, z, rtol))) return rc;
-        HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
         double rz = 0;
-        if ((rc = dot_h<T>(ctx, r, z, n, &rz))) return rc;
+        if ((rc = precond_dot<T, S>(ctx, r, z, rtol, &rz))) return rc;
+        HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
         while (it < maxit) {
             if ((rc = matvec_graph<T, S>(ctx, s, Hs))) return rc;
-            double sHs = 0;
-            if ((rc = dot_h<T>(ctx, s, Hs, n, &sHs))) return rc;
+            if ((rc = readback(ctx, 1))) return rc;
+            const double sHs = h3 * ctx->hres[0];
             if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate
                 if (it == 0) HIP_OK(hipMemcpyAsync(x, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
                 break;
@@ -702,9 +743,8 @@ int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *it
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[0]);
             if (rnorm <= rtol * r0) break;
-            if ((rc = apply_precond<T, S>(ctx, r, z, rtol))) return rc;
             double rz_new = 0;
-            if ((rc = dot_h<T>(ctx, r, z, n, &rz_new))) return rc;
+            if ((rc = precond_dot<T, S>(ctx, r, z, rtol, &rz_new))) return rc;
             const double mu = rz_new / rz;
             rz = rz_new;
             xpay<T>(n, z, mu, s, s, ctx->stream);  // s = z + mu s
@@ -928,7 +968,10 @@ int make_twiddles(mireg_ctx *ctx) {
             h[j].re = (T)cosl(ang);
             h[j].im = (T)sinl(ang);
         }
-        HIP_OK(hipMemcpy(ctx->tw[a], h.data(), n[a] * sizeof(cx<T>), hipMemcpyHostToDevice));
+        // on the context's stream: a copy on the legacy stream would invalidate
+        // a graph capture running in another thread
+        HIP_OK(hipMemcpyAsync(ctx->tw[a], h.data(), n[a] * sizeof(cx<T>), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
     }
     return MIREG_OK;
 }
@@ -1041,6 +1084,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);
     for (int a = 0; a < 3 && !rc; ++a) rc = alloc(ctx, &ctx->tw[a], (size_t)p->n[a] * 2 * ctx->elem);
     if (!rc) rc = alloc(ctx, (void **)&ctx->partials, 4 * kRedBlocks * sizeof(double));
+    if (!rc) rc = alloc(ctx, (void **)&ctx->xpart, ((size_t)ctx->g.n2 * ctx->g.k3 / 8 + 16) * sizeof(double));
     if (!rc) rc = alloc(ctx, (void **)&ctx->dres, 8 * sizeof(double));
     if (!rc && hipHostMalloc((void **)&ctx->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         rc = ctx->fail(MIREG_E_NOMEM, "hipHostMalloc failed");

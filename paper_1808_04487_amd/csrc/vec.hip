@@ -37,12 +37,46 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_dot(const T *__restrict__ a, const T *__restrict__ b,
-                                                     long long n, double *__restrict__ part) {
+__global__ __launch_bounds__(kRedThreads) void k_dot_scalar(const T *__restrict__ a, const T *__restrict__ b,
+                                                            long long n, double *__restrict__ part) {
     double v[1] = {0.0};
     for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
          i += (long long)gridDim.x * kRedThreads)
         v[0] += (double)a[i] * (double)b[i];
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Four consecutive elements per step (one 16- or 32-byte load per operand),
+// four independent FP64 accumulators; the n % 4 tail is added by block 0.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_dot(const T *__restrict__ a, const T *__restrict__ b,
+                                                     long long n, double *__restrict__ part) {
+    using V4 = typename Vec4<T>::type;
+    const long long n4 = n / 4;
+    const V4 *a4 = reinterpret_cast<const V4 *>(a), *b4 = reinterpret_cast<const V4 *>(b);
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n4;
+         i += (long long)gridDim.x * kRedThreads) {
+        const V4 x = a4[i], y = b4[i];
+        s0 += (double)x.x * (double)y.x;
+        s1 += (double)x.y * (double)y.y;
+        s2 += (double)x.z * (double)y.z;
+        s3 += (double)x.w * (double)y.w;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) s0 += (double)a[4 * n4 + threadIdx.x] * (double)b[4 * n4 + threadIdx.x];
+    double v[1] = {(s0 + s1) + (s2 + s3)};
     block_sum<1>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -61,17 +95,53 @@ __global__ __launch_bounds__(kRedThreads) void k_sumsq_diff(const TA *__restrict
 }
 
 template <typename T>
+__device__ __forceinline__ T pcg_step(double k, T s, T Hs, T &x, T &r, double &acc);
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_pcg_update_scalar(long long n, double k, const T *__restrict__ s,
+                                                                   const T *__restrict__ Hs, T *__restrict__ x,
+                                                                   T *__restrict__ r, double *__restrict__ part) {
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kRedThreads)
+        pcg_step(k, s[i], Hs[i], x[i], r[i], v[0]);
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T pcg_step(double k, T s, T Hs, T &x, T &r, double &acc) {
+    x = (T)((double)x + k * (double)s);
+    r = (T)((double)r - k * (double)Hs);
+    acc += (double)r * (double)r;
+    return r;
+}
+
+template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_pcg_update(long long n, double k, const T *__restrict__ s,
                                                             const T *__restrict__ Hs, T *__restrict__ x,
                                                             T *__restrict__ r, double *__restrict__ part) {
-    double v[1] = {0.0};
-    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+    using V4 = typename Vec4<T>::type;
+    const long long n4 = n / 4;
+    const V4 *s4 = reinterpret_cast<const V4 *>(s), *h4 = reinterpret_cast<const V4 *>(Hs);
+    V4 *x4 = reinterpret_cast<V4 *>(x), *r4 = reinterpret_cast<V4 *>(r);
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n4;
          i += (long long)gridDim.x * kRedThreads) {
-        x[i] = (T)((double)x[i] + k * (double)s[i]);
-        const T ri = (T)((double)r[i] - k * (double)Hs[i]);
-        r[i] = ri;
-        v[0] += (double)ri * (double)ri;
+        const V4 sv = s4[i], hv = h4[i];
+        V4 xv = x4[i], rv = r4[i];
+        pcg_step(k, sv.x, hv.x, xv.x, rv.x, a0);
+        pcg_step(k, sv.y, hv.y, xv.y, rv.y, a1);
+        pcg_step(k, sv.z, hv.z, xv.z, rv.z, a2);
+        pcg_step(k, sv.w, hv.w, xv.w, rv.w, a3);
+        x4[i] = xv;
+        r4[i] = rv;
     }
+    if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) {
+        const long long i = 4 * n4 + threadIdx.x;
+        pcg_step(k, s[i], Hs[i], x[i], r[i], a0);
+    }
+    double v[1] = {(a0 + a1) + (a2 + a3)};
     block_sum<1>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
@@ -213,10 +283,19 @@ const char *const kKernelNames[K_COUNT] = {
     "fft_x1_proj", "fft_x1_tail", "fft_c2r_x3", "sl_departure", "sl_interp", "sl_adjoint_init",
     "sl_adjoint_step", "sl_adjoint_accum", "sl_incstate_init", "sl_incstate_step", "reduce", "vector"};
 
+// Vector kernels read 4 elements at once when the pointer allows it.
+template <typename T>
+static bool aligned4(const T *p) {
+    return (reinterpret_cast<uintptr_t>(p) % (4 * sizeof(T))) == 0;
+}
+
 template <typename T>
 void dot(const T *a, const T *b, long long n, double *partials, double *result, hipStream_t s) {
     HookScope hs(K_REDUCE, 2.0 * n * sizeof(T));
-    hipLaunchKernelGGL((k_dot<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
+    if (aligned4(a) && aligned4(b))
+        hipLaunchKernelGGL((k_dot<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
+    else
+        hipLaunchKernelGGL((k_dot_scalar<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename TA, typename TB>
@@ -229,8 +308,12 @@ template <typename T>
 void pcg_update(long long n, double k, const T *sdir, const T *Hs, T *x, T *r, double *partials,
                 double *result, hipStream_t s) {
     HookScope hs(K_VECTOR, 6.0 * n * sizeof(T));
-    hipLaunchKernelGGL((k_pcg_update<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, k, sdir, Hs, x, r,
-                       partials);
+    if (aligned4(sdir) && aligned4(Hs) && aligned4(x) && aligned4(r))
+        hipLaunchKernelGGL((k_pcg_update<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, k, sdir, Hs, x, r,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_pcg_update_scalar<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, k, sdir, Hs, x,
+                           r, partials);
     hipLaunchKernelGGL((k_finish_sum<1>), dim3(1), dim3(kRedThreads), 0, s, partials, result);
 }
 template <typename T>
