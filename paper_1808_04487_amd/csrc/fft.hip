@@ -356,6 +356,195 @@ __global__ __launch_bounds__(256) void k_sum_partials(int n, const double *__res
 }
 
 // ---------------------------------------------------------------------------
+// Krylov vectors held as spectra.  PCG keeps x, r and the direction s as
+// their half spectra F u (all three axes transformed, unnormalised forward
+// DFT, the [k1][k2][k3] order the x1 pass leaves), three arrays of NS modes
+// per vector field.  The preconditioner is a pointwise multiplier there and
+// the Hessian's spectral tail needs the spectrum of s, which is kept: one
+// forward transform (of the transport output b) and one inverse (of the new
+// direction) per iteration instead of the five of the physical-space
+// iteration.  Sums over the grid come from Parseval: sum_x u v =
+// (1/N) sum over the half spectrum of w Re(conj(F u) F v), w = 1 on the
+// k3 = 0 and Nyquist planes, 2 elsewhere.
+// ---------------------------------------------------------------------------
+struct KrylovPtrs {
+    void *w[3];        // x2/x3-transformed work spectra
+    const void *a[3];  // spectral operand
+    void *o[3];        // spectral output (read first in KP_DIR)
+};
+
+// x1 passes of the Krylov iteration:
+//   KP_FWD:  o = x1 forward transform of w                      (F u from the x2/x3 spectra)
+//   KP_HESS: o = alpha a(k) a_in + K F b, with F b from w;       red: sum_x s . Hs
+//   KP_DIR:  o = M^{-1}(k) a_in + mu o (o not read if first); w = x1 inverse of o / N
+//   KP_INV:  w = x1 inverse of a_in / N
+template <typename T, int L, int PASS>
+__global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc, T mu,
+                                                           int first, const cx<T> *__restrict__ tw) {
+    constexpr int V = 1;
+    using S = FftShape<T, L, V, kColThreads>;
+    constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
+    using Lay = LayoutCols<W>;
+    __shared__ cx<T> lds[Lay::size(L)];
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const long long q = (long long)blockIdx.x * W + c;
+    const bool ok = q < Q;
+    const long long qq = ok ? q : 0;
+    const int i2 = (int)(qq / oc.k3), i3 = (int)(qq % oc.k3);
+    const T k2 = (T)wavenumber(i2, oc.n2), k3 = (T)i3;
+    const T t2 = (2 * i2 == oc.n2) ? (T)0 : k2, t3 = (2 * i3 == oc.n3) ? (T)0 : k3;
+    auto mode = [&](int e) {
+        Mode<T> m;
+        const int i1 = t + TPC * e;
+        m.k1 = (T)wavenumber(i1, oc.n1);
+        m.t1 = (2 * i1 == oc.n1) ? (T)0 : m.k1;
+        m.k2 = k2;
+        m.t2 = t2;
+        m.k3 = k3;
+        m.t3 = t3;
+        return m;
+    };
+    auto load = [&](const void *base, cx<T>(&r)[EPT]) {
+        const cx<T> *p = reinterpret_cast<const cx<T> *>(base) + qq;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r[e] = ok ? p[(long long)(t + TPC * e) * Q] : make_cx<T>(0, 0);
+    };
+    auto store = [&](void *base, cx<T>(&r)[EPT]) {
+        cx<T> *p = reinterpret_cast<cx<T> *>(base) + qq;
+        if (ok) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) p[(long long)(t + TPC * e) * Q] = r[e];
+        }
+    };
+    cx<T> reg[EPT];
+    double dacc = 0;
+    const double wk3 = (i3 == 0 || 2 * i3 == oc.n3) ? 1.0 : 2.0;
+    if constexpr (PASS == KP_FWD) {
+        for (int a = 0; a < 3; ++a) {
+            load(f.w[a], reg);
+            fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
+            store(f.o[a], reg);
+        }
+    } else if constexpr (PASS == KP_HESS) {
+        cx<T> b0[EPT], b1[EPT], b2[EPT];
+        load(f.w[0], b0);
+        fft_line<T, L, V, -1, Lay>(b0, t, c, tw, 1, lds);
+        load(f.w[1], b1);
+        fft_line<T, L, V, -1, Lay>(b1, t, c, tw, 1, lds);
+        load(f.w[2], b2);
+        fft_line<T, L, V, -1, Lay>(b2, t, c, tw, 1, lds);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) project(mode(e), oc, b0[e], b1[e], b2[e]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T>(&ba)[EPT] = a == 0 ? b0 : (a == 1 ? b1 : b2);
+            load(f.a[a], reg);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const cx<T> sh = reg[e];
+                reg[e] = scale(sh, oc.alpha * reg_symbol(mode(e), oc.reg)) + ba[e];
+                if (ok) dacc += wk3 * ((double)sh.re * (double)reg[e].re + (double)sh.im * (double)reg[e].im);
+            }
+            store(f.o[a], reg);
+        }
+    } else if constexpr (PASS == KP_DIR) {
+        for (int a = 0; a < 3; ++a) {
+            cx<T> rh[EPT];
+            load(f.a[a], rh);
+            if (!first) load(f.o[a], reg);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const cx<T> z = scale(rh[e], scalar_symbol(mode(e), oc));
+                reg[e] = first ? z : z + scale(reg[e], mu);
+            }
+            store(f.o[a], reg);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], oc.norm);
+            fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
+            store(f.w[a], reg);
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            load(f.a[a], reg);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], oc.norm);
+            fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
+            store(f.w[a], reg);
+        }
+    }
+    if constexpr (PASS == KP_HESS) {
+        if (oc.red) {
+            __shared__ double red_sh[kColThreads / 64];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
+            if ((threadIdx.x & 63) == 0) red_sh[threadIdx.x >> 6] = dacc;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double tot = 0;
+                for (int w = 0; w < kColThreads / 64; ++w) tot += red_sh[w];
+                oc.red[blockIdx.x] = tot * (double)oc.norm;
+            }
+        }
+    }
+}
+
+// x, r, s, Hs spectra (three components each), by value.
+template <typename T>
+struct KrylovSet {
+    cx<T> *p[12];
+};
+
+// Pointwise step of the spectral PCG: x += alpha s, r -= alpha Hs (when
+// write), then per-workgroup partials of sum_x r . M^{-1} r (part[b]) and
+// sum_x r . r (part[nb + b]) from the updated r.  Grid-stride over the NS
+// modes with a fixed grid, so the sums are reproducible.
+template <typename T>
+__global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int n2, int n3, int k3, int reg,
+                                                       T beta_v, T alpha, int write, KrylovSet<T> v,
+                                                       double norm, double *__restrict__ part) {
+    cx<T> *const *x = v.p, *const *r = v.p + 3;
+    const cx<T> *const *s = v.p + 6, *const *h = v.p + 9;
+    double rz = 0, rr = 0;
+    for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NS; j += gridDim.x * 256u) {
+        const unsigned i3 = j % (unsigned)k3, row = j / (unsigned)k3;
+        const unsigned i2 = row % (unsigned)n2, i1 = row / (unsigned)n2;
+        const T w1 = (T)wavenumber((int)i1, n1), w2 = (T)wavenumber((int)i2, n2), w3 = (T)i3;
+        const T ks = w1 * w1 + w2 * w2 + w3 * w3;
+        const T sym = reg == 2 ? ks * ks : ks;
+        const double sigma = ks == (T)0 ? 1.0 : (double)((T)1 / (beta_v * sym));
+        const double wk3 = (i3 == 0 || 2 * i3 == (unsigned)n3) ? 1.0 : 2.0;
+        double m2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T> rv = r[a][j];
+            if (write) {
+                rv = rv - scale(h[a][j], alpha);
+                r[a][j] = rv;
+                x[a][j] = x[a][j] + scale(s[a][j], alpha);
+            }
+            m2 += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+        }
+        rr += wk3 * m2;
+        rz += wk3 * sigma * m2;
+    }
+    __shared__ double sh[2][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        rz += __shfl_down(rz, off, 64);
+        rr += __shfl_down(rr, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = rz;
+        sh[1][threadIdx.x >> 6] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = ((sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3])) * norm;
+        part[gridDim.x + blockIdx.x] = ((sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3])) * norm;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 #define MIREG_SWITCH_POW2(n, MACRO) \
@@ -546,6 +735,160 @@ template void spectral_resample<float>(const Grid &, const Grid &, int, const fl
 template void spectral_resample<double>(const Grid &, const Grid &, int, const double *const *, double *const *,
                                         cx<double> *, cx<double> *, const Twiddles<double> &,
                                         const Twiddles<double> &, hipStream_t);
+
+// ---- Krylov host passes ----
+template <typename T, int PASS>
+static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int first,
+                             const cx<T> *tw, hipStream_t s, int *blocks) {
+    const long long Q = (long long)g.n2 * g.k3;
+    // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3
+    const double fields = PASS == KP_HESS ? 9.0 : (PASS == KP_DIR ? 12.0 : 6.0);
+    HookScope hs(K_X1_KRYLOV, fields * 2.0 * sizeof(T) * g.NS);
+#define MIREG_L(L)                                                                                       \
+    {                                                                                                    \
+        constexpr int W = FftShape<T, L, 1, kColThreads>::W;                                             \
+        dim3 grid((unsigned)((Q + W - 1) / W));                                                          \
+        if (blocks) *blocks = (int)grid.x;                                                               \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(kColThreads), 0, s, f, Q, oc, mu, first, tw); \
+    }
+    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+#undef MIREG_L
+}
+
+template <typename T>
+static OpConst<T> krylov_const(const Grid &g, const SpecParams &sp) {
+    OpConst<T> oc{};
+    oc.n1 = g.n1;
+    oc.n2 = g.n2;
+    oc.n3 = g.n3;
+    oc.k3 = g.k3;
+    oc.sym = SYM_AINV;
+    oc.nf = 3;
+    oc.reg = sp.reg;
+    oc.div = sp.div;
+    oc.alpha = (T)sp.beta_v;
+    oc.beta_v = (T)sp.beta_v;
+    oc.beta_w = (T)sp.beta_w;
+    oc.norm = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+    oc.red = nullptr;
+    return oc;
+}
+
+template <typename T>
+void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *work, const Twiddles<T> &tw,
+                    hipStream_t s) {
+    FieldPtrs fin{}, fw{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fin.p[a] = const_cast<T *>(u[a]);
+        fw.p[a] = work + (long long)a * g.NS;
+        kp.w[a] = fw.p[a];
+        kp.o[a] = hat[a];
+    }
+    launch_r2c<T>(g, fin, fw, 3, tw.t[2], s);
+    launch_x2<T, -1>(g, fw, 3, tw.t[1], s);
+    SpecParams sp{};
+    sp.reg = 1;
+    launch_x1_krylov<T, KP_FWD>(g, kp, krylov_const<T>(g, sp), (T)0, 0, tw.t[0], s, nullptr);
+}
+
+template <typename T>
+void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
+                    const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
+    FieldPtrs fin{}, fw{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fin.p[a] = const_cast<T *>(b[a]);
+        fw.p[a] = work + (long long)a * g.NS;
+        kp.w[a] = fw.p[a];
+        kp.a[a] = shat[a];
+        kp.o[a] = hhat[a];
+    }
+    launch_r2c<T>(g, fin, fw, 3, tw.t[2], s);
+    launch_x2<T, -1>(g, fw, 3, tw.t[1], s);
+    OpConst<T> oc = krylov_const<T>(g, sp);
+    oc.red = sp.red;
+    int blocks = 0;
+    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, 0, tw.t[0], s, &blocks);
+    if (oc.red) {
+        HookScope hs(K_REDUCE, 8.0 * blocks);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
+    }
+}
+
+template <typename T>
+void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, bool first,
+                      T *const *s_out, cx<T> *work, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
+    FieldPtrs fw{}, fout{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fw.p[a] = work + (long long)a * g.NS;
+        fout.p[a] = s_out[a];
+        kp.w[a] = fw.p[a];
+        kp.a[a] = rhat[a];
+        kp.o[a] = shat[a];
+    }
+    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, first ? 1 : 0, tw.t[0], s, nullptr);
+    launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
+    launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
+}
+
+template <typename T>
+void krylov_inverse(const Grid &g, const cx<T> *const *hat, T *const *u, cx<T> *work, const Twiddles<T> &tw,
+                    hipStream_t s) {
+    FieldPtrs fw{}, fout{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fw.p[a] = work + (long long)a * g.NS;
+        fout.p[a] = u[a];
+        kp.w[a] = fw.p[a];
+        kp.a[a] = hat[a];
+    }
+    SpecParams sp{};
+    sp.reg = 1;
+    launch_x1_krylov<T, KP_INV>(g, kp, krylov_const<T>(g, sp), (T)0, 0, tw.t[0], s, nullptr);
+    launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
+    launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
+}
+
+template <typename T>
+void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *xhat, cx<T> *const *rhat,
+                   const cx<T> *const *shat, const cx<T> *const *hhat, const SpecParams &sp, double *partials,
+                   double *out2, hipStream_t s) {
+    KrylovSet<T> v{};
+    for (int a = 0; a < 3; ++a) {
+        v.p[a] = xhat[a];
+        v.p[3 + a] = rhat[a];
+        v.p[6 + a] = const_cast<cx<T> *>(shat[a]);
+        v.p[9 + a] = const_cast<cx<T> *>(hhat[a]);
+    }
+    constexpr int nb = kRedBlocks;
+    {
+        HookScope hs(K_KRYLOV_UPDATE, (write ? 18.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
+        hipLaunchKernelGGL((k_krylov_update<T>), dim3(nb), dim3(256), 0, s, (unsigned)g.NS, g.n1, g.n2, g.n3, g.k3,
+                           sp.reg, (T)sp.beta_v, (T)alpha, write ? 1 : 0, v,
+                           1.0 / ((double)g.n1 * g.n2 * g.n3), partials);
+    }
+    HookScope hs(K_REDUCE, 16.0 * nb);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials, out2);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, out2 + 1);
+}
+
+#define MIREG_KRYLOV(T)                                                                                          \
+    template void krylov_forward<T>(const Grid &, const T *const *, cx<T> *const *, cx<T> *, const Twiddles<T> &, \
+                                    hipStream_t);                                                                \
+    template void krylov_hessian<T>(const Grid &, const T *const *, const cx<T> *const *, cx<T> *const *,         \
+                                    cx<T> *, const Twiddles<T> &, const SpecParams &, hipStream_t);              \
+    template void krylov_direction<T>(const Grid &, const cx<T> *const *, cx<T> *const *, double, bool,          \
+                                      T *const *, cx<T> *, const Twiddles<T> &, const SpecParams &, hipStream_t); \
+    template void krylov_inverse<T>(const Grid &, const cx<T> *const *, T *const *, cx<T> *, const Twiddles<T> &, \
+                                    hipStream_t);                                                                \
+    template void krylov_update<T>(const Grid &, double, bool, cx<T> *const *, cx<T> *const *,                   \
+                                   const cx<T> *const *, const cx<T> *const *, const SpecParams &, double *,     \
+                                   double *, hipStream_t);
+MIREG_KRYLOV(float)
+MIREG_KRYLOV(double)
+#undef MIREG_KRYLOV
 
 template void spectral_apply<float>(const Grid &, int, int, int, const void *const *, float *const *,
                                     cx<float> *, const Twiddles<float> &, const SpecParams &,

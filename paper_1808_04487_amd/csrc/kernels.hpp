@@ -9,7 +9,7 @@ namespace mireg {
 enum KernelId {
     K_R2C = 0, K_C2C_FWD, K_C2C_INV, K_X1_SCALE, K_X1_GRAD, K_X1_DIV, K_X1_PROJ, K_X1_TAIL, K_C2R,
     K_DEPARTURE, K_INTERP, K_ADJ_INIT, K_ADJ_STEP, K_ADJ_ACC, K_INC_INIT, K_INC_STEP, K_REDUCE, K_VECTOR,
-    K_COUNT
+    K_X1_KRYLOV, K_KRYLOV_UPDATE, K_COUNT
 };
 extern const char *const kKernelNames[K_COUNT];
 
@@ -73,6 +73,36 @@ struct Twiddles {
 template <typename T>
 void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *const *in, T *const *out,
                     cx<T> *spec, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+
+// ---- PCG with Krylov vectors held as half spectra (all three axes
+// transformed, unnormalised forward DFT; three arrays of NS modes per vector
+// field).  work holds three half spectra.  The preconditioner is the
+// spectral one, M^{-1}(k) = 1 / (beta_v a(k)), 1 at k = 0 (sp: reg, beta_v).
+enum KrylovPass { KP_FWD = 0, KP_HESS = 1, KP_DIR = 2, KP_INV = 3 };
+// hat = F u
+template <typename T>
+void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *work, const Twiddles<T> &tw,
+                    hipStream_t s);
+// hhat = beta_v a(k) shat + K F b (sp: reg, div, beta_v, beta_w); with
+// sp.red / sp.red_out set, *red_out = sum_x s . Hs
+template <typename T>
+void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
+                    const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+// shat = M^{-1} rhat + mu shat (shat not read when first), s_out = F^{-1} shat
+template <typename T>
+void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, bool first,
+                      T *const *s_out, cx<T> *work, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+// u = F^{-1} hat
+template <typename T>
+void krylov_inverse(const Grid &g, const cx<T> *const *hat, T *const *u, cx<T> *work, const Twiddles<T> &tw,
+                    hipStream_t s);
+// xhat += alpha shat, rhat -= alpha hhat (when write); then out2[0] =
+// sum_x r . M^{-1} r and out2[1] = sum_x r . r (device); partials holds
+// 2 kRedBlocks doubles
+template <typename T>
+void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *xhat, cx<T> *const *rhat,
+                   const cx<T> *const *shat, const cx<T> *const *hhat, const SpecParams &sp, double *partials,
+                   double *out2, hipStream_t s);
 
 // Spectral resampling between two grids (each axis the same or half/double
 // the size): out = the trigonometric interpolant of in, truncated to the

@@ -101,6 +101,9 @@ struct StatsHook : mireg::KernelHook {
 
 }  // namespace
 
+// Krylov spectra of the spectral PCG (mireg_ctx::kspec)
+enum KrylovVec { KV_X = 0, KV_R = 1, KV_S = 2, KV_H = 3 };
+
 struct mireg_ctx {
     mireg_params p{};
     hipStream_t stream = nullptr;
@@ -120,6 +123,7 @@ struct mireg_ctx {
     void *b = nullptr;      // 3N, time integral of the gradient / matvec
     void *vecs = nullptr;   // kVecs x 3N work vectors
     void *spec = nullptr;   // 6 half spectra
+    void *kspec = nullptr;  // 12 half spectra: x, r, s, Hs of the spectral PCG
     void *tw[3] = {nullptr, nullptr, nullptr};
     double *partials = nullptr, *dres = nullptr;  // device reduction buffers
     double *xpart = nullptr;                      // partials of the fused spectral dot products
@@ -142,6 +146,7 @@ struct mireg_ctx {
     hipGraphExec_t mv_exec = nullptr;
     const void *mv_in = nullptr;
     void *mv_out = nullptr;
+    bool mv_spectral = false;
     long long mv_version = -1;
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -177,6 +182,11 @@ struct mireg_ctx {
     template <typename T>
     T *vec(int i) const {
         return static_cast<T *>(vecs) + (long long)i * 3 * g.N;
+    }
+    // component a of Krylov spectrum v (KV_X, KV_R, KV_S, KV_H)
+    template <typename T>
+    cx<T> *khat(int v, int a) const {
+        return static_cast<cx<T> *>(kspec) + (long long)(3 * v + a) * g.NS;
     }
 };
 
@@ -470,14 +480,10 @@ int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
 }
 
 // ---- Gauss-Newton Hessian matvec ----
-// dot: also leave sum_x vt . Hvt in dres[0] (from the spectra of the last pass)
+// Transport part: ctx->b = the time integral of the incremental adjoint for
+// the direction vt (the caches it reads are current).
 template <typename T, typename S = T>
-int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
-    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    ensure_state<T, S>(ctx);
-    ensure_gradm<T, S>(ctx);
-    ensure_d<T, S>(ctx);
-    ensure_Y<T, S>(ctx);
+void matvec_transport(mireg_ctx *ctx, const T *vt) {
     const long long N = ctx->N();
     const int nt = ctx->p.nt;
     const double dt = 1.0 / nt;
@@ -505,24 +511,66 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
         }
     }
     backward_sweep<T, S>(ctx, lam, b);
-    op_tail<T, S>(ctx, ctx->p.beta_v, vt, b, Hvt, dot);
-    return check_launch(ctx);
 }
 
-// Hvt = H vt and dres[0] = sum_x vt . Hvt, through a captured graph of the
-// whole matvec when graphs are on (kernels only: no
-// host synchronisation, no memset), re-captured when the velocity or the
-// buffers change; the caches it reads are built eagerly first.  Used when
-// graphs are on and neither timers nor kernel statistics are.
+// dot: also leave sum_x vt . Hvt in dres[0] (from the spectra of the last pass)
 template <typename T, typename S = T>
-int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
-    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return impl_matvec<T, S>(ctx, vt, Hvt, true);
+int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
     ensure_d<T, S>(ctx);
     ensure_Y<T, S>(ctx);
-    if (!ctx->mv_exec || ctx->mv_version != ctx->vel_version || ctx->mv_in != vt || ctx->mv_out != Hvt) {
+    matvec_transport<T, S>(ctx, vt);
+    op_tail<T, S>(ctx, ctx->p.beta_v, vt, ctx->f<T>(ctx->b), Hvt, dot);
+    return check_launch(ctx);
+}
+
+// Matvec of the spectral PCG: the spectrum of H s from the kept spectrum of
+// s (KV_S) and the transport output, into KV_H; dres[0] = sum_x s . Hs.
+template <typename T, typename S = T>
+int impl_matvec_spectral(mireg_ctx *ctx, const T *s) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
+    matvec_transport<T, S>(ctx, s);
+    const long long N = ctx->N();
+    const T *b = ctx->f<T>(ctx->b);
+    const T *bp[3] = {b, b + N, b + 2 * N};
+    const cx<T> *sh[3] = {ctx->khat<T>(KV_S, 0), ctx->khat<T>(KV_S, 1), ctx->khat<T>(KV_S, 2)};
+    cx<T> *hh[3] = {ctx->khat<T>(KV_H, 0), ctx->khat<T>(KV_H, 1), ctx->khat<T>(KV_H, 2)};
+    SpecParams sp = spec_params<T>(ctx);
+    sp.red = ctx->xpart;
+    sp.red_out = ctx->dres;
+    {
+        Phase ph(ctx, 0);
+        krylov_hessian<T>(ctx->g, bp, sh, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp, ctx->stream);
+    }
+    return check_launch(ctx);
+}
+
+// PCG's matvec: Hvt = H vt (spectral: the spectrum of H vt in KV_H, Hvt
+// unused) and dres[0] = sum_x vt . Hvt, through a captured graph of the
+// whole matvec when graphs are on (kernels only: no host synchronisation,
+// no memset), re-captured when the velocity, the buffers or the kind
+// change; the caches it reads are built eagerly first.  Graphs are used
+// when neither timers nor kernel statistics are on.
+template <typename T, typename S = T>
+int matvec_body(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral) {
+    return spectral ? impl_matvec_spectral<T, S>(ctx, vt) : impl_matvec<T, S>(ctx, vt, Hvt, true);
+}
+template <typename T, typename S = T>
+int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false) {
+    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return matvec_body<T, S>(ctx, vt, Hvt, spectral);
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
+    if (!ctx->mv_exec || ctx->mv_version != ctx->vel_version || ctx->mv_in != vt || ctx->mv_out != Hvt ||
+        ctx->mv_spectral != spectral) {
         if (ctx->mv_exec) {
             hipGraphExecDestroy(ctx->mv_exec);
             ctx->mv_exec = nullptr;
@@ -536,7 +584,7 @@ int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         int rc = MIREG_OK;
         if (e == hipSuccess) {
-            rc = impl_matvec<T, S>(ctx, vt, Hvt, true);
+            rc = matvec_body<T, S>(ctx, vt, Hvt, spectral);
             e = hipStreamEndCapture(ctx->cap_stream, &graph);
         }
         ctx->stream = own;
@@ -548,6 +596,7 @@ int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt) {
         ctx->mv_version = ctx->vel_version;
         ctx->mv_in = vt;
         ctx->mv_out = Hvt;
+        ctx->mv_spectral = spectral;
     }
     HIP_OK(hipGraphLaunch(ctx->mv_exec, ctx->stream));
     return check_launch(ctx);
@@ -712,8 +761,89 @@ int precond_dot(mireg_ctx *ctx, const T *r, T *z, double eps_h, double *rz) {
 }
 
 // ---- PCG (Algorithm "inner iteration") ----
+// With the spectral preconditioner the Krylov vectors x, r and s are kept as
+// half spectra (KV_X, KV_R, KV_S; H s as KV_H): the preconditioner is a
+// pointwise multiplier there, H s is needed only as a spectrum, and only the
+// direction s is transformed back (the transport needs it on the grid).
+// Same iteration as below, with inner products from Parseval.
+template <typename T, typename S = T>
+int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
+    const long long N = ctx->N();
+    const double h3 = ctx->cell();
+    T *s = ctx->vec<T>(2);
+    T *sp3[3] = {s, s + N, s + 2 * N}, *xp[3] = {x, x + N, x + 2 * N};
+    const T *rp[3] = {rhs, rhs + N, rhs + 2 * N};
+    cx<T> *xh[3], *rh[3], *sh[3], *hh[3];
+    for (int a = 0; a < 3; ++a) {
+        xh[a] = ctx->khat<T>(KV_X, a);
+        rh[a] = ctx->khat<T>(KV_R, a);
+        sh[a] = ctx->khat<T>(KV_S, a);
+        hh[a] = ctx->khat<T>(KV_H, a);
+    }
+    cx<T> *work = static_cast<cx<T> *>(ctx->spec);
+    const Twiddles<T> tw = twiddles<T>(ctx);
+    const SpecParams sp = spec_params<T>(ctx);
+    int rc;
+    {
+        Phase ph(ctx, 0);
+        krylov_forward<T>(ctx->g, rp, rh, work, tw, ctx->stream);  // r = rhs, x = 0
+        fill<T>(6 * ctx->g.NS, (T)0, reinterpret_cast<T *>(xh[0]), ctx->stream);
+        krylov_update<T>(ctx->g, 0.0, false, xh, rh, sh, hh, sp, ctx->partials, ctx->dres + 1, ctx->stream);
+    }
+    if ((rc = readback(ctx, 3))) return rc;
+    const double r0 = std::sqrt(h3 * ctx->hres[2]);
+    double rz = h3 * ctx->hres[1];
+    int it = 0;
+    double rnorm = r0;
+    bool x_is_s = false;
+    if (r0 > 0) {
+        {
+            Phase ph(ctx, 0);  // s = z = M^{-1} r
+            krylov_direction<T>(ctx->g, rh, sh, 0.0, true, sp3, work, tw, sp, ctx->stream);
+        }
+        while (it < maxit) {
+            if ((rc = matvec_graph<T, S>(ctx, s, nullptr, true))) return rc;
+            if ((rc = readback(ctx, 1))) return rc;
+            const double sHs = h3 * ctx->hres[0];
+            if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate (z on the first)
+                x_is_s = it == 0;
+                break;
+            }
+            const double alpha = rz / sHs;
+            {
+                Phase ph(ctx, 2);
+                krylov_update<T>(ctx->g, alpha, true, xh, rh, sh, hh, sp, ctx->partials, ctx->dres + 1,
+                                 ctx->stream);
+            }
+            if ((rc = readback(ctx, 3))) return rc;
+            ++it;
+            rnorm = std::sqrt(h3 * ctx->hres[2]);
+            if (rnorm <= rtol * r0) break;
+            const double rz_new = h3 * ctx->hres[1];
+            const double mu = rz_new / rz;
+            rz = rz_new;
+            {
+                Phase ph(ctx, 0);  // s = z + mu s
+                krylov_direction<T>(ctx->g, rh, sh, mu, false, sp3, work, tw, sp, ctx->stream);
+            }
+        }
+    }
+    if (x_is_s) {
+        HIP_OK(hipMemcpyAsync(x, s, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    } else if (it > 0) {
+        Phase ph(ctx, 0);
+        krylov_inverse<T>(ctx->g, xh, xp, work, tw, ctx->stream);
+    } else {
+        fill<T>(3 * N, (T)0, x, ctx->stream);
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = r0 > 0 ? rnorm / r0 : 0.0;
+    return check_launch(ctx);
+}
+
 template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
+    if (ctx->pc_kind == MIREG_PC_SPECTRAL) return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres);
     const long long n = 3 * ctx->N();
     const double h3 = ctx->cell();
     T *r = ctx->vec<T>(0), *z = ctx->vec<T>(1), *s = ctx->vec<T>(2), *Hs = ctx->vec<T>(3);
@@ -1082,6 +1212,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, &ctx->b, 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->vecs, (size_t)mireg_ctx::kVecs * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);
+    if (!rc) rc = alloc(ctx, &ctx->kspec, (size_t)12 * ctx->g.NS * 2 * ctx->elem);
     for (int a = 0; a < 3 && !rc; ++a) rc = alloc(ctx, &ctx->tw[a], (size_t)p->n[a] * 2 * ctx->elem);
     if (!rc) rc = alloc(ctx, (void **)&ctx->partials, 4 * kRedBlocks * sizeof(double));
     if (!rc) rc = alloc(ctx, (void **)&ctx->xpart, ((size_t)ctx->g.n2 * ctx->g.k3 / 8 + 16) * sizeof(double));

@@ -281,7 +281,8 @@ thread_local KernelHook *g_hook = nullptr;
 const char *const kKernelNames[K_COUNT] = {
     "fft_r2c_x3", "fft_c2c_x2_fwd", "fft_c2c_x2_inv", "fft_x1_scale", "fft_x1_grad", "fft_x1_div",
     "fft_x1_proj", "fft_x1_tail", "fft_c2r_x3", "sl_departure", "sl_interp", "sl_adjoint_init",
-    "sl_adjoint_step", "sl_adjoint_accum", "sl_incstate_init", "sl_incstate_step", "reduce", "vector"};
+    "sl_adjoint_step", "sl_adjoint_accum", "sl_incstate_init", "sl_incstate_step", "reduce", "vector",
+    "fft_x1_krylov", "krylov_update"};
 
 // Vector kernels read 4 elements at once when the pointer allows it.
 template <typename T>
