@@ -35,7 +35,7 @@ struct PGrid {
 };
 
 // Tile shapes (x1 x x2 x x3 points) of the semi-Lagrangian kernels.
-enum SlTile { TILE_4x8x32 = 0, TILE_8x8x16 = 1, TILE_8x16x16 = 2 };
+enum SlTile { TILE_4x8x32 = 0, TILE_8x8x16 = 1, TILE_8x16x16 = 2, TILE_4x8x16 = 3 };
 template <int S>
 struct TileDims;
 template <>
@@ -49,6 +49,10 @@ struct TileDims<TILE_8x8x16> {
 template <>
 struct TileDims<TILE_8x16x16> {
     static constexpr int TZ = 8, TY = 16, TX = 16;
+};
+template <>
+struct TileDims<TILE_4x8x16> {
+    static constexpr int TZ = 4, TY = 8, TX = 16;
 };
 
 constexpr int kSlThreads = 256;
@@ -70,8 +74,8 @@ static PGrid pgrid(const Grid &g) {
     p.s23 = p.s3 + __builtin_ctz((unsigned)g.n2);
     p.N = g.N;
     p.shape = g.sl_tile;
-    const int TZ = p.shape == TILE_4x8x32 ? 4 : 8, TY = p.shape == TILE_8x16x16 ? 16 : 8,
-              TX = p.shape == TILE_4x8x32 ? 32 : 16;
+    const int TZ = (p.shape == TILE_4x8x32 || p.shape == TILE_4x8x16) ? 4 : 8,
+              TY = p.shape == TILE_8x16x16 ? 16 : 8, TX = p.shape == TILE_4x8x32 ? 32 : 16;
     p.tx = (g.n3 + TX - 1) / TX;
     p.ty = (g.n2 + TY - 1) / TY;
     p.tz = (g.n1 + TZ - 1) / TZ;
@@ -281,7 +285,8 @@ __device__ __forceinline__ bool block_box(int *box, int mn1, int mn2, int mn3, i
 
 // Generic tiled semi-Lagrangian sweep.  Op provides:
 //   void disp(unsigned idx, T *d)       displacement of point idx (cells, 3 values)
-//   void stage(unsigned gidx, T *v)     the NF gathered quantities at grid index gidx
+//   void stage(unsigned gidx, T *v)     loads behind the NF gathered quantities at grid index gidx
+//   void staged(T *v)                   turns those loads into the NF quantities (no loads)
 //   Pre pre(unsigned idx)               operands of the point update, loaded early
 //   void finish(unsigned idx, const Pre &, const T *acc)  output of point idx
 // g.lds_cap is the dynamic LDS size of the launch in box nodes: tiles whose
@@ -350,6 +355,8 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
         const unsigned m1 = g.n1 - 1, m2 = g.n2 - 1, m3 = g.n3 - 1;
         for (int k0 = threadIdx.x; k0 < V; k0 += kSlThreads * kStageU) {
             T v[kStageU][NF];
+            // Only loads here; whatever combines them (staged) runs at the
+            // LDS store, so all kStageU loads are in flight before the first wait.
 #pragma unroll
             for (int u = 0; u < kStageU; ++u) {
                 if (k0 + u * kSlThreads < V) {
@@ -374,6 +381,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             for (int u = 0; u < kStageU; ++u) {
                 const int k = k0 + u * kSlThreads;
                 if (k < V) {
+                    op.staged(v[u]);
 #pragma unroll
                     for (int f = 0; f < NF; ++f) lds[box_at<NF>(k, f, cap)] = v[u][f];
                 }
@@ -415,7 +423,12 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             }
             T acc[NF];
             contract<T, ORDER, NF>(
-                a1, a2, a3, o1, o2, o3, [&](unsigned off, T *v) { op.stage(off, v); }, acc);
+                a1, a2, a3, o1, o2, o3,
+                [&](unsigned off, T *v) {
+                    op.stage(off, v);
+                    op.staged(v);
+                },
+                acc);
             op.finish(tp.idx(g, p), pre[p], acc);
         }
     }
@@ -487,6 +500,7 @@ struct DepartureOp {
         x[1] = ld<T>(v, N + i);
         x[2] = ld<T>(v, 2 * N + i);
     }
+    __device__ void staged(T *) const {}
     struct Pre {
         T v1, v2, v3;
     };
@@ -512,6 +526,7 @@ struct InterpOp {
         d[2] = ld<T>(D, 2 * N + i);
     }
     __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(f, i); }
+    __device__ void staged(T *) const {}
     struct Pre {};
     __device__ Pre pre(unsigned) const { return Pre{}; }
     __device__ void finish(unsigned i, const Pre &, const T *a) const { st(out, i, a[0]); }
@@ -532,11 +547,12 @@ struct AdjointOp {
         d[1] = ld<T>(Y, N + i);
         d[2] = ld<T>(Y, 2 * N + i);
     }
+    // stage loads lambda and div v; staged forms the pair (lambda, lambda div v)
     __device__ void stage(unsigned i, T *x) const {
-        const T l = ld<T>(lin, i);
-        x[0] = l;
-        x[1] = l * ld<T>(dv, i);
+        x[0] = ld<T>(lin, i);
+        x[1] = ld<T>(dv, i);
     }
+    __device__ void staged(T *x) const { x[1] = x[0] * x[1]; }
     struct Pre {
         T d;
     };
@@ -562,6 +578,7 @@ struct AdjointAccumOp {
     T a_end, a_mid;
     __device__ void disp(unsigned i, T *d) const { step.disp(i, d); }
     __device__ void stage(unsigned i, T *x) const { step.stage(i, x); }
+    __device__ void staged(T *x) const { step.staged(x); }
     using Pre = typename AdjointOp<T, SL>::Pre;
     __device__ Pre pre(unsigned i) const { return step.pre(i); }
     __device__ void finish(unsigned i, const Pre &p, const T *a) const {
@@ -602,6 +619,7 @@ struct IncStateOp {
         d[2] = ld<T>(X, 2 * N + i);
     }
     __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(qin, i); }
+    __device__ void staged(T *) const {}
     struct Pre {
         T f;
     };
@@ -658,6 +676,7 @@ static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) 
     switch (g.shape) {
         case TILE_8x8x16: launch_sl_shape<T, NF, TILE_8x8x16>(g, order, op, s); break;
         case TILE_8x16x16: launch_sl_shape<T, NF, TILE_8x16x16>(g, order, op, s); break;
+        case TILE_4x8x16: launch_sl_shape<T, NF, TILE_4x8x16>(g, order, op, s); break;
         default: launch_sl_shape<T, NF, TILE_4x8x32>(g, order, op, s); break;
     }
 }
@@ -676,12 +695,14 @@ void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(3, TILE_8x8x16); break;
             case TILE_8x16x16: MIREG_BOX(3, TILE_8x16x16); break;
+            case TILE_4x8x16: MIREG_BOX(3, TILE_4x8x16); break;
             default: MIREG_BOX(3, TILE_4x8x32); break;
         }
     } else {
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(1, TILE_8x8x16); break;
             case TILE_8x16x16: MIREG_BOX(1, TILE_8x16x16); break;
+            case TILE_4x8x16: MIREG_BOX(1, TILE_4x8x16); break;
             default: MIREG_BOX(1, TILE_4x8x32); break;
         }
     }
