@@ -1191,7 +1191,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
         // 0: 4x8x32, 1: 8x8x16, 2: 8x16x16 (x1 x x2 x x3).
         const char *t = getenv("MIREG_SL_TILE");
         ctx->g.sl_tile = t ? atoi(t) : 1;
-        if (ctx->g.sl_tile < 0 || ctx->g.sl_tile > 3) ctx->g.sl_tile = 1;
+        if (ctx->g.sl_tile < 0 || ctx->g.sl_tile > 2) ctx->g.sl_tile = 1;
     }
     ctx->elem = p->dtype == MIREG_F64 ? 8 : 4;
     const size_t F = (size_t)ctx->g.N * ctx->elem;

@@ -21,6 +21,8 @@
 // (Sec. 3.5: only time histories are kept, no full space-time Newton).
 #include <limits.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mireg {
@@ -29,13 +31,14 @@ struct PGrid {
     int n1, n2, n3;
     int s3, s23;  // log2(n3), log2(n2 n3)
     long long N;
-    int tx, ty, tz;  // tiles per axis
+    int tx, ty, tz;  // tiles per axis (powers of two)
+    int ltx, lty;    // log2(tx), log2(ty)
     int lds_cap;     // largest box (nodes) staged in LDS in this launch; 0 disables staging
     int shape;       // tile shape (SlTile)
 };
 
 // Tile shapes (x1 x x2 x x3 points) of the semi-Lagrangian kernels.
-enum SlTile { TILE_4x8x32 = 0, TILE_8x8x16 = 1, TILE_8x16x16 = 2, TILE_4x8x16 = 3 };
+enum SlTile { TILE_4x8x32 = 0, TILE_8x8x16 = 1, TILE_8x16x16 = 2 };
 template <int S>
 struct TileDims;
 template <>
@@ -50,13 +53,12 @@ template <>
 struct TileDims<TILE_8x16x16> {
     static constexpr int TZ = 8, TY = 16, TX = 16;
 };
-template <>
-struct TileDims<TILE_4x8x16> {
-    static constexpr int TZ = 4, TY = 8, TX = 16;
-};
 
 constexpr int kSlThreads = 256;
-constexpr int kStageU = 8;        // staging loads in flight per thread
+constexpr int kStageU = 8;        // staging loads in flight per thread (wide planes)
+constexpr int kStageZ = 4;        // planes per staging batch
+constexpr int kStageCols = 2;     // plane positions per thread (planes of up to 512 nodes)
+static_assert(kStageCols == 2, "the plane staging instantiates one and two positions");
 constexpr int kLdsBytes = 65536;  // largest LDS allocation of one workgroup
 
 // Cells per unit length on axis a (the grid spans 2 pi).
@@ -74,11 +76,17 @@ static PGrid pgrid(const Grid &g) {
     p.s23 = p.s3 + __builtin_ctz((unsigned)g.n2);
     p.N = g.N;
     p.shape = g.sl_tile;
-    const int TZ = (p.shape == TILE_4x8x32 || p.shape == TILE_4x8x16) ? 4 : 8,
-              TY = p.shape == TILE_8x16x16 ? 16 : 8, TX = p.shape == TILE_4x8x32 ? 32 : 16;
+    int TZ = 8, TY = 8, TX = 16;
+    switch (p.shape) {
+        case TILE_4x8x32: TZ = 4, TY = 8, TX = 32; break;
+        case TILE_8x16x16: TZ = 8, TY = 16, TX = 16; break;
+        default: break;
+    }
     p.tx = (g.n3 + TX - 1) / TX;
     p.ty = (g.n2 + TY - 1) / TY;
     p.tz = (g.n1 + TZ - 1) / TZ;
+    p.ltx = __builtin_ctz((unsigned)p.tx);
+    p.lty = __builtin_ctz((unsigned)p.ty);
     p.lds_cap = g.lds_cap;
     return p;
 }
@@ -215,10 +223,11 @@ __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const Ax
 }
 
 // LDS layout of the staged box: NF <= 2 interleaved (the NF values of a node
-// are adjacent, one 4/8/16-byte read), NF = 3 one array per quantity.
+// are adjacent, one 4/8/16-byte read), NF = 3 one array of `stride` nodes per
+// quantity.
 template <int NF>
-__device__ __forceinline__ int box_at(int k, int f, int cap) {
-    return NF <= 2 ? k * NF + f : f * cap + k;
+__device__ __forceinline__ int box_at(int k, int f, int stride) {
+    return NF <= 2 ? k * NF + f : f * stride + k;
 }
 
 // Workgroup index -> tile index, contiguous runs of tiles per XCD (workgroups
@@ -250,7 +259,7 @@ struct TilePoints {
     static constexpr int ZSTEP = kSlThreads / (TX * TY);
     int i1_0, i2, i3;  // grid index of point 0 (i1 advances by ZSTEP per point)
     __device__ TilePoints(const PGrid &g, int tile) {
-        const int bx = tile % g.tx, by = (tile / g.tx) % g.ty, bz = tile / (g.tx * g.ty);
+        const int bx = tile & (g.tx - 1), by = (tile >> g.ltx) & (g.ty - 1), bz = tile >> (g.ltx + g.lty);
         i3 = bx * TX + (int)threadIdx.x % TX;
         i2 = by * TY + ((int)threadIdx.x / TX) % TY;
         i1_0 = bz * TZ + (int)threadIdx.x / (TX * TY);
@@ -261,6 +270,22 @@ struct TilePoints {
         return ((unsigned)i1(p) << g.s23) + ((unsigned)i2 << g.s3) + (unsigned)i3;
     }
 };
+
+// q = a / b and r = a - q b for 0 <= a, 0 < b, both below 2^16, from the
+// float estimate a (1/b) (relative error below 2^-22, so off by at most
+// one) and one correction step.
+__device__ __forceinline__ int small_div(int a, int b, float rb, int &r) {
+    int q = (int)((float)a * rb);
+    r = a - q * b;
+    if (r < 0) {
+        --q;
+        r += b;
+    } else if (r >= b) {
+        ++q;
+        r -= b;
+    }
+    return q;
+}
 
 // Block-wide bounding box of the base nodes (min, max per axis) into box[6];
 // returns false when the tile has no point inside the grid (uniform).
@@ -285,7 +310,9 @@ __device__ __forceinline__ bool block_box(int *box, int mn1, int mn2, int mn3, i
 
 // Generic tiled semi-Lagrangian sweep.  Op provides:
 //   void disp(unsigned idx, T *d)       displacement of point idx (cells, 3 values)
-//   void stage(unsigned gidx, T *v)     loads behind the NF gathered quantities at grid index gidx
+//   void stage(unsigned plane, unsigned rc, T *v)
+//                                       loads behind the NF gathered quantities at grid index
+//                                       plane + rc (plane: x1 offset, block-uniform)
 //   void staged(T *v)                   turns those loads into the NF quantities (no loads)
 //   Pre pre(unsigned idx)               operands of the point update, loaded early
 //   void finish(unsigned idx, const Pre &, const T *acc)  output of point idx
@@ -338,52 +365,107 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
     }
     __syncthreads();  // box initialised
     if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
-    // box of every stencil node, in unwrapped grid coordinates
-    const int lo1 = box[0] + FIRST, lo2 = box[1] + FIRST, lo3 = box[2] + FIRST;
-    const long long e1 = (long long)box[3] - box[0] + NP, e2 = (long long)box[4] - box[1] + NP,
-                    e3 = (long long)box[5] - box[2] + NP;
+    // box of every stencil node, in unwrapped grid coordinates (block-uniform)
+    const int c0 = __builtin_amdgcn_readfirstlane(box[0]), c1 = __builtin_amdgcn_readfirstlane(box[1]),
+              c2 = __builtin_amdgcn_readfirstlane(box[2]), c3 = __builtin_amdgcn_readfirstlane(box[3]),
+              c4 = __builtin_amdgcn_readfirstlane(box[4]), c5 = __builtin_amdgcn_readfirstlane(box[5]);
+    const int lo1 = c0 + FIRST, lo2 = c1 + FIRST, lo3 = c2 + FIRST;
+    const long long e1 = (long long)c3 - c0 + NP, e2 = (long long)c4 - c1 + NP, e3 = (long long)c5 - c2 + NP;
     const long long vol = e1 * e2 * e3;
-    const int cap = g.lds_cap;
+    // LDS holds cap + 1 nodes: the box (at most cap) and one spare node;
+    // NF = 3 keeps one array of cap + 1 per quantity
+    const int cap = g.lds_cap, stride = cap + 1;
     if (vol <= (long long)cap) {  // uniform across the block
-        // 2. copy the box into LDS: flat index k = (z E2 + y) E3 + x; each thread
-        //    walks k = tid, tid + 256, ... with (z, y, x) carried incrementally,
-        //    kStageU loads in flight before the LDS stores
-        const int E2 = (int)e2, E3 = (int)e3, E23 = E2 * E3, V = (int)vol;
-        const int dz = kSlThreads / E23, rest = kSlThreads - dz * E23, dy = rest / E3, dx = rest - dy * E3;
-        int z = (int)threadIdx.x / E23, y = ((int)threadIdx.x - z * E23) / E3;
-        int x = (int)threadIdx.x - z * E23 - y * E3;
+        // 2. copy the box into LDS, node (z, y, x) at k = z E23 + r, r = y E3 + x
+        //    (vol <= cap < 2^16).
+        const int E1 = (int)e1, E2 = (int)e2, E3 = (int)e3, E23 = E2 * E3, V = (int)vol;
+        const float rE3 = 1.0f / (float)E3;
         const unsigned m1 = g.n1 - 1, m2 = g.n2 - 1, m3 = g.n3 - 1;
-        for (int k0 = threadIdx.x; k0 < V; k0 += kSlThreads * kStageU) {
-            T v[kStageU][NF];
-            // Only loads here; whatever combines them (staged) runs at the
-            // LDS store, so all kStageU loads are in flight before the first wait.
+        if (E23 <= kStageCols * kSlThreads) {  // uniform
+            // Plane by plane: thread tid copies the plane positions r = tid +
+            // 256 j, whose wrapped (x2, x3) offsets are formed once; the plane
+            // offset is block-uniform.  A batch of kStageZ planes is straight-
+            // line code, all its loads in flight before the LDS stores: lanes
+            // past the plane or planes past the box load a duplicate node and
+            // store it to the spare node `cap`.
+            unsigned rc[kStageCols];
+            int rk[kStageCols];
 #pragma unroll
-            for (int u = 0; u < kStageU; ++u) {
-                if (k0 + u * kSlThreads < V) {
-                    const unsigned gi = (((unsigned)(lo1 + z) & m1) << g.s23) + (((unsigned)(lo2 + y) & m2) << g.s3) +
-                                        ((unsigned)(lo3 + x) & m3);
-                    op.stage(gi, v[u]);
-                }
-                // advance (z, y, x) by kSlThreads elements
-                x += dx;
-                y += dy;
-                z += dz;
-                if (x >= E3) {
-                    x -= E3;
-                    ++y;
-                }
-                if (y >= E2) {
-                    y -= E2;
-                    ++z;
-                }
+            for (int j = 0; j < kStageCols; ++j) {
+                const int r = (int)threadIdx.x + j * kSlThreads;
+                int x;
+                const int y = small_div(r, E3, rE3, x);
+                rc[j] = (((unsigned)(lo2 + y) & m2) << g.s3) | ((unsigned)(lo3 + x) & m3);
+                rk[j] = r < E23 ? r : -1;
             }
+            auto planes = [&](auto cols) {
+                constexpr int JJ = decltype(cols)::value;
+                unsigned src[JJ];
 #pragma unroll
-            for (int u = 0; u < kStageU; ++u) {
-                const int k = k0 + u * kSlThreads;
-                if (k < V) {
-                    op.staged(v[u]);
+                for (int j = 0; j < JJ; ++j) src[j] = rk[j] >= 0 ? rc[j] : rc[0];
+                for (int z0 = 0; z0 < E1; z0 += kStageZ) {
+                    T v[kStageZ][JJ][NF];
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) lds[box_at<NF>(k, f, cap)] = v[u][f];
+                    for (int zz = 0; zz < kStageZ; ++zz) {
+                        const int z = z0 + zz < E1 ? z0 + zz : E1 - 1;
+                        const unsigned plane = ((unsigned)(lo1 + z) & m1) << g.s23;
+#pragma unroll
+                        for (int j = 0; j < JJ; ++j) op.stage(plane, src[j], v[zz][j]);
+                    }
+#pragma unroll
+                    for (int zz = 0; zz < kStageZ; ++zz) {
+                        const int kz = z0 + zz < E1 ? (z0 + zz) * E23 : -1;
+#pragma unroll
+                        for (int j = 0; j < JJ; ++j) {
+                            op.staged(v[zz][j]);
+                            const int k = (kz >= 0 && rk[j] >= 0) ? kz + rk[j] : cap;
+#pragma unroll
+                            for (int f = 0; f < NF; ++f) lds[box_at<NF>(k, f, stride)] = v[zz][j][f];
+                        }
+                    }
+                }
+            };
+            if (E23 > kSlThreads)
+                planes(std::integral_constant<int, 2>{});
+            else
+                planes(std::integral_constant<int, 1>{});
+        } else {
+            // Wide planes: thread tid walks k = tid, tid + 256, ... with (z, y, x)
+            // carried incrementally (unwrapped as lo + (z, y, x)).
+            const float rE23 = 1.0f / (float)E23;
+            int rest, dx;
+            const int dz = small_div(kSlThreads, E23, rE23, rest), dy = small_div(rest, E3, rE3, dx);
+            int r0, x;
+            const int z = small_div((int)threadIdx.x, E23, rE23, r0), y = small_div(r0, E3, rE3, x);
+            int uz = lo1 + z, uy = lo2 + y, ux = lo3 + x;
+            const int hi2 = lo2 + E2, hi3 = lo3 + E3;
+            for (int k0 = threadIdx.x; k0 < V; k0 += kSlThreads * kStageU) {
+                T v[kStageU][NF];
+#pragma unroll
+                for (int u = 0; u < kStageU; ++u) {
+                    if (k0 + u * kSlThreads < V)
+                        op.stage(((unsigned)uz & m1) << g.s23, (((unsigned)uy & m2) << g.s3) | ((unsigned)ux & m3),
+                                 v[u]);
+                    ux += dx;
+                    uy += dy;
+                    uz += dz;
+                    if (ux >= hi3) {
+                        ux -= E3;
+                        ++uy;
+                    }
+                    if (uy >= hi2) {
+                        uy -= E2;
+                        ++uz;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStageU; ++u) {
+                    const int k = k0 + u * kSlThreads;
+                    if (k < V) {
+                        op.staged(v[u]);
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) lds[box_at<NF>(k, f, stride)] = v[u][f];
+                    }
                 }
             }
         }
@@ -401,7 +483,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
                 a1, a2, a3, base, E23, E3,
                 [&](int row, int r, T *v) {
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) v[f] = lds[box_at<NF>(row + r, f, cap)];
+                    for (int f = 0; f < NF; ++f) v[f] = lds[box_at<NF>(row + r, f, stride)];
                 },
                 acc);
             op.finish(tp.idx(g, p), pre[p], acc);
@@ -425,7 +507,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             contract<T, ORDER, NF>(
                 a1, a2, a3, o1, o2, o3,
                 [&](unsigned off, T *v) {
-                    op.stage(off, v);
+                    op.stage(0u, off, v);
                     op.staged(v);
                 },
                 acc);
@@ -495,10 +577,10 @@ struct DepartureOp {
         d[1] = sdt * ld<T>(v, N + i) * ih2;
         d[2] = sdt * ld<T>(v, 2 * N + i) * ih3;
     }
-    __device__ void stage(unsigned i, T *x) const {
-        x[0] = ld<T>(v, i);
-        x[1] = ld<T>(v, N + i);
-        x[2] = ld<T>(v, 2 * N + i);
+    __device__ void stage(unsigned pl, unsigned i, T *x) const {
+        x[0] = ld<T>(v + pl, i);
+        x[1] = ld<T>(v + N + pl, i);
+        x[2] = ld<T>(v + 2 * N + pl, i);
     }
     __device__ void staged(T *) const {}
     struct Pre {
@@ -525,7 +607,7 @@ struct InterpOp {
         d[1] = ld<T>(D, N + i);
         d[2] = ld<T>(D, 2 * N + i);
     }
-    __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(f, i); }
+    __device__ void stage(unsigned pl, unsigned i, T *x) const { x[0] = ld<T>(f + pl, i); }
     __device__ void staged(T *) const {}
     struct Pre {};
     __device__ Pre pre(unsigned) const { return Pre{}; }
@@ -548,9 +630,9 @@ struct AdjointOp {
         d[2] = ld<T>(Y, 2 * N + i);
     }
     // stage loads lambda and div v; staged forms the pair (lambda, lambda div v)
-    __device__ void stage(unsigned i, T *x) const {
-        x[0] = ld<T>(lin, i);
-        x[1] = ld<T>(dv, i);
+    __device__ void stage(unsigned pl, unsigned i, T *x) const {
+        x[0] = ld<T>(lin + pl, i);
+        x[1] = ld<T>(dv + pl, i);
     }
     __device__ void staged(T *x) const { x[1] = x[0] * x[1]; }
     struct Pre {
@@ -577,7 +659,7 @@ struct AdjointAccumOp {
     int nt;
     T a_end, a_mid;
     __device__ void disp(unsigned i, T *d) const { step.disp(i, d); }
-    __device__ void stage(unsigned i, T *x) const { step.stage(i, x); }
+    __device__ void stage(unsigned pl, unsigned i, T *x) const { step.stage(pl, i, x); }
     __device__ void staged(T *x) const { step.staged(x); }
     using Pre = typename AdjointOp<T, SL>::Pre;
     __device__ Pre pre(unsigned i) const { return step.pre(i); }
@@ -618,7 +700,7 @@ struct IncStateOp {
         d[1] = ld<T>(X, N + i);
         d[2] = ld<T>(X, 2 * N + i);
     }
-    __device__ void stage(unsigned i, T *x) const { x[0] = ld<T>(qin, i); }
+    __device__ void stage(unsigned pl, unsigned i, T *x) const { x[0] = ld<T>(qin + pl, i); }
     __device__ void staged(T *) const {}
     struct Pre {
         T f;
@@ -655,7 +737,7 @@ static inline unsigned blocks_for(long long n) { return (unsigned)((n + kSlThrea
 // at most 64 KB, and none when staging is switched off (g.lds_cap = 0).
 template <typename T, int NF>
 static int launch_cap(const PGrid &g, int box) {
-    const int hard = kLdsBytes / (NF * (int)sizeof(T));
+    const int hard = kLdsBytes / (NF * (int)sizeof(T)) - 1;  // and the spare node
     int cap = box < hard ? box : hard;
     return cap < g.lds_cap ? cap : g.lds_cap;
 }
@@ -663,7 +745,7 @@ static int launch_cap(const PGrid &g, int box) {
 template <typename T, int NF, int SHAPE, class Op>
 static void launch_sl_shape(const PGrid &g, int order, const Op &op, hipStream_t s) {
     const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
-    const size_t lds = (size_t)g.lds_cap * NF * sizeof(T);
+    const size_t lds = g.lds_cap > 0 ? (size_t)(g.lds_cap + 1) * NF * sizeof(T) : 0;
     if (order == 3)
         hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op);
     else
@@ -676,7 +758,6 @@ static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) 
     switch (g.shape) {
         case TILE_8x8x16: launch_sl_shape<T, NF, TILE_8x8x16>(g, order, op, s); break;
         case TILE_8x16x16: launch_sl_shape<T, NF, TILE_8x16x16>(g, order, op, s); break;
-        case TILE_4x8x16: launch_sl_shape<T, NF, TILE_4x8x16>(g, order, op, s); break;
         default: launch_sl_shape<T, NF, TILE_4x8x32>(g, order, op, s); break;
     }
 }
@@ -695,14 +776,12 @@ void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(3, TILE_8x8x16); break;
             case TILE_8x16x16: MIREG_BOX(3, TILE_8x16x16); break;
-            case TILE_4x8x16: MIREG_BOX(3, TILE_4x8x16); break;
             default: MIREG_BOX(3, TILE_4x8x32); break;
         }
     } else {
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(1, TILE_8x8x16); break;
             case TILE_8x16x16: MIREG_BOX(1, TILE_8x16x16); break;
-            case TILE_4x8x16: MIREG_BOX(1, TILE_4x8x16); break;
             default: MIREG_BOX(1, TILE_4x8x32); break;
         }
     }
