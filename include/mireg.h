@@ -10,7 +10,8 @@
  * where m solves dm/dt + grad m . v = 0, m(0) = mT, and w = div v.
  *
  * Conventions shared by every entry point:
- *  - Grid: n = (n1, n2, n3), each a power of two in [8, 512]; point
+ *  - Grid: n = (n1, n2, n3), each a power of two in [8, 512] or one of
+ *    48, 80, 96, 160 (radix-3 and radix-5 transforms); point
  *    (i1, i2, i3) sits at x_a = 2 pi i_a / n_a.  Scalar fields are dense
  *    C-ordered [n1][n2][n3] arrays (x3 fastest); vector fields are
  *    [3][n1][n2][n3].  Element type is the context's boundary type: float
@@ -68,7 +69,7 @@ typedef enum { MIREG_H1 = 1, MIREG_H2 = 2 } mireg_reg;
 typedef enum { MIREG_DIV_NONE = 0, MIREG_DIV_NEAR = 1, MIREG_DIV_LERAY = 2 } mireg_div;
 
 typedef struct {
-    int n[3];           /* grid size, powers of two in [8, 512] */
+    int n[3];           /* grid size: powers of two in [8, 512], or 48, 80, 96, 160 */
     int nt;             /* number of time steps (the paper uses 4), 1..64 */
     int interp_order;   /* 3: tricubic Lagrange (paper), 1: trilinear */
     int reg;            /* mireg_reg */
@@ -167,7 +168,8 @@ int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z);
  *    (F_H) pass unchanged.  eps_H is the tolerance of the enclosing PCG (1
  *    for mireg_precond_apply); max_inner caps the coarse iterations.  The
  *    coarse context (n/2 per axis, every axis >= 16) is created on first use.
- * kappa in (0, 1) (the paper: 0.1).  MIREG_E_SHAPE if the grid is too small. */
+ * kappa in (0, 1) (the paper: 0.1).  MIREG_E_SHAPE if the grid is too small
+ * or n/2 is not a supported size (48 and 80 have none). */
 typedef enum { MIREG_PC_SPECTRAL = 0, MIREG_PC_TWO_LEVEL = 1 } mireg_precond_kind;
 int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
 

@@ -23,12 +23,23 @@ namespace mireg {
 // ---------------------------------------------------------------------------
 constexpr int kLineThreads = 256;  // x3 passes
 constexpr int kColThreads = 512;   // strided passes: wide column tiles
+// Workgroup sizes: the above for power-of-two lines; for 3 2^a and 5 2^a
+// lines (fewer threads per line) as many lines as keep the LDS tile below
+// about 40 KB -- 64 x3 lines or 32 columns in FP32, half of that in FP64.
+template <typename T, int M>
+constexpr int line_threads() {
+    return is_pow2(M) ? kLineThreads : (sizeof(T) == 4 ? 64 : 32) * (M / FftCfg<T, M, 0>::EPT);
+}
+template <typename T, int L, int V>
+constexpr int col_threads() {
+    return is_pow2(L) ? kColThreads : (sizeof(T) == 4 ? 32 : 16) * (L / FftCfg<T, L, V>::EPT);
+}
 
 template <typename T, int M>
 __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
                                                          long long lines,
                                                          const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, M, 0, kLineThreads>;
+    using S = FftShape<T, M, 0, line_threads<T, M>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
     __shared__ cx<T> lds[Lay::size(M)];
@@ -50,7 +61,7 @@ __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtr
         for (int e = 0; e < EPT; ++e) {
             const int k = t + TPC * e;
             const cx<T> zk = lds[Lay::at(c, k)];
-            const cx<T> zm = conj(lds[Lay::at(c, (M - k) & (M - 1))]);
+            const cx<T> zm = conj(lds[Lay::at(c, (M - k) % M)]);
             const cx<T> E = scale(zk + zm, (T)0.5);
             const cx<T> O = scale(mul_mi(zk - zm), (T)0.5);
             out[k] = E + tw[k] * O;
@@ -66,7 +77,7 @@ template <typename T, int M>
 __global__ __launch_bounds__(kLineThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs dst,
                                                          long long lines,
                                                          const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, M, 0, kLineThreads>;
+    using S = FftShape<T, M, 0, line_threads<T, M>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
     __shared__ cx<T> lds[Lay::size(M)];
@@ -107,7 +118,7 @@ template <typename T, int L, int DIR>
 __global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
                                                           long long ostride, long long pstride,
                                                           const cx<T> *__restrict__ tw) {
-    using S = FftShape<T, L, 0, kColThreads>;
+    using S = FftShape<T, L, 0, col_threads<T, L, 0>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
@@ -204,7 +215,8 @@ template <typename T, int L, int KIND>
 __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q, OpConst<T> oc,
                                                        const cx<T> *__restrict__ tw) {
     constexpr int V = x1_variant<KIND>();
-    using S = FftShape<T, L, V, kColThreads>;
+    constexpr int NT = col_threads<T, L, V>();
+    using S = FftShape<T, L, V, NT>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
@@ -329,14 +341,14 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
     }
     if constexpr (KIND == SPEC_SCALE || KIND == SPEC_TAIL) {
         if (oc.red) {
-            __shared__ double red_sh[kColThreads / 64];
+            __shared__ double red_sh[NT / 64];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
             if ((threadIdx.x & 63) == 0) red_sh[threadIdx.x >> 6] = dacc;
             __syncthreads();
             if (threadIdx.x == 0) {
                 double tot = 0;
-                for (int w = 0; w < kColThreads / 64; ++w) tot += red_sh[w];
+                for (int w = 0; w < NT / 64; ++w) tot += red_sh[w];
                 oc.red[blockIdx.x] = tot;
             }
         }
@@ -382,7 +394,8 @@ template <typename T, int L, int PASS>
 __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc, T mu,
                                                            int first, const cx<T> *__restrict__ tw) {
     constexpr int V = 1;
-    using S = FftShape<T, L, V, kColThreads>;
+    constexpr int NT = col_threads<T, L, V>();
+    using S = FftShape<T, L, V, NT>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
@@ -474,14 +487,14 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
     }
     if constexpr (PASS == KP_HESS) {
         if (oc.red) {
-            __shared__ double red_sh[kColThreads / 64];
+            __shared__ double red_sh[NT / 64];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
             if ((threadIdx.x & 63) == 0) red_sh[threadIdx.x >> 6] = dacc;
             __syncthreads();
             if (threadIdx.x == 0) {
                 double tot = 0;
-                for (int w = 0; w < kColThreads / 64; ++w) tot += red_sh[w];
+                for (int w = 0; w < NT / 64; ++w) tot += red_sh[w];
                 oc.red[blockIdx.x] = tot * (double)oc.norm;
             }
         }
@@ -547,14 +560,34 @@ __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int 
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-#define MIREG_SWITCH_POW2(n, MACRO) \
+// x3 lines (n3 / 2) and strided lines (n1, n2) of the supported grids:
+// powers of two and 48, 80, 96, 160
+#define MIREG_SWITCH_LINE(n, MACRO) \
     switch (n) {                    \
         case 4: MACRO(4); break;    \
         case 8: MACRO(8); break;    \
         case 16: MACRO(16); break;  \
+        case 24: MACRO(24); break;  \
         case 32: MACRO(32); break;  \
+        case 40: MACRO(40); break;  \
+        case 48: MACRO(48); break;  \
         case 64: MACRO(64); break;  \
+        case 80: MACRO(80); break;  \
         case 128: MACRO(128); break;\
+        case 256: MACRO(256); break;\
+        default: break;             \
+    }
+#define MIREG_SWITCH_COL(n, MACRO)  \
+    switch (n) {                    \
+        case 8: MACRO(8); break;    \
+        case 16: MACRO(16); break;  \
+        case 32: MACRO(32); break;  \
+        case 48: MACRO(48); break;  \
+        case 64: MACRO(64); break;  \
+        case 80: MACRO(80); break;  \
+        case 96: MACRO(96); break;  \
+        case 128: MACRO(128); break;\
+        case 160: MACRO(160); break;\
         case 256: MACRO(256); break;\
         case 512: MACRO(512); break;\
         default: break;             \
@@ -567,11 +600,12 @@ static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
     HookScope hs(K_R2C, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
 #define MIREG_L(M)                                                                                     \
     {                                                                                                  \
-        constexpr int W = FftShape<T, M, 0, kLineThreads>::W;                                          \
+        constexpr int NT = line_threads<T, M>();                                                       \
+        constexpr int W = FftShape<T, M, 0, NT>::W;                                                    \
         dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);          \
+        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(NT), 0, s, src, dst, lines, tw);               \
     }
-    MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
+    MIREG_SWITCH_LINE(g.n3 / 2, MIREG_L)
 #undef MIREG_L
 }
 
@@ -582,11 +616,12 @@ static void launch_c2r(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
     HookScope hs(K_C2R, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
 #define MIREG_L(M)                                                                                     \
     {                                                                                                  \
-        constexpr int W = FftShape<T, M, 0, kLineThreads>::W;                                          \
+        constexpr int NT = line_threads<T, M>();                                                       \
+        constexpr int W = FftShape<T, M, 0, NT>::W;                                                    \
         dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(kLineThreads), 0, s, src, dst, lines, tw);     \
+        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(NT), 0, s, src, dst, lines, tw);               \
     }
-    MIREG_SWITCH_POW2(g.n3 / 2, MIREG_L)
+    MIREG_SWITCH_LINE(g.n3 / 2, MIREG_L)
 #undef MIREG_L
 }
 
@@ -597,12 +632,13 @@ static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipSt
     HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
 #define MIREG_L(L)                                                                           \
     {                                                                                        \
-        constexpr int W = FftShape<T, L, 0, kColThreads>::W;                                 \
+        constexpr int NT = col_threads<T, L, 0>();                                           \
+        constexpr int W = FftShape<T, L, 0, NT>::W;                                          \
         dim3 grid((unsigned)((Q + W - 1) / W), nf);                                          \
-        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kColThreads), 0, s, f, Q, inner, \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, inner,       \
                            ostride, pstride, tw);                                            \
     }
-    MIREG_SWITCH_POW2(g.n2, MIREG_L)
+    MIREG_SWITCH_COL(g.n2, MIREG_L)
 #undef MIREG_L
 }
 
@@ -614,12 +650,13 @@ static int launch_x1(const Grid &g, FieldPtrs f, int nin, int nout, const OpCons
     int blocks = 0;
 #define MIREG_L(L)                                                                              \
     {                                                                                           \
-        constexpr int W = FftShape<T, L, x1_variant<KIND>(), kColThreads>::W;                   \
+        constexpr int NT = col_threads<T, L, x1_variant<KIND>()>();                             \
+        constexpr int W = FftShape<T, L, x1_variant<KIND>(), NT>::W;                            \
         dim3 grid((unsigned)((Q + W - 1) / W));                                                 \
         blocks = (int)grid.x;                                                                   \
-        hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(kColThreads), 0, s, f, Q, oc, tw); \
+        hipLaunchKernelGGL((k_x1_op<T, L, KIND>), grid, dim3(NT), 0, s, f, Q, oc, tw);          \
     }
-    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+    MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
     return blocks;
 }
@@ -695,11 +732,12 @@ static void launch_x1_fft(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, h
     HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
 #define MIREG_L(L)                                                                                          \
     {                                                                                                       \
-        constexpr int W = FftShape<T, L, 0, kColThreads>::W;                                                \
+        constexpr int NT = col_threads<T, L, 0>();                                                          \
+        constexpr int W = FftShape<T, L, 0, NT>::W;                                                         \
         dim3 grid((unsigned)((Q + W - 1) / W), nf);                                                         \
-        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(kColThreads), 0, s, f, Q, Q, 0LL, Q, tw);  \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, Q, 0LL, Q, tw);           \
     }
-    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+    MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
 }
 
@@ -746,12 +784,13 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
     HookScope hs(K_X1_KRYLOV, fields * 2.0 * sizeof(T) * g.NS);
 #define MIREG_L(L)                                                                                       \
     {                                                                                                    \
-        constexpr int W = FftShape<T, L, 1, kColThreads>::W;                                             \
+        constexpr int NT = col_threads<T, L, 1>();                                                       \
+        constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
         dim3 grid((unsigned)((Q + W - 1) / W));                                                          \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(kColThreads), 0, s, f, Q, oc, mu, first, tw); \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, first, tw);    \
     }
-    MIREG_SWITCH_POW2(g.n1, MIREG_L)
+    MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
 }
 

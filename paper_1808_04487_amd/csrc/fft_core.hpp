@@ -1,6 +1,6 @@
 // Register/LDS building blocks of the pencil FFT passes.
 //
-// A line of length L (a power of two) is held by TPC = L/EPT threads; thread
+// A line of length L (2^a, 3 2^a or 5 2^a) is held by TPC = L/EPT threads; thread
 // t keeps the elements at positions t + TPC*e, e = 0..EPT-1, in registers.
 // The transform is a mixed-radix Stockham sequence (radices R0, R1, R2 from
 // FftCfg): every stage takes butterflies j = t + TPC*b, reads inputs
@@ -37,11 +37,45 @@ __host__ __device__ constexpr double cos16(int j) {
 }
 __host__ __device__ constexpr double sin16(int j) { return cos16(j - 4); }
 
-// w_R^p = exp(DIR * 2 pi i p / R) for R dividing 16 (DIR = -1 forward).
+// cos / sin of 2 pi j / 6 and 2 pi j / 10, exact to double rounding.
+__host__ __device__ constexpr double cos6(int j) {
+    return (j % 6 == 0) ? 1.0 : (j % 6 == 1 || j % 6 == 5) ? 0.5 : (j % 6 == 3) ? -1.0 : -0.5;
+}
+__host__ __device__ constexpr double sin6(int j) {
+    return (j % 6 == 0 || j % 6 == 3) ? 0.0
+           : (j % 6 == 1 || j % 6 == 2) ? 0.86602540378443864676
+                                         : -0.86602540378443864676;
+}
+__host__ __device__ constexpr double cos10(int j) {
+    return (j % 10 == 0)                    ? 1.0
+           : (j % 10 == 1 || j % 10 == 9)   ? 0.80901699437494742410
+           : (j % 10 == 2 || j % 10 == 8)   ? 0.30901699437494742410
+           : (j % 10 == 3 || j % 10 == 7)   ? -0.30901699437494742410
+           : (j % 10 == 4 || j % 10 == 6)   ? -0.80901699437494742410
+                                            : -1.0;
+}
+__host__ __device__ constexpr double sin10(int j) {
+    return (j % 10 == 0 || j % 10 == 5)   ? 0.0
+           : (j % 10 == 1 || j % 10 == 4) ? 0.58778525229247312917
+           : (j % 10 == 2 || j % 10 == 3) ? 0.95105651629515357212
+           : (j % 10 == 6 || j % 10 == 9) ? -0.58778525229247312917
+                                          : -0.95105651629515357212;
+}
+
+// w_R^p = exp(DIR * 2 pi i p / R) for R dividing 16, 6 or 10 (DIR = -1 forward).
 template <typename T, int R, int DIR>
 __device__ __forceinline__ cx<T> root(int p) {
-    const int j = (p * (16 / R)) & 15;
-    return make_cx<T>((T)cos16(j), (T)(DIR * sin16(j)));
+    if constexpr (16 % R == 0) {
+        const int j = (p * (16 / R)) & 15;
+        return make_cx<T>((T)cos16(j), (T)(DIR * sin16(j)));
+    } else if constexpr (6 % R == 0) {
+        const int j = (p * (6 / R)) % 6;
+        return make_cx<T>((T)cos6(j), (T)(DIR * sin6(j)));
+    } else {
+        static_assert(10 % R == 0, "unsupported root of unity");
+        const int j = (p * (10 / R)) % 10;
+        return make_cx<T>((T)cos10(j), (T)(DIR * sin10(j)));
+    }
 }
 
 // In-register DFT of length R in {1, 2, 4, 8, 16}, natural order in and out.
@@ -116,6 +150,62 @@ struct Dft<T, 8, DIR> {
     }
 };
 
+// Odd radices: the DFT of length 3 and 5 written out with the real and
+// imaginary parts of their roots, and 6 = 2 x 3, 10 = 2 x 5 by one radix-2
+// step over two odd-length DFTs (even and odd inputs).
+template <typename T, int DIR>
+struct Dft<T, 3, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        const cx<T> s = x[1] + x[2], d = x[1] - x[2];
+        const cx<T> a = x[0] - scale(s, (T)0.5);
+        const cx<T> id = (DIR < 0) ? mul_mi(d) : mul_i(d);
+        const cx<T> b = scale(id, (T)0.86602540378443864676);
+        x[0] = x[0] + s;
+        x[1] = a + b;
+        x[2] = a - b;
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 5, DIR> {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        constexpr T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        constexpr T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        const cx<T> a1 = x[1] + x[4], b1 = x[1] - x[4], a2 = x[2] + x[3], b2 = x[2] - x[3];
+        const cx<T> p1 = x[0] + scale(a1, c1) + scale(a2, c2);
+        const cx<T> p2 = x[0] + scale(a1, c2) + scale(a2, c1);
+        const cx<T> q1 = scale(b1, s1) + scale(b2, s2), q2 = scale(b1, s2) - scale(b2, s1);
+        const cx<T> iq1 = (DIR < 0) ? mul_mi(q1) : mul_i(q1), iq2 = (DIR < 0) ? mul_mi(q2) : mul_i(q2);
+        x[0] = x[0] + a1 + a2;
+        x[1] = p1 + iq1;
+        x[4] = p1 - iq1;
+        x[2] = p2 + iq2;
+        x[3] = p2 - iq2;
+    }
+};
+template <typename T, int Q, int DIR>
+struct DftTwoOdd {
+    static __device__ __forceinline__ void run(cx<T> *x) {
+        cx<T> e[Q], o[Q];
+#pragma unroll
+        for (int n = 0; n < Q; ++n) {
+            e[n] = x[2 * n];
+            o[n] = x[2 * n + 1];
+        }
+        Dft<T, Q, DIR>::run(e);
+        Dft<T, Q, DIR>::run(o);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const cx<T> t = k == 0 ? o[0] : o[k] * root<T, 2 * Q, DIR>(k);
+            x[k] = e[k] + t;
+            x[k + Q] = e[k] - t;
+        }
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 6, DIR> : DftTwoOdd<T, 3, DIR> {};
+template <typename T, int DIR>
+struct Dft<T, 10, DIR> : DftTwoOdd<T, 5, DIR> {};
+
 // Elements per thread and radices per line length, in two variants: V = 0
 // (16 elements per thread for FP32 at L >= 128) and V = 1 (at most 8, for
 // kernels that keep several lines in registers).  Every radix divides EPT
@@ -152,8 +242,20 @@ MIREG_FFTCFG2(double, 64, 8, 8, 8, 1)
 MIREG_FFTCFG2(double, 128, 8, 8, 4, 4)
 MIREG_FFTCFG2(double, 256, 8, 8, 8, 4)
 MIREG_FFTCFG2(double, 512, 8, 8, 8, 8)
+// 3 2^a and 5 2^a (grids of 48, 80, 96 and 160 points per axis and their
+// half-length x3 lines); one configuration for both variants
+#define MIREG_FFTCFG_T(LL, E, A, B, C) MIREG_FFTCFG2(float, LL, E, A, B, C) MIREG_FFTCFG2(double, LL, E, A, B, C)
+MIREG_FFTCFG_T(24, 12, 4, 6, 1)
+MIREG_FFTCFG_T(40, 20, 4, 10, 1)
+MIREG_FFTCFG_T(48, 12, 4, 4, 3)
+MIREG_FFTCFG_T(80, 20, 4, 4, 5)
+MIREG_FFTCFG_T(96, 12, 4, 4, 6)
+MIREG_FFTCFG_T(160, 20, 4, 4, 10)
+#undef MIREG_FFTCFG_T
 #undef MIREG_FFTCFG2
 #undef MIREG_FFTCFG
+
+__host__ __device__ constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // Register array of one thread's share of a line.
 template <typename T, int L, int V>
@@ -194,7 +296,7 @@ __device__ __forceinline__ void stockham_stage(Regs<T, L, V> &reg, int t, int c,
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + TPC * b;
-        const int k = j & (NS - 1);
+        const int k = j % NS;
         cx<T> v[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = reg[b + m * NB];
@@ -217,7 +319,7 @@ __device__ __forceinline__ void stockham_stage(Regs<T, L, V> &reg, int t, int c,
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = t + TPC * b;
-            const int k = j & (NS - 1);
+            const int k = j % NS;
             const int base = (j / NS) * NS * R + k;
 #pragma unroll
             for (int m = 0; m < R; ++m) lds[Lay::at(c, base + m * NS)] = out[b + m * NB];

@@ -26,7 +26,11 @@ using namespace mireg;
 
 namespace {
 
-bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+// Axis lengths the FFT passes and transport kernels support: powers of two
+// in [8, 512] and 48, 80, 96, 160 (3 and 5 times a power of two).
+bool supported_axis(int n) {
+    return (n >= 8 && n <= 512 && (n & (n - 1)) == 0) || n == 48 || n == 80 || n == 96 || n == 160;
+}
 
 struct Timers {
     bool on = false;
@@ -1166,7 +1170,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!p || !out) return MIREG_E_ARG;
     *out = nullptr;
     for (int a = 0; a < 3; ++a)
-        if (!pow2_in_range(p->n[a])) return MIREG_E_SHAPE;
+        if (!supported_axis(p->n[a])) return MIREG_E_SHAPE;
     if (p->nt < 1 || p->nt > 64 || (p->interp_order != 1 && p->interp_order != 3) ||
         (p->reg != MIREG_H1 && p->reg != MIREG_H2) || p->div < 0 || p->div > 2 || !(p->beta_v > 0) ||
         !(p->beta_w >= 0) || (p->div == MIREG_DIV_NEAR && !(p->beta_w > 0)) ||
@@ -1320,8 +1324,10 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner) {
     if (kind != MIREG_PC_SPECTRAL && kind != MIREG_PC_TWO_LEVEL) return ctx->fail(MIREG_E_ARG, "unknown preconditioner");
     if (!(kappa > 0 && kappa < 1) || max_inner < 1) return ctx->fail(MIREG_E_ARG, "kappa must be in (0, 1), max_inner >= 1");
     if (kind == MIREG_PC_TWO_LEVEL && !ctx->coarse) {
-        if (ctx->g.n1 < 16 || ctx->g.n2 < 16 || ctx->g.n3 < 16)
-            return ctx->fail(MIREG_E_SHAPE, "the two-level preconditioner needs at least 16 points per axis");
+        if (ctx->g.n1 < 16 || ctx->g.n2 < 16 || ctx->g.n3 < 16 || !supported_axis(ctx->g.n1 / 2) ||
+            !supported_axis(ctx->g.n2 / 2) || !supported_axis(ctx->g.n3 / 2))
+            return ctx->fail(MIREG_E_SHAPE,
+                             "the two-level preconditioner needs at least 16 points per axis and a supported n/2");
         mireg_params p = ctx->p;
         p.n[0] = ctx->g.n1 / 2;
         p.n[1] = ctx->g.n2 / 2;

@@ -1,7 +1,7 @@
 // Semi-Lagrangian transport kernels (Sec. 2.3.1, Sec. 3.4) for gfx950.
 //
 // Off-grid values are third-degree Lagrange polynomials on a 4x4x4 stencil
-// (trilinear on 2x2x2), periodic on power-of-two grids.  Departure points are
+// (trilinear on 2x2x2), periodic.  Departure points are
 // stored as displacements in cell units, so t = d - floor(d) keeps full
 // precision in FP32 anywhere on the grid.
 //
@@ -29,10 +29,11 @@ namespace mireg {
 
 struct PGrid {
     int n1, n2, n3;
-    int s3, s23;  // log2(n3), log2(n2 n3)
+    int n23;      // n2 n3
+    unsigned m1, m2, m3;  // n_a - 1 on power-of-two axes, 0 on the others
     long long N;
-    int tx, ty, tz;  // tiles per axis (powers of two)
-    int ltx, lty;    // log2(tx), log2(ty)
+    int tx, ty, tz;  // tiles per axis
+    int ltx, lty;    // log2(tx), log2(ty) when both are powers of two, else -1
     int lds_cap;     // largest box (nodes) staged in LDS in this launch; 0 disables staging
     int shape;       // tile shape (SlTile)
 };
@@ -72,8 +73,11 @@ static PGrid pgrid(const Grid &g) {
     p.n1 = g.n1;
     p.n2 = g.n2;
     p.n3 = g.n3;
-    p.s3 = __builtin_ctz((unsigned)g.n3);
-    p.s23 = p.s3 + __builtin_ctz((unsigned)g.n2);
+    p.n23 = g.n2 * g.n3;
+    auto mask = [](int n) { return (n & (n - 1)) == 0 ? (unsigned)(n - 1) : 0u; };
+    p.m1 = mask(g.n1);
+    p.m2 = mask(g.n2);
+    p.m3 = mask(g.n3);
     p.N = g.N;
     p.shape = g.sl_tile;
     int TZ = 8, TY = 8, TX = 16;
@@ -85,8 +89,9 @@ static PGrid pgrid(const Grid &g) {
     p.tx = (g.n3 + TX - 1) / TX;
     p.ty = (g.n2 + TY - 1) / TY;
     p.tz = (g.n1 + TZ - 1) / TZ;
-    p.ltx = __builtin_ctz((unsigned)p.tx);
-    p.lty = __builtin_ctz((unsigned)p.ty);
+    const bool pow2_tiles = (p.tx & (p.tx - 1)) == 0 && (p.ty & (p.ty - 1)) == 0;
+    p.ltx = pow2_tiles ? __builtin_ctz((unsigned)p.tx) : -1;
+    p.lty = pow2_tiles ? __builtin_ctz((unsigned)p.ty) : -1;
     p.lds_cap = g.lds_cap;
     return p;
 }
@@ -249,6 +254,13 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// a mod n (Euclidean) for any a; mask = n - 1 when n is a power of two, else 0.
+__device__ __forceinline__ unsigned wrap(int a, int n, unsigned mask) {
+    if (mask) return (unsigned)a & mask;
+    const int r = a % n;
+    return (unsigned)(r < 0 ? r + n : r);
+}
+
 // Point p of a thread in its tile: tile-local linear index tid + 256 p, x3
 // fastest.  Shared by the transport kernels and the box measurement, so both
 // see the same tiles.
@@ -259,7 +271,16 @@ struct TilePoints {
     static constexpr int ZSTEP = kSlThreads / (TX * TY);
     int i1_0, i2, i3;  // grid index of point 0 (i1 advances by ZSTEP per point)
     __device__ TilePoints(const PGrid &g, int tile) {
-        const int bx = tile & (g.tx - 1), by = (tile >> g.ltx) & (g.ty - 1), bz = tile >> (g.ltx + g.lty);
+        int bx, by, bz;
+        if (g.ltx >= 0) {
+            bx = tile & (g.tx - 1);
+            by = (tile >> g.ltx) & (g.ty - 1);
+            bz = tile >> (g.ltx + g.lty);
+        } else {
+            bx = tile % g.tx;
+            by = (tile / g.tx) % g.ty;
+            bz = tile / (g.tx * g.ty);
+        }
         i3 = bx * TX + (int)threadIdx.x % TX;
         i2 = by * TY + ((int)threadIdx.x / TX) % TY;
         i1_0 = bz * TZ + (int)threadIdx.x / (TX * TY);
@@ -267,7 +288,7 @@ struct TilePoints {
     __device__ int i1(int p) const { return i1_0 + p * ZSTEP; }
     __device__ bool ok(const PGrid &g, int p) const { return i1(p) < g.n1 && i2 < g.n2 && i3 < g.n3; }
     __device__ unsigned idx(const PGrid &g, int p) const {
-        return ((unsigned)i1(p) << g.s23) + ((unsigned)i2 << g.s3) + (unsigned)i3;
+        return __umul24((unsigned)i1(p), (unsigned)g.n23) + __umul24((unsigned)i2, (unsigned)g.n3) + (unsigned)i3;
     }
 };
 
@@ -380,7 +401,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
         //    (vol <= cap < 2^16).
         const int E1 = (int)e1, E2 = (int)e2, E3 = (int)e3, E23 = E2 * E3, V = (int)vol;
         const float rE3 = 1.0f / (float)E3;
-        const unsigned m1 = g.n1 - 1, m2 = g.n2 - 1, m3 = g.n3 - 1;
+        const unsigned n23 = (unsigned)g.n23, n3 = (unsigned)g.n3;
         if (E23 <= kStageCols * kSlThreads) {  // uniform
             // Plane by plane: thread tid copies the plane positions r = tid +
             // 256 j, whose wrapped (x2, x3) offsets are formed once; the plane
@@ -395,7 +416,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
                 const int r = (int)threadIdx.x + j * kSlThreads;
                 int x;
                 const int y = small_div(r, E3, rE3, x);
-                rc[j] = (((unsigned)(lo2 + y) & m2) << g.s3) | ((unsigned)(lo3 + x) & m3);
+                rc[j] = __umul24(wrap(lo2 + y, g.n2, g.m2), n3) + wrap(lo3 + x, g.n3, g.m3);
                 rk[j] = r < E23 ? r : -1;
             }
             auto planes = [&](auto cols) {
@@ -408,7 +429,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
 #pragma unroll
                     for (int zz = 0; zz < kStageZ; ++zz) {
                         const int z = z0 + zz < E1 ? z0 + zz : E1 - 1;
-                        const unsigned plane = ((unsigned)(lo1 + z) & m1) << g.s23;
+                        const unsigned plane = __umul24(wrap(lo1 + z, g.n1, g.m1), n23);
 #pragma unroll
                         for (int j = 0; j < JJ; ++j) op.stage(plane, src[j], v[zz][j]);
                     }
@@ -444,8 +465,8 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
 #pragma unroll
                 for (int u = 0; u < kStageU; ++u) {
                     if (k0 + u * kSlThreads < V)
-                        op.stage(((unsigned)uz & m1) << g.s23, (((unsigned)uy & m2) << g.s3) | ((unsigned)ux & m3),
-                                 v[u]);
+                        op.stage(__umul24(wrap(uz, g.n1, g.m1), n23),
+                                 __umul24(wrap(uy, g.n2, g.m2), n3) + wrap(ux, g.n3, g.m3), v[u]);
                     ux += dx;
                     uy += dy;
                     uz += dz;
@@ -499,9 +520,9 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             unsigned o1[NP], o2[NP], o3[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                o1[k] = ((unsigned)(b1[p] + FIRST + k) & (unsigned)(g.n1 - 1)) << g.s23;
-                o2[k] = ((unsigned)(b2[p] + FIRST + k) & (unsigned)(g.n2 - 1)) << g.s3;
-                o3[k] = (unsigned)(b3[p] + FIRST + k) & (unsigned)(g.n3 - 1);
+                o1[k] = __umul24(wrap(b1[p] + FIRST + k, g.n1, g.m1), (unsigned)g.n23);
+                o2[k] = __umul24(wrap(b2[p] + FIRST + k, g.n2, g.m2), (unsigned)g.n3);
+                o3[k] = wrap(b3[p] + FIRST + k, g.n3, g.m3);
             }
             T acc[NF];
             contract<T, ORDER, NF>(
