@@ -22,9 +22,9 @@ FP16) is timed on the same inputs and reported in "precision_variant".
 "two_level" repeats the timed solves with the two-level coarse-grid
 preconditioner (coarse grid 128^3, nested CG to kappa times the PCG
 tolerance; kappa 0.1 as in the paper, and 0.5).
-"batched" solves 16 pairs at 64^3 and 12 at 128^3 (the power-of-two members
-of the uneven batch) with four concurrent streams, graph-captured matvecs and
-autotuned tiles, against one stream without either.
+"batched" solves the uneven batch -- 16 pairs at 64^3, 16 at 96^3, 12 at
+128^3 and 4 at 160^3 -- with four concurrent streams, graph-captured matvecs
+and autotuned tiles, against one stream without either.
 "warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
 trained network's prediction (paper_1808_04487_amd/weights) to the same
 absolute gradient tolerance.
@@ -201,10 +201,10 @@ def batched_eval(args, torch):
     graphs, autotuner); each configuration runs once untimed first."""
     from paper_1808_04487_amd import batch
 
-    sizes = [64] * 16 + [128] * 12
+    sizes = batch.UNEVEN_BATCH
     pairs = batch.make_pairs(sizes)
-    out = {"workload": "16 pairs at 64^3 + 12 at 128^3, seeds (100+2p, 101+2p), amplitude U[0.05, 0.2] 2 pi; "
-                       "H1-div beta_v=5e-3, eps_g=5e-2", "pairs": len(sizes),
+    out = {"workload": "16 pairs at 64^3, 16 at 96^3, 12 at 128^3, 4 at 160^3, seeds (100+2p, 101+2p), "
+                       "amplitude U[0.05, 0.2] 2 pi; H1-div beta_v=5e-3, eps_g=5e-2", "pairs": len(sizes),
            "points": int(sum(n ** 3 for n in sizes))}
     for key, kw in (("sequential", dict(workers=1, graphs=False, autotune=False)),
                     ("batched", dict(workers=4, graphs=True, autotune=True))):

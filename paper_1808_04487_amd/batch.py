@@ -9,11 +9,11 @@ captured HIP graph and picks its transport tile shape with the autotuner
 after its first solve; neither changes a result bit, so a batched solve
 returns exactly what solving the pairs one by one returns.
 
-Pairs of the batch workload (power-of-two sizes): pair p has its phantom
-from seed 100 + 2p (periodic Voronoi, 120 seeds, Gaussian of 2 cells,
-rescaled to [0, 1]) and its velocity from seed 101 + 2p (Gaussian-filtered
-white noise of physical width pi/4, Leray, max |v| drawn from
-U[0.05, 0.2] 2 pi by a generator seeded with 7).
+The uneven batch: 16 pairs at 64^3, 16 at 96^3, 12 at 128^3 and 4 at 160^3,
+in that order.  Pair p has its phantom from seed 100 + 2p (periodic Voronoi,
+120 seeds, Gaussian of 2 cells, rescaled to [0, 1]) and its velocity from
+seed 101 + 2p (Gaussian-filtered white noise of physical width pi/4, Leray,
+max |v| drawn from U[0.05, 0.2] 2 pi by a generator seeded with 7).
 """
 import math
 import queue
@@ -26,6 +26,7 @@ import torch
 from . import mireg, synth
 
 TWO_PI = 2.0 * math.pi
+UNEVEN_BATCH = [64] * 16 + [96] * 16 + [128] * 12 + [160] * 4
 SOLVER = dict(nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
 
 
