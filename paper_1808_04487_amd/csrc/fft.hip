@@ -390,6 +390,7 @@ struct KrylovPtrs {
 //   KP_HESS: o = alpha a(k) a_in + K F b, with F b from w;       red: sum_x s . Hs
 //   KP_DIR:  o = M^{-1}(k) a_in + mu o (o not read if first); w = x1 inverse of o / N
 //   KP_INV:  w = x1 inverse of a_in / N
+// KP_FWD, KP_DIR and KP_INV treat component blockIdx.y; KP_HESS all three.
 template <typename T, int L, int PASS>
 __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc, T mu,
                                                            int first, const cx<T> *__restrict__ tw) {
@@ -433,7 +434,8 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
     double dacc = 0;
     const double wk3 = (i3 == 0 || 2 * i3 == oc.n3) ? 1.0 : 2.0;
     if constexpr (PASS == KP_FWD) {
-        for (int a = 0; a < 3; ++a) {
+        {
+            const int a = blockIdx.y;
             load(f.w[a], reg);
             fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
             store(f.o[a], reg);
@@ -461,7 +463,8 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
             store(f.o[a], reg);
         }
     } else if constexpr (PASS == KP_DIR) {
-        for (int a = 0; a < 3; ++a) {
+        {
+            const int a = blockIdx.y;
             cx<T> rh[EPT];
             load(f.a[a], rh);
             if (!first) load(f.o[a], reg);
@@ -477,7 +480,8 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
             store(f.w[a], reg);
         }
     } else {
-        for (int a = 0; a < 3; ++a) {
+        {
+            const int a = blockIdx.y;
             load(f.a[a], reg);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], oc.norm);
@@ -786,7 +790,7 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
     {                                                                                                    \
         constexpr int NT = col_threads<T, L, 1>();                                                       \
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
-        dim3 grid((unsigned)((Q + W - 1) / W));                                                          \
+        dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
         if (blocks) *blocks = (int)grid.x;                                                               \
         hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, first, tw);    \
     }

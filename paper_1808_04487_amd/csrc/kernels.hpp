@@ -120,10 +120,10 @@ void spectral_resample(const Grid &gs, const Grid &gd, int nf, const T *const *i
 // global memory, so any value is correct and only the speed depends on it.
 
 // *out (device) = largest stencil box over the transport tiles for the
-// displacement (a D_a) b_a in cell units.
+// displacement (a D_a) b_a in cell units; slots: 1024 device words of scratch.
 template <typename T>
 void sl_box_volume(const Grid &g, int order, const T *D, double a, const double b[3], unsigned *out,
-                   hipStream_t s);
+                   unsigned *slots, hipStream_t s);
 // disp = sign dt/2 (v + I[v](x + sign dt v)) / h  (cell units); the
 // predictor displacement is (sign dt v_a) n_a / (2 pi)
 template <typename T>

@@ -318,7 +318,9 @@ template <typename T>
 int measure_box(mireg_ctx *ctx, const T *D, double a, const double b[3]) {
     if (ctx->g.lds_cap == 0) return 0;
     unsigned *dev = reinterpret_cast<unsigned *>(ctx->dres);
-    sl_box_volume<T>(ctx->g, ctx->p.interp_order, D, a, b, dev, ctx->stream);
+    // the reduction partials (4 kRedBlocks doubles) serve as the 1024 slots
+    sl_box_volume<T>(ctx->g, ctx->p.interp_order, D, a, b, dev, reinterpret_cast<unsigned *>(ctx->partials),
+                     ctx->stream);
     if (readback(ctx, 1) != MIREG_OK) return INT_MAX;  // every tile then takes the largest LDS
     unsigned v = 0;
     memcpy(&v, ctx->hres, sizeof v);

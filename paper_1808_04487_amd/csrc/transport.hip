@@ -539,10 +539,12 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
 
 // Largest stencil box (nodes) over the tiles of k_sl for the displacement
 // d_a = (a_a D_a) b_a, the same expression the step operators evaluate:
-// one block per tile, atomic maximum into *out.
+// one block per tile, atomic maximum into one of kBoxSlots slots (so that
+// the blocks do not all serialise on one address), then k_max_slots.
+constexpr int kBoxSlots = 1024;
 template <typename T, int ORDER, int SHAPE>
 __global__ __launch_bounds__(kSlThreads) void k_box(PGrid g, const T *__restrict__ D, T a, T b1, T b2, T b3,
-                                                    unsigned *__restrict__ out) {
+                                                    unsigned *__restrict__ slots) {
     using TP = TilePoints<SHAPE>;
     constexpr int NP = AxisW<T, ORDER>::NP;
     __shared__ int box[6];
@@ -573,12 +575,24 @@ __global__ __launch_bounds__(kSlThreads) void k_box(PGrid g, const T *__restrict
     if (threadIdx.x == 0) {
         const long long vol = ((long long)box[3] - box[0] + NP) * ((long long)box[4] - box[1] + NP) *
                               ((long long)box[5] - box[2] + NP);
-        atomicMax(out, (unsigned)(vol < (long long)UINT_MAX ? vol : (long long)UINT_MAX));
+        atomicMax(&slots[blockIdx.x & (kBoxSlots - 1)], (unsigned)(vol < (long long)UINT_MAX ? vol : (long long)UINT_MAX));
     }
 }
 
-__global__ void k_set_u32(unsigned *p, unsigned v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ __launch_bounds__(256) void k_zero_slots(unsigned *slots) {
+    slots[blockIdx.x * 256 + threadIdx.x] = 0u;
+}
+
+// out[0] = max of the kBoxSlots slots (one workgroup)
+__global__ __launch_bounds__(256) void k_max_slots(const unsigned *__restrict__ slots, unsigned *__restrict__ out) {
+    __shared__ unsigned sh[4];
+    unsigned m = 0;
+    for (int i = threadIdx.x; i < kBoxSlots; i += 256) m = max(m, slots[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
 }
 
 // ---------------------------------------------------------------------------
@@ -785,14 +799,14 @@ static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) 
 
 template <typename T>
 void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double b[3], unsigned *out,
-                   hipStream_t s) {
+                   unsigned *slots, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_VECTOR, 3.0 * sizeof(T) * g.N);
     const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, out, 0u);
+    hipLaunchKernelGGL(k_zero_slots, dim3(kBoxSlots / 256), dim3(256), 0, s, slots);
 #define MIREG_BOX(ORD, SH)                                                                                     \
     hipLaunchKernelGGL((k_box<T, ORD, SH>), dim3(nb), dim3(kSlThreads), 0, s, g, D, (T)a, (T)b[0], (T)b[1], \
-                       (T)b[2], out)
+                       (T)b[2], slots)
     if (order == 3) {
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(3, TILE_8x8x16); break;
@@ -807,6 +821,7 @@ void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double
         }
     }
 #undef MIREG_BOX
+    hipLaunchKernelGGL(k_max_slots, dim3(1), dim3(256), 0, s, slots, out);
 }
 
 template <typename T>
@@ -872,7 +887,7 @@ void incstate_step(const Grid &gg, int order, double coef, double sign, const S 
     template void departure<T>(const Grid &, int, int, double, const T *, T *, int, hipStream_t);        \
     template void interp_field<T, T, T>(const Grid &, int, const T *, const T *, T *, int, hipStream_t); \
     template void sl_box_volume<T>(const Grid &, int, const T *, double, const double *, unsigned *,     \
-                                   hipStream_t);
+                                   unsigned *, hipStream_t);
 #define MIREG_INST(T, S)                                                                                  \
     template void adjoint_init<T, S>(const Grid &, const T *, const T *, S *, hipStream_t);              \
     template void adjoint_step<T, S>(const Grid &, int, double, const S *, const T *, const T *, S *,    \
