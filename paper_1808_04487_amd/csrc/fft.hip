@@ -385,15 +385,23 @@ struct KrylovPtrs {
     void *o[3];        // spectral output (read first in KP_DIR)
 };
 
-// x1 passes of the Krylov iteration:
+// x1 passes of the Krylov iteration (flags: KF_*, kernels.hpp):
 //   KP_FWD:  o = x1 forward transform of w                      (F u from the x2/x3 spectra)
 //   KP_HESS: o = alpha a(k) a_in + K F b, with F b from w;       red: sum_x s . Hs
-//   KP_DIR:  o = M^{-1}(k) a_in + mu o (o not read if first); w = x1 inverse of o / N
+//            KF_SQRT: the symmetrically scaled operator c (alpha a(k) c a_in + K F b),
+//            c = (alpha a(k))^{-1/2} (1 at k = 0), F b being the transport of c a_in
+//   KP_DIR:  o = z + mu o (o not read with KF_FIRST), z = M^{-1}(k) a_in, or a_in
+//            with KF_ZRAW; w = x1 inverse of o / N (of c o / N with KF_SQRT)
 //   KP_INV:  w = x1 inverse of a_in / N
 // KP_FWD, KP_DIR and KP_INV treat component blockIdx.y; KP_HESS all three.
+template <typename T>
+__device__ __forceinline__ T ainv_sqrt_symbol(const Mode<T> &m, const OpConst<T> &oc) {
+    return ksq(m) == (T)0 ? (T)1 : (T)1 / sqrt(oc.alpha * reg_symbol(m, oc.reg));
+}
 template <typename T, int L, int PASS>
 __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc, T mu,
-                                                           int first, const cx<T> *__restrict__ tw) {
+                                                           int flags, const cx<T> *__restrict__ tw) {
+    const bool first = flags & KF_FIRST, sqrt_scaled = flags & KF_SQRT, zraw = flags & KF_ZRAW;
     constexpr int V = 1;
     constexpr int NT = col_threads<T, L, V>();
     using S = FftShape<T, L, V, NT>;
@@ -457,7 +465,13 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const cx<T> sh = reg[e];
-                reg[e] = scale(sh, oc.alpha * reg_symbol(mode(e), oc.reg)) + ba[e];
+                const Mode<T> m = mode(e);
+                if (sqrt_scaled) {
+                    const T c = ainv_sqrt_symbol(m, oc);
+                    reg[e] = scale(scale(scale(sh, c), oc.alpha * reg_symbol(m, oc.reg)) + ba[e], c);
+                } else {
+                    reg[e] = scale(sh, oc.alpha * reg_symbol(m, oc.reg)) + ba[e];
+                }
                 if (ok) dacc += wk3 * ((double)sh.re * (double)reg[e].re + (double)sh.im * (double)reg[e].im);
             }
             store(f.o[a], reg);
@@ -470,12 +484,13 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
             if (!first) load(f.o[a], reg);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const cx<T> z = scale(rh[e], scalar_symbol(mode(e), oc));
+                const cx<T> z = zraw ? rh[e] : scale(rh[e], scalar_symbol(mode(e), oc));
                 reg[e] = first ? z : z + scale(reg[e], mu);
             }
             store(f.o[a], reg);
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], oc.norm);
+            for (int e = 0; e < EPT; ++e)
+                reg[e] = scale(reg[e], sqrt_scaled ? ainv_sqrt_symbol(mode(e), oc) * oc.norm : oc.norm);
             fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
             store(f.w[a], reg);
         }
@@ -780,7 +795,7 @@ template void spectral_resample<double>(const Grid &, const Grid &, int, const d
 
 // ---- Krylov host passes ----
 template <typename T, int PASS>
-static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int first,
+static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int flags,
                              const cx<T> *tw, hipStream_t s, int *blocks) {
     const long long Q = (long long)g.n2 * g.k3;
     // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3
@@ -792,7 +807,7 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
         dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, first, tw);    \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw);    \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -837,7 +852,7 @@ void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *
 
 template <typename T>
 void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
-                    const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
+                    const Twiddles<T> &tw, const SpecParams &sp, int flags, hipStream_t s) {
     FieldPtrs fin{}, fw{};
     KrylovPtrs kp{};
     for (int a = 0; a < 3; ++a) {
@@ -852,7 +867,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
     OpConst<T> oc = krylov_const<T>(g, sp);
     oc.red = sp.red;
     int blocks = 0;
-    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, 0, tw.t[0], s, &blocks);
+    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
@@ -860,7 +875,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
 }
 
 template <typename T>
-void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, bool first,
+void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, int flags,
                       T *const *s_out, cx<T> *work, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
     FieldPtrs fw{}, fout{};
     KrylovPtrs kp{};
@@ -871,7 +886,7 @@ void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *sha
         kp.a[a] = rhat[a];
         kp.o[a] = shat[a];
     }
-    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, first ? 1 : 0, tw.t[0], s, nullptr);
+    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, flags, tw.t[0], s, nullptr);
     launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
     launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
 }
@@ -917,13 +932,124 @@ void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *xhat, 
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, out2 + 1);
 }
 
+// ---- Two-level preconditioner on Krylov spectra (fine grid n, coarse n/2) ----
+// Mode (w1, w2, w3) of a half spectrum [n1][n2][n3/2+1] at linear index j.
+__device__ __forceinline__ void half_mode(unsigned j, int n1, int n2, int k3, int &w1, int &w2, int &w3) {
+    const unsigned i3 = j % (unsigned)k3, row = j / (unsigned)k3;
+    w1 = wavenumber((int)(row / (unsigned)n2), n1);
+    w2 = wavenumber((int)(row % (unsigned)n2), n2);
+    w3 = (int)i3;
+}
+template <typename T>
+__device__ __forceinline__ void tl_symbols(int w1, int w2, int w3, int reg, T beta_v, T &sigma, T &c) {
+    const T ks = (T)w1 * (T)w1 + (T)w2 * (T)w2 + (T)w3 * (T)w3;
+    const T a = reg == 2 ? ks * ks : ks;
+    sigma = ks == (T)0 ? (T)1 : (T)1 / (beta_v * a);
+    c = ks == (T)0 ? (T)1 : (T)1 / sqrt(beta_v * a);
+}
+
+// Coarse right-hand side of the nested CG: rc = pc = Q_R c r for every coarse
+// mode, i.e. (Nc/Nf) c(k) rf(k) on the modes below the coarse Nyquist, 0 on
+// the coarse Nyquist planes.  Component blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tl_restrict(int n1f, int n2f, int k3f, int n1c, int n2c, int n3c, int k3c,
+                                                     unsigned NSc, int reg, T beta_v, T factor, KrylovSet<T> v) {
+    const unsigned j = blockIdx.x * 256u + threadIdx.x;
+    if (j >= NSc) return;
+    const int a = blockIdx.y;
+    int w1, w2, w3;
+    half_mode(j, n1c, n2c, k3c, w1, w2, w3);
+    cx<T> val = make_cx<T>(0, 0);
+    if (2 * abs(w1) < n1c && 2 * abs(w2) < n2c && 2 * w3 < n3c) {
+        T sigma, c;
+        tl_symbols<T>(w1, w2, w3, reg, beta_v, sigma, c);
+        const int s1 = w1 >= 0 ? w1 : w1 + n1f, s2 = w2 >= 0 ? w2 : w2 + n2f;
+        val = scale(v.p[a][((long long)s1 * n2f + s2) * k3f + w3], factor * c);
+    }
+    v.p[3 + a][j] = val;
+    v.p[6 + a][j] = val;
+}
+
+// Fine preconditioned residual z = c (F_H c r + Q_P u): on the modes below
+// n_a/4 on every axis c(k) (Nf/Nc) u(k), elsewhere sigma(k) r(k); partials
+// of sum_x r . z (part[b], fixed grid of kRedBlocks workgroups).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tl_combine(int n1f, int n2f, int n3f, int k3f, int n2c, int k3c, unsigned NSf,
+                                                    int reg, T beta_v, T factor, double norm, KrylovSet<T> v,
+                                                    double *__restrict__ part) {
+    cx<T> *const *rf = v.p, *const *uc = v.p + 3, *const *zf = v.p + 6;
+    const int n1c = n1f / 2;
+    double acc = 0;
+    for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NSf; j += gridDim.x * 256u) {
+        int w1, w2, w3;
+        half_mode(j, n1f, n2f, k3f, w1, w2, w3);
+        T sigma, c;
+        tl_symbols<T>(w1, w2, w3, reg, beta_v, sigma, c);
+        const bool low = 4 * abs(w1) < n1f && 4 * abs(w2) < n2f && 4 * w3 < n3f;
+        const long long jc = low ? ((long long)(w1 >= 0 ? w1 : w1 + n1c) * n2c + (w2 >= 0 ? w2 : w2 + n2c)) * k3c + w3 : 0;
+        const double wk3 = (w3 == 0 || 2 * w3 == n3f) ? 1.0 : 2.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cx<T> r = rf[a][j];
+            const cx<T> z = low ? scale(uc[a][jc], factor * c) : scale(r, sigma);
+            zf[a][j] = z;
+            acc += wk3 * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
+        }
+    }
+    __shared__ double sh[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + (sh[2] + sh[3])) * norm;
+}
+
+template <typename T>
+void twolevel_restrict(const Grid &gf, const Grid &gc, const cx<T> *const *rf, cx<T> *const *rc, cx<T> *const *pc,
+                       const SpecParams &sp, hipStream_t s) {
+    KrylovSet<T> v{};
+    for (int a = 0; a < 3; ++a) {
+        v.p[a] = const_cast<cx<T> *>(rf[a]);
+        v.p[3 + a] = rc[a];
+        v.p[6 + a] = pc[a];
+    }
+    HookScope hs(K_VECTOR, 9.0 * sizeof(cx<T>) * gc.NS);
+    const T factor = (T)((double)gc.N / (double)gf.N);
+    dim3 grid((unsigned)((gc.NS + 255) / 256), 3);
+    hipLaunchKernelGGL((k_tl_restrict<T>), grid, dim3(256), 0, s, gf.n1, gf.n2, gf.k3, gc.n1, gc.n2, gc.n3, gc.k3,
+                       (unsigned)gc.NS, sp.reg, (T)sp.beta_v, factor, v);
+}
+
+template <typename T>
+void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, const cx<T> *const *uc,
+                      cx<T> *const *zf, const SpecParams &sp, double *partials, double *out, hipStream_t s) {
+    KrylovSet<T> v{};
+    for (int a = 0; a < 3; ++a) {
+        v.p[a] = const_cast<cx<T> *>(rf[a]);
+        v.p[3 + a] = const_cast<cx<T> *>(uc[a]);
+        v.p[6 + a] = zf[a];
+    }
+    const T factor = (T)((double)gf.N / (double)gc.N);
+    {
+        HookScope hs(K_VECTOR, 6.0 * sizeof(cx<T>) * gf.NS);
+        hipLaunchKernelGGL((k_tl_combine<T>), dim3(kRedBlocks), dim3(256), 0, s, gf.n1, gf.n2, gf.n3, gf.k3, gc.n2,
+                           gc.k3, (unsigned)gf.NS, sp.reg, (T)sp.beta_v, factor, 1.0 / (double)gf.N, v, partials);
+    }
+    HookScope hs(K_REDUCE, 8.0 * kRedBlocks);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, kRedBlocks, partials, out);
+}
+
 #define MIREG_KRYLOV(T)                                                                                          \
     template void krylov_forward<T>(const Grid &, const T *const *, cx<T> *const *, cx<T> *, const Twiddles<T> &, \
                                     hipStream_t);                                                                \
     template void krylov_hessian<T>(const Grid &, const T *const *, const cx<T> *const *, cx<T> *const *,         \
-                                    cx<T> *, const Twiddles<T> &, const SpecParams &, hipStream_t);              \
-    template void krylov_direction<T>(const Grid &, const cx<T> *const *, cx<T> *const *, double, bool,          \
+                                    cx<T> *, const Twiddles<T> &, const SpecParams &, int, hipStream_t);         \
+    template void krylov_direction<T>(const Grid &, const cx<T> *const *, cx<T> *const *, double, int,           \
                                       T *const *, cx<T> *, const Twiddles<T> &, const SpecParams &, hipStream_t); \
+    template void twolevel_restrict<T>(const Grid &, const Grid &, const cx<T> *const *, cx<T> *const *,          \
+                                       cx<T> *const *, const SpecParams &, hipStream_t);                          \
+    template void twolevel_combine<T>(const Grid &, const Grid &, const cx<T> *const *, const cx<T> *const *,     \
+                                      cx<T> *const *, const SpecParams &, double *, double *, hipStream_t);       \
     template void krylov_inverse<T>(const Grid &, const cx<T> *const *, T *const *, cx<T> *, const Twiddles<T> &, \
                                     hipStream_t);                                                                \
     template void krylov_update<T>(const Grid &, double, bool, cx<T> *const *, cx<T> *const *,                   \

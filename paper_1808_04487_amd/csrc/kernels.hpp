@@ -79,19 +79,33 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
 // field).  work holds three half spectra.  The preconditioner is the
 // spectral one, M^{-1}(k) = 1 / (beta_v a(k)), 1 at k = 0 (sp: reg, beta_v).
 enum KrylovPass { KP_FWD = 0, KP_HESS = 1, KP_DIR = 2, KP_INV = 3 };
+// KF_FIRST: the direction is z (no previous direction); KF_SQRT: the operator
+// and the direction's grid field carry c = (beta_v a(k))^{-1/2} (the nested CG
+// of the two-level preconditioner); KF_ZRAW: z is the given spectrum itself.
+enum KrylovFlags { KF_FIRST = 1, KF_SQRT = 2, KF_ZRAW = 4 };
 // hat = F u
 template <typename T>
 void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *work, const Twiddles<T> &tw,
                     hipStream_t s);
-// hhat = beta_v a(k) shat + K F b (sp: reg, div, beta_v, beta_w); with
-// sp.red / sp.red_out set, *red_out = sum_x s . Hs
+// hhat = beta_v a(k) shat + K F b (sp: reg, div, beta_v, beta_w); KF_SQRT:
+// hhat = c (beta_v a(k) c shat + K F b); with sp.red / sp.red_out set,
+// *red_out = sum_x s . Hs
 template <typename T>
 void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
-                    const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
-// shat = M^{-1} rhat + mu shat (shat not read when first), s_out = F^{-1} shat
+                    const Twiddles<T> &tw, const SpecParams &sp, int flags, hipStream_t s);
+// shat = z + mu shat (shat not read with KF_FIRST), z = M^{-1} rhat (rhat
+// itself with KF_ZRAW); s_out = F^{-1} shat (F^{-1} c shat with KF_SQRT)
 template <typename T>
-void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, bool first,
+void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, int flags,
                       T *const *s_out, cx<T> *work, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s);
+// Two-level preconditioner on spectra: rc = pc = Q_R c rf (coarse grid gc =
+// gf / 2); zf = c (F_H c rf + Q_P uc) and *out = sum_x r . z (partials: kRedBlocks)
+template <typename T>
+void twolevel_restrict(const Grid &gf, const Grid &gc, const cx<T> *const *rf, cx<T> *const *rc, cx<T> *const *pc,
+                       const SpecParams &sp, hipStream_t s);
+template <typename T>
+void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, const cx<T> *const *uc,
+                      cx<T> *const *zf, const SpecParams &sp, double *partials, double *out, hipStream_t s);
 // u = F^{-1} hat
 template <typename T>
 void krylov_inverse(const Grid &g, const cx<T> *const *hat, T *const *u, cx<T> *work, const Twiddles<T> &tw,

@@ -106,7 +106,7 @@ struct StatsHook : mireg::KernelHook {
 }  // namespace
 
 // Krylov spectra of the spectral PCG (mireg_ctx::kspec)
-enum KrylovVec { KV_X = 0, KV_R = 1, KV_S = 2, KV_H = 3 };
+enum KrylovVec { KV_X = 0, KV_R = 1, KV_S = 2, KV_H = 3, KV_Z = 4 };
 
 struct mireg_ctx {
     mireg_params p{};
@@ -127,7 +127,7 @@ struct mireg_ctx {
     void *b = nullptr;      // 3N, time integral of the gradient / matvec
     void *vecs = nullptr;   // kVecs x 3N work vectors
     void *spec = nullptr;   // 6 half spectra
-    void *kspec = nullptr;  // 12 half spectra: x, r, s, Hs of the spectral PCG
+    void *kspec = nullptr;  // 15 half spectra: x, r, s, Hs, z of the spectral PCG
     void *tw[3] = {nullptr, nullptr, nullptr};
     double *partials = nullptr, *dres = nullptr;  // device reduction buffers
     double *xpart = nullptr;                      // partials of the fused spectral dot products
@@ -187,7 +187,7 @@ struct mireg_ctx {
     T *vec(int i) const {
         return static_cast<T *>(vecs) + (long long)i * 3 * g.N;
     }
-    // component a of Krylov spectrum v (KV_X, KV_R, KV_S, KV_H)
+    // component a of Krylov spectrum v (KV_X, KV_R, KV_S, KV_H, KV_Z)
     template <typename T>
     cx<T> *khat(int v, int a) const {
         return static_cast<cx<T> *>(kspec) + (long long)(3 * v + a) * g.NS;
@@ -552,7 +552,7 @@ int impl_matvec_spectral(mireg_ctx *ctx, const T *s) {
     sp.red_out = ctx->dres;
     {
         Phase ph(ctx, 0);
-        krylov_hessian<T>(ctx->g, bp, sh, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp, ctx->stream);
+        krylov_hessian<T>(ctx->g, bp, sh, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp, 0, ctx->stream);
     }
     return check_launch(ctx);
 }
@@ -629,11 +629,10 @@ void resample3(mireg_ctx *a, mireg_ctx *b, const T *in, T *out, int nf) {
 // Two-level preconditioner (Sec. 2.3.3): z = Hreg^{-1/2} (Q_P u + F_H t),
 // t = Hreg^{-1/2} r, u ~ (Hreg_c^{-1/2} H_c Hreg_c^{-1/2})^{-1} Q_R t by CG on
 // the coarse context to kappa * eps_h.
-template <typename T, typename S = T>
-int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
+// The coarse problem follows the fine images and velocity (spectral resampling).
+template <typename T>
+void coarse_sync(mireg_ctx *ctx) {
     mireg_ctx *c = ctx->coarse;
-    const long long n = 3 * ctx->N(), nc = 3 * c->N();
-    int rc;
     if (!ctx->coarse_images) {
         resample3<T>(ctx, c, ctx->f<T>(ctx->mT), c->f<T>(c->mT), 1);
         resample3<T>(ctx, c, ctx->f<T>(ctx->mR), c->f<T>(c->mR), 1);
@@ -646,6 +645,14 @@ int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
         c->invalidate();
         ctx->coarse_vel_version = ctx->vel_version;
     }
+}
+
+template <typename T, typename S = T>
+int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
+    mireg_ctx *c = ctx->coarse;
+    const long long n = 3 * ctx->N(), nc = 3 * c->N();
+    int rc;
+    coarse_sync<T>(ctx);
     T *t = ctx->vec<T>(7);
     op_scale<T, S>(ctx, SYM_AINV_SQRT, 3, ctx->p.beta_v, 0.0, r, t);
     T *b = c->vec<T>(4), *u = c->vec<T>(5), *w = c->vec<T>(6), *y = c->vec<T>(7);
@@ -742,36 +749,90 @@ int apply_precond(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
     return impl_precond<T, S>(ctx, r, z);
 }
 
-// z = M^{-1} r and *rz = <r, z> (grid inner product); the spectral
-// preconditioner gets the product from its own spectra.
+// The two-level preconditioner on Krylov spectra: KV_Z = M^{-1} KV_R and
+// *rz = <r, z>.  The nested CG runs on the coarse context's spectra: u
+// (KV_X), its residual (KV_R), direction p (KV_S) and S p (KV_H), S = c H_c c
+// with c = (beta_v a(k))^{-1/2}; each direction's transport takes c p on the
+// coarse grid (coarse vector 2).  Same iteration as two_level_apply.
 template <typename T, typename S = T>
-int precond_dot(mireg_ctx *ctx, const T *r, T *z, double eps_h, double *rz) {
-    if (ctx->pc_kind == MIREG_PC_TWO_LEVEL) {
-        int rc = two_level_apply<T, S>(ctx, r, z, eps_h);
-        return rc ? rc : dot_h<T>(ctx, r, z, 3 * ctx->N(), rz);
+int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
+    mireg_ctx *c = ctx->coarse;
+    int rc;
+    coarse_sync<T>(ctx);
+    ensure_state<T, S>(c);
+    ensure_gradm<T, S>(c);
+    ensure_d<T, S>(c);
+    ensure_Y<T, S>(c);
+    const long long Nc = c->N();
+    T *w = c->vec<T>(2);
+    T *wp[3] = {w, w + Nc, w + 2 * Nc};
+    const T *b = c->f<T>(c->b);
+    const T *bp[3] = {b, b + Nc, b + 2 * Nc};
+    cx<T> *rf[3], *zf[3], *uc[3], *rcs[3], *pc[3], *qc[3];
+    for (int a = 0; a < 3; ++a) {
+        rf[a] = ctx->khat<T>(KV_R, a);
+        zf[a] = ctx->khat<T>(KV_Z, a);
+        uc[a] = c->khat<T>(KV_X, a);
+        rcs[a] = c->khat<T>(KV_R, a);
+        pc[a] = c->khat<T>(KV_S, a);
+        qc[a] = c->khat<T>(KV_H, a);
     }
-    const long long N = ctx->N();
-    const void *in[3] = {r, r + N, r + 2 * N};
-    T *o[3] = {z, z + N, z + 2 * N};
-    SpecParams sp = spec_params<T>(ctx);
-    sp.sym = SYM_AINV;
-    sp.nf = 3;
-    sp.alpha = ctx->p.beta_v;
-    sp.red = ctx->xpart;
-    sp.red_out = ctx->dres;
-    spec<T, S>(ctx, SPEC_SCALE, 3, 3, in, o, sp);
-    int rc = readback(ctx, 1);
-    if (rc) return rc;
-    *rz = ctx->cell() * ctx->hres[0];
+    cx<T> *cwork = static_cast<cx<T> *>(c->spec);
+    const Twiddles<T> tw = twiddles<T>(c);
+    const SpecParams sp = spec_params<T>(c);
+    SpecParams sdot = sp;
+    sdot.red = c->xpart;
+    sdot.red_out = c->dres;
+    const double h3c = c->cell();
+    {
+        Phase ph(ctx, 0);  // r = p = Q_R c r_fine, u = 0
+        twolevel_restrict<T>(ctx->g, c->g, rf, rcs, pc, sp, c->stream);
+        fill<T>(6 * c->g.NS, (T)0, reinterpret_cast<T *>(uc[0]), c->stream);
+        krylov_update<T>(c->g, 0.0, false, uc, rcs, pc, qc, sp, c->partials, c->dres + 1, c->stream);
+    }
+    if ((rc = readback(c, 3))) return rc;
+    double rr = h3c * c->hres[2];
+    const double tol = ctx->pc_kappa * eps_h * std::sqrt(rr);
+    if (rr > 0) {
+        Phase ph(ctx, 0);
+        krylov_direction<T>(c->g, rcs, pc, 0.0, KF_FIRST | KF_ZRAW | KF_SQRT, wp, cwork, tw, sp, c->stream);
+    }
+    for (int it = 0; it < ctx->pc_max_inner && std::sqrt(rr) > tol; ++it) {
+        matvec_transport<T, S>(c, w);
+        {
+            Phase ph(ctx, 0);
+            krylov_hessian<T>(c->g, bp, pc, qc, cwork, tw, sdot, KF_SQRT, c->stream);
+        }
+        ctx->coarse_matvecs += 1;
+        if ((rc = readback(c, 1))) return rc;
+        const double pq = h3c * c->hres[0];
+        if (!(pq > 0)) break;
+        krylov_update<T>(c->g, rr / pq, true, uc, rcs, pc, qc, sp, c->partials, c->dres + 1, c->stream);
+        if ((rc = readback(c, 3))) return rc;
+        const double rr_new = h3c * c->hres[2];
+        if (std::sqrt(rr_new) <= tol) break;
+        {
+            Phase ph(ctx, 0);  // p = r + beta p
+            krylov_direction<T>(c->g, rcs, pc, rr_new / rr, KF_ZRAW | KF_SQRT, wp, cwork, tw, sp, c->stream);
+        }
+        rr = rr_new;
+    }
+    {
+        Phase ph(ctx, 0);
+        twolevel_combine<T>(ctx->g, c->g, rf, uc, zf, spec_params<T>(ctx), ctx->partials, ctx->dres + 1,
+                            ctx->stream);
+    }
+    if ((rc = readback(ctx, 2))) return rc;
+    *rz = ctx->cell() * ctx->hres[1];
     return check_launch(ctx);
 }
 
 // ---- PCG (Algorithm "inner iteration") ----
-// With the spectral preconditioner the Krylov vectors x, r and s are kept as
-// half spectra (KV_X, KV_R, KV_S; H s as KV_H): the preconditioner is a
-// pointwise multiplier there, H s is needed only as a spectrum, and only the
-// direction s is transformed back (the transport needs it on the grid).
-// Same iteration as below, with inner products from Parseval.
+// The Krylov vectors x, r and s are kept as half spectra (KV_X, KV_R, KV_S;
+// H s as KV_H): the spectral preconditioner is a pointwise multiplier there
+// and the two-level one (KV_Z) pointwise apart from its nested CG, H s is
+// needed only as a spectrum, and only the direction s is transformed back
+// (the transport needs it on the grid).  Inner products come from Parseval.
 template <typename T, typename S = T>
 int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
     const long long N = ctx->N();
@@ -779,13 +840,18 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     T *s = ctx->vec<T>(2);
     T *sp3[3] = {s, s + N, s + 2 * N}, *xp[3] = {x, x + N, x + 2 * N};
     const T *rp[3] = {rhs, rhs + N, rhs + 2 * N};
-    cx<T> *xh[3], *rh[3], *sh[3], *hh[3];
+    const bool two_level = ctx->pc_kind == MIREG_PC_TWO_LEVEL;
+    cx<T> *xh[3], *rh[3], *sh[3], *hh[3], *zh[3];
     for (int a = 0; a < 3; ++a) {
         xh[a] = ctx->khat<T>(KV_X, a);
         rh[a] = ctx->khat<T>(KV_R, a);
         sh[a] = ctx->khat<T>(KV_S, a);
         hh[a] = ctx->khat<T>(KV_H, a);
+        zh[a] = ctx->khat<T>(KV_Z, a);
     }
+    // z = M^{-1} r: from r in the direction pass (spectral), or KV_Z (two-level)
+    cx<T> *const *zsrc = two_level ? zh : rh;
+    const int zflag = two_level ? KF_ZRAW : 0;
     cx<T> *work = static_cast<cx<T> *>(ctx->spec);
     const Twiddles<T> tw = twiddles<T>(ctx);
     const SpecParams sp = spec_params<T>(ctx);
@@ -803,9 +869,10 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     double rnorm = r0;
     bool x_is_s = false;
     if (r0 > 0) {
+        if (two_level && (rc = two_level_spectral<T, S>(ctx, rtol, &rz))) return rc;
         {
             Phase ph(ctx, 0);  // s = z = M^{-1} r
-            krylov_direction<T>(ctx->g, rh, sh, 0.0, true, sp3, work, tw, sp, ctx->stream);
+            krylov_direction<T>(ctx->g, zsrc, sh, 0.0, KF_FIRST | zflag, sp3, work, tw, sp, ctx->stream);
         }
         while (it < maxit) {
             if ((rc = matvec_graph<T, S>(ctx, s, nullptr, true))) return rc;
@@ -825,12 +892,13 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[2]);
             if (rnorm <= rtol * r0) break;
-            const double rz_new = h3 * ctx->hres[1];
+            double rz_new = h3 * ctx->hres[1];
+            if (two_level && (rc = two_level_spectral<T, S>(ctx, rtol, &rz_new))) return rc;
             const double mu = rz_new / rz;
             rz = rz_new;
             {
                 Phase ph(ctx, 0);  // s = z + mu s
-                krylov_direction<T>(ctx->g, rh, sh, mu, false, sp3, work, tw, sp, ctx->stream);
+                krylov_direction<T>(ctx->g, zsrc, sh, mu, zflag, sp3, work, tw, sp, ctx->stream);
             }
         }
     }
@@ -849,46 +917,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
 
 template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
-    if (ctx->pc_kind == MIREG_PC_SPECTRAL) return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres);
-    const long long n = 3 * ctx->N();
-    const double h3 = ctx->cell();
-    T *r = ctx->vec<T>(0), *z = ctx->vec<T>(1), *s = ctx->vec<T>(2), *Hs = ctx->vec<T>(3);
-    int rc;
-    HIP_OK(hipMemcpyAsync(r, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
-    fill<T>(n, (T)0, x, ctx->stream);
-    double rr = 0;
-    if ((rc = dot_h<T>(ctx, r, r, n, &rr))) return rc;
-    const double r0 = std::sqrt(rr);
-    int it = 0;
-    double rnorm = r0;
-    if (r0 > 0) {
-        double rz = 0;
-        if ((rc = precond_dot<T, S>(ctx, r, z, rtol, &rz))) return rc;
-        HIP_OK(hipMemcpyAsync(s, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
-        while (it < maxit) {
-            if ((rc = matvec_graph<T, S>(ctx, s, Hs))) return rc;
-            if ((rc = readback(ctx, 1))) return rc;
-            const double sHs = h3 * ctx->hres[0];
-            if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate
-                if (it == 0) HIP_OK(hipMemcpyAsync(x, z, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
-                break;
-            }
-            const double kappa = rz / sHs;
-            pcg_update<T>(n, kappa, s, Hs, x, r, ctx->partials, ctx->dres, ctx->stream);
-            if ((rc = readback(ctx, 1))) return rc;
-            ++it;
-            rnorm = std::sqrt(h3 * ctx->hres[0]);
-            if (rnorm <= rtol * r0) break;
-            double rz_new = 0;
-            if ((rc = precond_dot<T, S>(ctx, r, z, rtol, &rz_new))) return rc;
-            const double mu = rz_new / rz;
-            rz = rz_new;
-            xpay<T>(n, z, mu, s, s, ctx->stream);  // s = z + mu s
-        }
-    }
-    if (iters) *iters = it;
-    if (relres) *relres = r0 > 0 ? rnorm / r0 : 0.0;
-    return check_launch(ctx);
+    return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres);
 }
 
 template <typename T, typename S = T>
@@ -1218,7 +1247,7 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, &ctx->b, 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->vecs, (size_t)mireg_ctx::kVecs * 3 * F);
     if (!rc) rc = alloc(ctx, &ctx->spec, (size_t)6 * ctx->g.NS * 2 * ctx->elem);
-    if (!rc) rc = alloc(ctx, &ctx->kspec, (size_t)12 * ctx->g.NS * 2 * ctx->elem);
+    if (!rc) rc = alloc(ctx, &ctx->kspec, (size_t)15 * ctx->g.NS * 2 * ctx->elem);
     for (int a = 0; a < 3 && !rc; ++a) rc = alloc(ctx, &ctx->tw[a], (size_t)p->n[a] * 2 * ctx->elem);
     if (!rc) rc = alloc(ctx, (void **)&ctx->partials, 4 * kRedBlocks * sizeof(double));
     if (!rc) rc = alloc(ctx, (void **)&ctx->xpart, ((size_t)ctx->g.n2 * ctx->g.k3 / 8 + 16) * sizeof(double));
