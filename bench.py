@@ -59,6 +59,8 @@ def parse_args():
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-two-level", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: PCG replays its matvecs (and the nested coarse CG's) from captured HIP graphs")
     ap.add_argument("--warm-pairs", type=int, default=16, help="held-out pairs of the warm-start comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, run a fill and a multiply over 1 GiB (known "
@@ -277,6 +279,7 @@ def main():
     n = args.n
     ctx = mireg.Context((n, n, n), nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3,
                         beta_w=1.0, dtype=torch.float32)
+    ctx.set_graphs(bool(args.graphs))
     log(args, "context %d^3, workspace %.2f GB" % (n, ctx.workspace_bytes() / 1e9))
     t0 = time.perf_counter()
     mT, mR, v_true, probe = make_inputs(ctx, n, torch)

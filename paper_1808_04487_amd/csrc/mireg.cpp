@@ -151,6 +151,7 @@ struct mireg_ctx {
     const void *mv_in = nullptr;
     void *mv_out = nullptr;
     bool mv_spectral = false;
+    int mv_flags = 0;
     long long mv_version = -1;
     Timers tm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -534,8 +535,9 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
 
 // Matvec of the spectral PCG: the spectrum of H s from the kept spectrum of
 // s (KV_S) and the transport output, into KV_H; dres[0] = sum_x s . Hs.
+// flags KF_SQRT: the nested CG's scaled operator c H c (s = c times KV_S).
 template <typename T, typename S = T>
-int impl_matvec_spectral(mireg_ctx *ctx, const T *s) {
+int impl_matvec_spectral(mireg_ctx *ctx, const T *s, int flags = 0) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
@@ -552,7 +554,8 @@ int impl_matvec_spectral(mireg_ctx *ctx, const T *s) {
     sp.red_out = ctx->dres;
     {
         Phase ph(ctx, 0);
-        krylov_hessian<T>(ctx->g, bp, sh, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp, 0, ctx->stream);
+        krylov_hessian<T>(ctx->g, bp, sh, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx), sp, flags,
+                          ctx->stream);
     }
     return check_launch(ctx);
 }
@@ -564,19 +567,19 @@ int impl_matvec_spectral(mireg_ctx *ctx, const T *s) {
 // change; the caches it reads are built eagerly first.  Graphs are used
 // when neither timers nor kernel statistics are on.
 template <typename T, typename S = T>
-int matvec_body(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral) {
-    return spectral ? impl_matvec_spectral<T, S>(ctx, vt) : impl_matvec<T, S>(ctx, vt, Hvt, true);
+int matvec_body(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral, int flags) {
+    return spectral ? impl_matvec_spectral<T, S>(ctx, vt, flags) : impl_matvec<T, S>(ctx, vt, Hvt, true);
 }
 template <typename T, typename S = T>
-int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false) {
-    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return matvec_body<T, S>(ctx, vt, Hvt, spectral);
+int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false, int flags = 0) {
+    if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return matvec_body<T, S>(ctx, vt, Hvt, spectral, flags);
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
     ensure_d<T, S>(ctx);
     ensure_Y<T, S>(ctx);
     if (!ctx->mv_exec || ctx->mv_version != ctx->vel_version || ctx->mv_in != vt || ctx->mv_out != Hvt ||
-        ctx->mv_spectral != spectral) {
+        ctx->mv_spectral != spectral || ctx->mv_flags != flags) {
         if (ctx->mv_exec) {
             hipGraphExecDestroy(ctx->mv_exec);
             ctx->mv_exec = nullptr;
@@ -590,7 +593,7 @@ int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false) {
         hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         int rc = MIREG_OK;
         if (e == hipSuccess) {
-            rc = matvec_body<T, S>(ctx, vt, Hvt, spectral);
+            rc = matvec_body<T, S>(ctx, vt, Hvt, spectral, flags);
             e = hipStreamEndCapture(ctx->cap_stream, &graph);
         }
         ctx->stream = own;
@@ -603,6 +606,7 @@ int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false) {
         ctx->mv_in = vt;
         ctx->mv_out = Hvt;
         ctx->mv_spectral = spectral;
+        ctx->mv_flags = flags;
     }
     HIP_OK(hipGraphLaunch(ctx->mv_exec, ctx->stream));
     return check_launch(ctx);
@@ -766,8 +770,6 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
     const long long Nc = c->N();
     T *w = c->vec<T>(2);
     T *wp[3] = {w, w + Nc, w + 2 * Nc};
-    const T *b = c->f<T>(c->b);
-    const T *bp[3] = {b, b + Nc, b + 2 * Nc};
     cx<T> *rf[3], *zf[3], *uc[3], *rcs[3], *pc[3], *qc[3];
     for (int a = 0; a < 3; ++a) {
         rf[a] = ctx->khat<T>(KV_R, a);
@@ -780,9 +782,6 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
     cx<T> *cwork = static_cast<cx<T> *>(c->spec);
     const Twiddles<T> tw = twiddles<T>(c);
     const SpecParams sp = spec_params<T>(c);
-    SpecParams sdot = sp;
-    sdot.red = c->xpart;
-    sdot.red_out = c->dres;
     const double h3c = c->cell();
     {
         Phase ph(ctx, 0);  // r = p = Q_R c r_fine, u = 0
@@ -797,12 +796,9 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
         Phase ph(ctx, 0);
         krylov_direction<T>(c->g, rcs, pc, 0.0, KF_FIRST | KF_ZRAW | KF_SQRT, wp, cwork, tw, sp, c->stream);
     }
+    c->use_graphs = ctx->use_graphs;
     for (int it = 0; it < ctx->pc_max_inner && std::sqrt(rr) > tol; ++it) {
-        matvec_transport<T, S>(c, w);
-        {
-            Phase ph(ctx, 0);
-            krylov_hessian<T>(c->g, bp, pc, qc, cwork, tw, sdot, KF_SQRT, c->stream);
-        }
+        if ((rc = matvec_graph<T, S>(c, w, nullptr, true, KF_SQRT))) return rc;  // S p into KV_H
         ctx->coarse_matvecs += 1;
         if ((rc = readback(c, 1))) return rc;
         const double pq = h3c * c->hres[0];

@@ -99,3 +99,26 @@ def test_fp32_two_level_solve_needs_fewer_fine_matvecs():
     assert rs["status"] == rt["status"] == mireg.CONVERGED_REL
     assert rt["matvecs"] < rs["matvecs"] and rt["coarse_matvecs"] > 0
     assert abs(rt["mismatch_rel"] - rs["mismatch_rel"]) < 0.05 * rs["mismatch_rel"]
+
+
+def test_two_level_graph_replays_match_eager():
+    """PCG with the two-level preconditioner, its fine and nested coarse
+    matvecs replayed from captured graphs, equals the eager PCG bit for bit,
+    over two velocities and repeated solves."""
+    need_gpu()
+    n = (32, 32, 32)
+    dt = torch.float32
+    g, ctx, R, vs = problem(n, dt)
+    rhs = torch.from_numpy(smooth_vector(g, 84)).float().cuda()
+    for scale in (0.5, 0.8):
+        ctx.set_velocity(torch.from_numpy(scale * vs).float().cuda())
+        ctx.set_graphs(False)
+        x0, it0, _ = ctx.pcg(rhs, rtol=1e-4, maxit=30)
+        ctx.set_graphs(True)
+        x1, it1, _ = ctx.pcg(rhs, rtol=1e-4, maxit=30)
+        torch.cuda.synchronize()
+        x2, it2, _ = ctx.pcg(rhs, rtol=1e-4, maxit=30)
+        print("two-level graphs: scale", scale, "iterations", it0, it1, it2, flush=True)
+        assert it0 == it1 == it2 >= 2
+        assert torch.equal(x0, x1) and torch.equal(x0, x2)
+    ctx.set_graphs(False)
