@@ -13,8 +13,9 @@ uploaded before any timed region.
 One step = one full GN-Krylov solve from v = 0 (departure points, state,
 objective, adjoint, gradient, PCG with Hessian matvecs, line search).
 value = Hessian matvecs per second of the whole job: matvecs performed in
-the K timed solves divided by their wall time.  The matvec-only rate, the
-per-kernel breakdown (HIP events on the library stream) and the dominant
+the K timed solves divided by their wall time.  The matvec-only rate (median
+of 5 runs of 100 matvecs at the generating velocity, eager and replayed from
+a captured HIP graph), the per-kernel breakdown (HIP events on the library stream) and the dominant
 kernel's HBM roofline are reported beside it, and the FP64 CPU oracle is
 timed on a bounded sample of the same recipe as the CPU baseline.  The
 FP16-storage variant (FP32 arithmetic, adjoint and incremental fields held in
@@ -52,7 +53,8 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=2, help="timed GN solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed GN solves")
     ap.add_argument("--n", type=int, default=256, help="grid size per axis")
-    ap.add_argument("--matvecs", type=int, default=20, help="matvecs in the matvec-only timing")
+    ap.add_argument("--matvecs", type=int, default=100,
+                    help="matvecs per timed run of the matvec-only timing (median of 5 runs)")
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-variant", action="store_true")
@@ -157,21 +159,28 @@ def timed_solves(args, ctx, torch, warmup, steps):
     return reps, wall
 
 
-def matvec_ms(args, ctx, torch, v, probe):
-    """Matvec-only time at velocity v with the probe direction (events on the
-    library stream)."""
+def matvec_ms(args, ctx, torch, v, probe, graphs=False):
+    """Matvec-only time at velocity v with the probe direction: 10 untimed
+    matvecs, then the median over 5 runs of `matvecs` matvecs (events on the
+    library stream); graphs: the entry point replays a captured graph."""
     ctx.set_velocity(v)
+    ctx.set_graphs(graphs)
     out = ctx.empty(3)
-    for _ in range(3):
+    for _ in range(10):
         ctx.hessian_matvec(probe, out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(ctx.stream)
-    for _ in range(args.matvecs):
-        ctx.hessian_matvec(probe, out)
-    e1.record(ctx.stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / args.matvecs
-    log(args, "matvec-only (%s): %.3f ms (%.1f matvecs/s)" % (ctx.dtype_name, ms, 1000.0 / ms))
+    runs = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(args.matvecs):
+            ctx.hessian_matvec(probe, out)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        runs.append(e0.elapsed_time(e1) / args.matvecs)
+    ctx.set_graphs(bool(args.graphs))
+    ms = sorted(runs)[2]
+    log(args, "matvec-only (%s, %s): %.3f ms (%.1f matvecs/s)" % (ctx.dtype_name, "graph" if graphs else "eager",
+                                                                   ms, 1000.0 / ms))
     return ms
 
 
@@ -298,6 +307,7 @@ def main():
     total_mv = sum(r["matvecs"] for r in reps)
     value = total_mv / wall
     mv_ms = matvec_ms(args, ctx, torch, v_true, probe)
+    mv_graph_ms = matvec_ms(args, ctx, torch, v_true, probe, graphs=True)
     out = ctx.empty(3)
 
     # per-kernel event timing over a separate run of matvecs
@@ -389,6 +399,8 @@ def main():
                                             "mismatch_rel", "gnorm_rel")},
         "matvec_only_per_s": round(1000.0 / mv_ms, 2),
         "matvec_ms": round(mv_ms, 4),
+        "matvec_graph_per_s": round(1000.0 / mv_graph_ms, 2),
+        "matvec_graph_ms": round(mv_graph_ms, 4),
         "fft_ms_per_matvec": round(fft_ms, 4),
         "interp_ms_per_matvec": round(sl_ms, 4),
         "roofline": roofline,

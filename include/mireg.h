@@ -175,10 +175,11 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
 
 /* Launch-overhead and tuning controls (not in the paper; for many small
  * problems and for each grid size):
- * mireg_set_graphs: on != 0 makes PCG replay its Hessian matvec from a
- *   captured HIP graph (captured on a private stream, launched on the
- *   context's stream; re-captured when the velocity changes); off while
- *   timers or kernel statistics are enabled.  Results are identical.  HIP
+ * mireg_set_graphs: on != 0 makes PCG and mireg_hessian_matvec replay the
+ *   Hessian matvec from a captured HIP graph (captured on a private stream,
+ *   launched on the context's stream; re-captured when the velocity, the
+ *   vt / Hvt pointers or the caller (PCG or the entry point) change); off
+ *   while timers or kernel statistics are enabled.  Results are identical.  HIP
  *   invalidates a running capture when any thread uses the legacy (null)
  *   stream: with graphs on in one thread, other threads must keep their
  *   work off the null stream (mireg_create with a null stream uses it), or

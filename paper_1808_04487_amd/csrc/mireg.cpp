@@ -298,16 +298,12 @@ void op_proj(mireg_ctx *ctx, int div, const T *u, T *out) {
 }
 // out = alpha A u + K b
 template <typename T, typename S = T>
-void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out, bool dot = false) {
+void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
     const long long N = ctx->N();
     const void *in[6] = {u, u + N, u + 2 * N, b, b + N, b + 2 * N};
     T *o[3] = {out, out + N, out + 2 * N};
     SpecParams sp = spec_params<T>(ctx);
     sp.alpha = alpha;
-    if (dot) {  // dres[0] = sum_x u . out (Parseval, in the x1 pass)
-        sp.red = ctx->xpart;
-        sp.red_out = ctx->dres;
-    }
     spec<T, S>(ctx, SPEC_TAIL, 6, 3, in, o, sp);
 }
 
@@ -520,16 +516,17 @@ void matvec_transport(mireg_ctx *ctx, const T *vt) {
     backward_sweep<T, S>(ctx, lam, b);
 }
 
-// dot: also leave sum_x vt . Hvt in dres[0] (from the spectra of the last pass)
+// Hvt = beta_v A vt + K b~: the Gauss-Newton Hessian matvec in grid space
+// (eq. "hessian-matvec", Sec. 2.3.2)
 template <typename T, typename S = T>
-int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt, bool dot = false) {
+int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
     ensure_d<T, S>(ctx);
     ensure_Y<T, S>(ctx);
     matvec_transport<T, S>(ctx, vt);
-    op_tail<T, S>(ctx, ctx->p.beta_v, vt, ctx->f<T>(ctx->b), Hvt, dot);
+    op_tail<T, S>(ctx, ctx->p.beta_v, vt, ctx->f<T>(ctx->b), Hvt);
     return check_launch(ctx);
 }
 
@@ -560,15 +557,15 @@ int impl_matvec_spectral(mireg_ctx *ctx, const T *s, int flags = 0) {
     return check_launch(ctx);
 }
 
-// PCG's matvec: Hvt = H vt (spectral: the spectrum of H vt in KV_H, Hvt
-// unused) and dres[0] = sum_x vt . Hvt, through a captured graph of the
-// whole matvec when graphs are on (kernels only: no host synchronisation,
-// no memset), re-captured when the velocity, the buffers or the kind
-// change; the caches it reads are built eagerly first.  Graphs are used
-// when neither timers nor kernel statistics are on.
+// Hessian matvec of PCG (spectral: the spectrum of H vt in KV_H, Hvt unused,
+// and dres[0] = sum_x vt . Hvt) or of the entry point (Hvt = H vt), through
+// a captured graph of the whole matvec when graphs are on (kernels only: no
+// host synchronisation, no memset), re-captured when the velocity, the
+// buffers or the kind change; the caches it reads are built eagerly first.
+// Graphs are used when neither timers nor kernel statistics are on.
 template <typename T, typename S = T>
 int matvec_body(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral, int flags) {
-    return spectral ? impl_matvec_spectral<T, S>(ctx, vt, flags) : impl_matvec<T, S>(ctx, vt, Hvt, true);
+    return spectral ? impl_matvec_spectral<T, S>(ctx, vt, flags) : impl_matvec<T, S>(ctx, vt, Hvt);
 }
 template <typename T, typename S = T>
 int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false, int flags = 0) {
@@ -1316,7 +1313,7 @@ int mireg_gradient(mireg_ctx *ctx, void *g, double *gnorm) {
 int mireg_hessian_matvec(mireg_ctx *ctx, const void *vt, void *Hvt) {
     if (!ctx || !vt || !Hvt) return ctx ? ctx->fail(MIREG_E_ARG, "null matvec pointer") : MIREG_E_ARG;
     if (vt == Hvt) return ctx->fail(MIREG_E_ARG, "vt and Hvt must not alias");
-    return DISPATCH(ctx, (impl_matvec<T, S>(ctx, (const T *)vt, (T *)Hvt)));
+    return DISPATCH(ctx, (matvec_graph<T, S>(ctx, (const T *)vt, (T *)Hvt)));
 }
 
 int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {

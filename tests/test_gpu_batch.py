@@ -46,6 +46,41 @@ def test_graph_replays_match_eager():
         assert torch.equal(x0, x1) and torch.equal(x0, x2) and torch.equal(h0, h1)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_matvec_entry_graph_replays_match_eager(dtype):
+    """The matvec entry point replayed from a captured graph equals the eager
+    matvec bit for bit on every replay, with eager library and torch work and
+    synchronisations between replays; new input buffers, a new velocity and
+    PCG's own graph in between each force a re-capture."""
+    need_gpu()
+    n = (64, 64, 64)
+    g, ctx, vs = synthetic_ctx(n, dtype)
+    probes = [torch.from_numpy(smooth_vector(g, s)).to(dtype).cuda() for s in (94, 95)]
+    rhs = torch.from_numpy(smooth_vector(g, 96)).to(dtype).cuda()
+    out = ctx.empty(3)
+    for scale in (0.6, 0.9):
+        ctx.set_velocity(torch.from_numpy(scale * vs).to(dtype).cuda())
+        ctx.set_graphs(False)
+        ref = [ctx.hessian_matvec(p).clone() for p in probes]
+        ctx.set_graphs(True)
+        for rep in range(3):
+            for k, p in enumerate(probes):
+                ctx.hessian_matvec(p, out)                      # capture for this (vt, Hvt), then replay
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref[k]), (scale, rep, k)
+                ctx.hessian_matvec(p, out)                      # replay of the same graph
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref[k]), (scale, rep, k)
+                ctx.op("grad", probes[0][0])                    # eager library work
+                (probes[1] * 2.0).sum().item()                  # eager torch work and a sync
+            if rep == 1:
+                ctx.pcg(rhs, rtol=1e-3, maxit=5)                # PCG's spectral graph in between
+        print("velocity scale", scale, "replays equal", flush=True)
+    ctx.set_graphs(False)
+    assert torch.equal(ctx.hessian_matvec(probes[1]), ref[1])
+    ctx.close()
+
+
 def test_autotune_keeps_results():
     need_gpu()
     n = (64, 64, 64)
