@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import core, prep
+from oracle import core, prep, solver
 from paper_1808_04487_amd import mireg, synth
 
 from gpu_util import (as_input, assert_close, assert_close_composite, fp32_reg_tol, need_gpu,
@@ -20,13 +20,26 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def workload256():
-    """The benchmark recipe at 256^3, prepared by the oracle in FP64."""
+    """The benchmark recipe at 256^3, prepared by the oracle in FP64 from the
+    FP32-rounded template and velocity; the reference image is rounded to
+    FP32 too, so both sides see the same inputs."""
+    need_gpu()
     n = (256, 256, 256)
     g = core.Grid(n)
+    dt = torch.float32
     mT = prep.smooth_rescale(g, synth.voronoi_phantom(n, nseeds=120, seed=1), 2.0)
     v = prep.smooth_velocity(g, synth.white_noise(n, seed=2), math.pi / 4, 0.15 * 2 * math.pi)
     probe = prep.smooth_velocity(g, synth.white_noise(n, seed=3), math.pi / 4, 0.15 * 2 * math.pi)
-    return g, mT, v, probe
+    _, mT = as_input(mT, dt)
+    _, v = as_input(v, dt)
+    _, probe = as_input(probe, dt)
+    print("fullsize 256^3: oracle reference image", flush=True)
+    _, mR = as_input(prep.transport(g, mT, v), dt)
+    return g, mT, v, probe, mR
+
+
+def workload_params(g):
+    return core.Params(g.n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
 
 
 @pytest.mark.timeout(900)
@@ -35,14 +48,12 @@ def test_fullsize_transport_gradient_matvec(workload256):
     departure points, state m(1), reduced gradient and GN Hessian matvec,
     element by element against the FP64 oracle."""
     need_gpu()
-    g, mT0, v0, probe0 = workload256
+    g, mT0, v0, probe0, mR0 = workload256
     dt = torch.float32
     mT_t, mT = as_input(mT0, dt)
     v_t, v = as_input(v0, dt)
     p_t, p = as_input(probe0, dt)
-    print("fullsize 256^3: oracle reference", flush=True)
-    mR = prep.transport(g, mT, v)                      # reference image, oracle
-    mR_t, mR = as_input(mR, dt)
+    mR_t, mR = as_input(mR0, dt)
     ctx = mireg.Context(g.n, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0, dtype=dt)
     ctx.set_images(mT_t, mR_t)
     ctx.set_velocity(v_t)
@@ -55,8 +66,7 @@ def test_fullsize_transport_gradient_matvec(workload256):
     vw = 0.7 * v
     vw_t, vw = as_input(vw, dt)
     ctx.set_velocity(vw_t)
-    p_ = core.Params(g.n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
-    R = core.Registration(p_, mT, mR)
+    R = core.Registration(workload_params(g), mT, mR)
     R.set_velocity(vw)
     gr, _ = ctx.gradient()
     go = R.gradient()
@@ -65,7 +75,51 @@ def test_fullsize_transport_gradient_matvec(workload256):
     Ho = R.hessian_matvec(p)
     e = assert_close_composite(Hv, Ho, dt, what="matvec 256^3", tol32=fp32_reg_tol(g, 1, 5e-3, p, Ho))
     print("256^3 matvec rel err %.2e (L2 %.2e)" % (e, rel_err_l2(Hv, Ho)), flush=True)
+    # PCG on Krylov spectra (the solve's path), three iterations on both sides
+    rhs_t, rhs = as_input(-go, dt)
+    x, it, rel = ctx.pcg(rhs_t, rtol=1e-12, maxit=3)
+    xo, ito, relo = solver.pcg(R.hessian_matvec, R.precond, rhs, 1e-12, 3, g.inner)
+    print("256^3 pcg iterations %d/%d relres %.4e/%.4e" % (it, ito, rel, relo), flush=True)
+    assert it == ito == 3
+    assert abs(rel - relo) <= 1e-3 * relo
+    assert_close(x, xo, dt, factor=50, what="pcg x 256^3")
     ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_gn_solve_reaches_tolerance(workload256):
+    """The benchmark's solve (256^3 FP32 from v = 0, relative gradient
+    5e-2): the oracle, evaluated at the velocity the GPU returns, confirms
+    the gradient reduction, the reported mismatch and the objective."""
+    need_gpu()
+    g, mT0, v0, probe0, mR0 = workload256
+    dt = torch.float32
+    mT_t, mT = as_input(mT0, dt)
+    mR_t, mR = as_input(mR0, dt)
+    ctx = mireg.Context(g.n, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0, dtype=dt)
+    ctx.set_images(mT_t, mR_t)
+    v_t, rep = ctx.gn_solve(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+    ctx.close()
+    print("256^3 solve", rep, flush=True)
+    assert rep["status"] == 1 and rep["gnorm_rel"] <= 5e-2
+    R = core.Registration(workload_params(g), mT, mR)
+    print("oracle gradient at v = 0", flush=True)
+    R.set_velocity(np.zeros((3,) + g.n))
+    g0 = g.norm(R.gradient())
+    J0 = R.objective()[0]
+    print("oracle gradient at the returned velocity", flush=True)
+    R.set_velocity(v_t.cpu().double().numpy())
+    gk = g.norm(R.gradient())
+    J = R.objective()[0]
+    mis = R.mismatch_rel()
+    print("oracle at the solution: |g|/|g0| %.5f (reported %.5f), J %.6f -> %.6f (reported %.6f), "
+          "mismatch %.6f (reported %.6f)" % (gk / g0, rep["gnorm_rel"], J0, J, rep["J"], mis, rep["mismatch_rel"]),
+          flush=True)
+    assert abs(g0 - rep["gnorm0"]) <= 1e-4 * g0
+    assert abs(gk / g0 - rep["gnorm_rel"]) <= 1e-2 * rep["gnorm_rel"]
+    assert gk / g0 <= 5e-2 * 1.01
+    assert abs(J - rep["J"]) <= 2e-3 * abs(J) and J < 0.1 * J0
+    assert abs(mis - rep["mismatch_rel"]) <= 1e-2 * mis
 
 
 def test_max_grid_properties():
