@@ -382,7 +382,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(int n, const double *__res
 struct KrylovPtrs {
     void *w[3];        // x2/x3-transformed work spectra
     const void *a[3];  // spectral operand
-    void *o[3];        // spectral output (read first in KP_DIR)
+    void *o[3];        // spectral output (read first in KP_DIR; read only, the old direction, in KP_INV)
+    void *x[3];        // iterate updated with the old direction (KP_DIR with KF_XUPD)
 };
 
 // x1 passes of the Krylov iteration (flags: KF_*, kernels.hpp):
@@ -391,19 +392,37 @@ struct KrylovPtrs {
 //            KF_SQRT: the symmetrically scaled operator c (alpha a(k) c a_in + K F b),
 //            c = (alpha a(k))^{-1/2} (1 at k = 0), F b being the transport of c a_in
 //   KP_DIR:  o = z + mu o (o not read with KF_FIRST), z = M^{-1}(k) a_in, or a_in
-//            with KF_ZRAW; w = x1 inverse of o / N (of c o / N with KF_SQRT)
-//   KP_INV:  w = x1 inverse of a_in / N
+//            with KF_ZRAW; w = x1 inverse of o / N (of c o / N with KF_SQRT);
+//            KF_XUPD: first x += alpha o with the old o (the iterate's update of
+//            the previous iteration, deferred to this pass, which reads o anyway)
+//   KP_INV:  w = x1 inverse of a_in / N; KF_XUPD: of (a_in + alpha o) / N
 // KP_FWD, KP_DIR and KP_INV treat component blockIdx.y; KP_HESS all three.
 template <typename T>
 __device__ __forceinline__ T ainv_sqrt_symbol(const Mode<T> &m, const OpConst<T> &oc) {
     return ksq(m) == (T)0 ? (T)1 : (T)1 / sqrt(oc.alpha * reg_symbol(m, oc.reg));
 }
+// Workgroup size of the Krylov x1 passes: 1024 threads (32 columns, 256-byte
+// rows, still over a thousand workgroups per component) for FP32 lines of
+// 256 points, where they fit 128 registers without spilling; the column
+// default otherwise.
+template <typename T, int L>
+constexpr int krylov_threads() {
+    return (sizeof(T) == 4 && L == 256) ? 1024 : col_threads<T, L, 1>();
+}
+// Launch bound: at least that of the other column passes, so the other
+// instantiations keep their register budget.
+template <typename T, int L>
+constexpr int krylov_bound() {
+    return krylov_threads<T, L>() > kColThreads ? krylov_threads<T, L>() : kColThreads;
+}
 template <typename T, int L, int PASS>
-__global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc, T mu,
-                                                           int flags, const cx<T> *__restrict__ tw) {
+__global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc,
+                                                                      T mu, T alpha, int flags,
+                                                                      const cx<T> *__restrict__ tw) {
     const bool first = flags & KF_FIRST, sqrt_scaled = flags & KF_SQRT, zraw = flags & KF_ZRAW;
+    const bool xupd = flags & KF_XUPD;
     constexpr int V = 1;
-    constexpr int NT = col_threads<T, L, V>();
+    constexpr int NT = krylov_threads<T, L>();
     using S = FftShape<T, L, V, NT>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
@@ -479,9 +498,16 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
     } else if constexpr (PASS == KP_DIR) {
         {
             const int a = blockIdx.y;
+            if (!first) load(f.o[a], reg);
+            if (xupd && !first) {  // before r is read, so the three sets are never live together
+                cx<T> xv[EPT];
+                load(f.x[a], xv);
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) xv[e] = xv[e] + scale(reg[e], alpha);
+                store(f.x[a], xv);
+            }
             cx<T> rh[EPT];
             load(f.a[a], rh);
-            if (!first) load(f.o[a], reg);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const cx<T> z = zraw ? rh[e] : scale(rh[e], scalar_symbol(mode(e), oc));
@@ -498,6 +524,12 @@ __global__ __launch_bounds__(kColThreads) void k_x1_krylov(KrylovPtrs f, long lo
         {
             const int a = blockIdx.y;
             load(f.a[a], reg);
+            if (xupd) {
+                cx<T> sv[EPT];
+                load(f.o[a], sv);
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) reg[e] = reg[e] + scale(sv[e], alpha);
+            }
 #pragma unroll
             for (int e = 0; e < EPT; ++e) reg[e] = scale(reg[e], oc.norm);
             fft_line<T, L, V, +1, Lay>(reg, t, c, tw, 1, lds);
@@ -526,16 +558,17 @@ struct KrylovSet {
     cx<T> *p[12];
 };
 
-// Pointwise step of the spectral PCG: x += alpha s, r -= alpha Hs (when
-// write), then per-workgroup partials of sum_x r . M^{-1} r (part[b]) and
-// sum_x r . r (part[nb + b]) from the updated r.  Grid-stride over the NS
-// modes with a fixed grid, so the sums are reproducible.
+// Pointwise step of the spectral PCG: r -= alpha Hs (when write; the iterate
+// takes alpha s in the next direction pass), then per-workgroup partials of
+// sum_x r . M^{-1} r (part[b]) and sum_x r . r (part[nb + b]) from the
+// updated r.  Grid-stride over the NS modes with a fixed grid, so the sums
+// are reproducible.
 template <typename T>
 __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int n2, int n3, int k3, int reg,
                                                        T beta_v, T alpha, int write, KrylovSet<T> v,
                                                        double norm, double *__restrict__ part) {
-    cx<T> *const *x = v.p, *const *r = v.p + 3;
-    const cx<T> *const *s = v.p + 6, *const *h = v.p + 9;
+    cx<T> *const *r = v.p;
+    const cx<T> *const *h = v.p + 3;
     double rz = 0, rr = 0;
     for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NS; j += gridDim.x * 256u) {
         const unsigned i3 = j % (unsigned)k3, row = j / (unsigned)k3;
@@ -552,7 +585,6 @@ __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int 
             if (write) {
                 rv = rv - scale(h[a][j], alpha);
                 r[a][j] = rv;
-                x[a][j] = x[a][j] + scale(s[a][j], alpha);
             }
             m2 += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
         }
@@ -795,19 +827,23 @@ template void spectral_resample<double>(const Grid &, const Grid &, int, const d
 
 // ---- Krylov host passes ----
 template <typename T, int PASS>
-static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int flags,
+static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, T alpha, int flags,
                              const cx<T> *tw, hipStream_t s, int *blocks) {
     const long long Q = (long long)g.n2 * g.k3;
-    // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3
-    const double fields = PASS == KP_HESS ? 9.0 : (PASS == KP_DIR ? 12.0 : 6.0);
+    // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3;
+    // KF_XUPD adds x read and written (DIR) or the old direction read (INV)
+    const bool xupd = flags & KF_XUPD;
+    const double fields = PASS == KP_HESS ? 9.0
+                          : PASS == KP_DIR ? (xupd ? 18.0 : 12.0)
+                                           : (PASS == KP_INV && xupd ? 9.0 : 6.0);
     HookScope hs(K_X1_KRYLOV, fields * 2.0 * sizeof(T) * g.NS);
 #define MIREG_L(L)                                                                                       \
     {                                                                                                    \
-        constexpr int NT = col_threads<T, L, 1>();                                                       \
+        constexpr int NT = krylov_threads<T, L>();                                                       \
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
         dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw);    \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, alpha, flags, tw); \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -847,7 +883,7 @@ void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *
     launch_x2<T, -1>(g, fw, 3, tw.t[1], s);
     SpecParams sp{};
     sp.reg = 1;
-    launch_x1_krylov<T, KP_FWD>(g, kp, krylov_const<T>(g, sp), (T)0, 0, tw.t[0], s, nullptr);
+    launch_x1_krylov<T, KP_FWD>(g, kp, krylov_const<T>(g, sp), (T)0, (T)0, 0, tw.t[0], s, nullptr);
 }
 
 template <typename T>
@@ -867,7 +903,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
     OpConst<T> oc = krylov_const<T>(g, sp);
     oc.red = sp.red;
     int blocks = 0;
-    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
+    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
@@ -876,7 +912,8 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
 
 template <typename T>
 void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, int flags,
-                      T *const *s_out, cx<T> *work, const Twiddles<T> &tw, const SpecParams &sp, hipStream_t s) {
+                      cx<T> *const *xhat, double alpha, T *const *s_out, cx<T> *work, const Twiddles<T> &tw,
+                      const SpecParams &sp, hipStream_t s) {
     FieldPtrs fw{}, fout{};
     KrylovPtrs kp{};
     for (int a = 0; a < 3; ++a) {
@@ -885,15 +922,17 @@ void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *sha
         kp.w[a] = fw.p[a];
         kp.a[a] = rhat[a];
         kp.o[a] = shat[a];
+        kp.x[a] = xhat ? xhat[a] : nullptr;
     }
-    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, flags, tw.t[0], s, nullptr);
+    if (xhat && !(flags & KF_FIRST)) flags |= KF_XUPD;
+    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, (T)alpha, flags, tw.t[0], s, nullptr);
     launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
     launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
 }
 
 template <typename T>
-void krylov_inverse(const Grid &g, const cx<T> *const *hat, T *const *u, cx<T> *work, const Twiddles<T> &tw,
-                    hipStream_t s) {
+void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *shat, double alpha, T *const *u,
+                    cx<T> *work, const Twiddles<T> &tw, hipStream_t s) {
     FieldPtrs fw{}, fout{};
     KrylovPtrs kp{};
     for (int a = 0; a < 3; ++a) {
@@ -901,28 +940,27 @@ void krylov_inverse(const Grid &g, const cx<T> *const *hat, T *const *u, cx<T> *
         fout.p[a] = u[a];
         kp.w[a] = fw.p[a];
         kp.a[a] = hat[a];
+        kp.o[a] = shat ? const_cast<cx<T> *>(shat[a]) : nullptr;
     }
     SpecParams sp{};
     sp.reg = 1;
-    launch_x1_krylov<T, KP_INV>(g, kp, krylov_const<T>(g, sp), (T)0, 0, tw.t[0], s, nullptr);
+    launch_x1_krylov<T, KP_INV>(g, kp, krylov_const<T>(g, sp), (T)0, (T)alpha, shat ? KF_XUPD : 0, tw.t[0], s,
+                                nullptr);
     launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
     launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
 }
 
 template <typename T>
-void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *xhat, cx<T> *const *rhat,
-                   const cx<T> *const *shat, const cx<T> *const *hhat, const SpecParams &sp, double *partials,
-                   double *out2, hipStream_t s) {
+void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *rhat, const cx<T> *const *hhat,
+                   const SpecParams &sp, double *partials, double *out2, hipStream_t s) {
     KrylovSet<T> v{};
     for (int a = 0; a < 3; ++a) {
-        v.p[a] = xhat[a];
-        v.p[3 + a] = rhat[a];
-        v.p[6 + a] = const_cast<cx<T> *>(shat[a]);
-        v.p[9 + a] = const_cast<cx<T> *>(hhat[a]);
+        v.p[a] = rhat[a];
+        v.p[3 + a] = const_cast<cx<T> *>(hhat[a]);
     }
     constexpr int nb = kRedBlocks;
     {
-        HookScope hs(K_KRYLOV_UPDATE, (write ? 18.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
+        HookScope hs(K_KRYLOV_UPDATE, (write ? 9.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
         hipLaunchKernelGGL((k_krylov_update<T>), dim3(nb), dim3(256), 0, s, (unsigned)g.NS, g.n1, g.n2, g.n3, g.k3,
                            sp.reg, (T)sp.beta_v, (T)alpha, write ? 1 : 0, v,
                            1.0 / ((double)g.n1 * g.n2 * g.n3), partials);
@@ -972,12 +1010,14 @@ __global__ __launch_bounds__(256) void k_tl_restrict(int n1f, int n2f, int k3f, 
 
 // Fine preconditioned residual z = c (F_H c r + Q_P u): on the modes below
 // n_a/4 on every axis c(k) (Nf/Nc) u(k), elsewhere sigma(k) r(k); partials
-// of sum_x r . z (part[b], fixed grid of kRedBlocks workgroups).
+// of sum_x r . z (part[b], fixed grid of kRedBlocks workgroups).  u is
+// u + alpha p (the nested CG's last update, pending) when alpha != 0.
 template <typename T>
 __global__ __launch_bounds__(256) void k_tl_combine(int n1f, int n2f, int n3f, int k3f, int n2c, int k3c, unsigned NSf,
-                                                    int reg, T beta_v, T factor, double norm, KrylovSet<T> v,
-                                                    double *__restrict__ part) {
+                                                    int reg, T beta_v, T factor, T alpha, double norm,
+                                                    KrylovSet<T> v, double *__restrict__ part) {
     cx<T> *const *rf = v.p, *const *uc = v.p + 3, *const *zf = v.p + 6;
+    const cx<T> *const *pc = v.p + 9;
     const int n1c = n1f / 2;
     double acc = 0;
     for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NSf; j += gridDim.x * 256u) {
@@ -991,7 +1031,9 @@ __global__ __launch_bounds__(256) void k_tl_combine(int n1f, int n2f, int n3f, i
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const cx<T> r = rf[a][j];
-            const cx<T> z = low ? scale(uc[a][jc], factor * c) : scale(r, sigma);
+            cx<T> u = low ? uc[a][jc] : make_cx<T>(0, 0);
+            if (low && alpha != (T)0) u = u + scale(pc[a][jc], alpha);
+            const cx<T> z = low ? scale(u, factor * c) : scale(r, sigma);
             zf[a][j] = z;
             acc += wk3 * ((double)r.re * (double)z.re + (double)r.im * (double)z.im);
         }
@@ -1022,18 +1064,21 @@ void twolevel_restrict(const Grid &gf, const Grid &gc, const cx<T> *const *rf, c
 
 template <typename T>
 void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, const cx<T> *const *uc,
-                      cx<T> *const *zf, const SpecParams &sp, double *partials, double *out, hipStream_t s) {
+                      const cx<T> *const *pc, double alpha, cx<T> *const *zf, const SpecParams &sp,
+                      double *partials, double *out, hipStream_t s) {
     KrylovSet<T> v{};
     for (int a = 0; a < 3; ++a) {
         v.p[a] = const_cast<cx<T> *>(rf[a]);
         v.p[3 + a] = const_cast<cx<T> *>(uc[a]);
         v.p[6 + a] = zf[a];
+        v.p[9 + a] = const_cast<cx<T> *>(pc[a]);
     }
     const T factor = (T)((double)gf.N / (double)gc.N);
     {
         HookScope hs(K_VECTOR, 6.0 * sizeof(cx<T>) * gf.NS);
         hipLaunchKernelGGL((k_tl_combine<T>), dim3(kRedBlocks), dim3(256), 0, s, gf.n1, gf.n2, gf.n3, gf.k3, gc.n2,
-                           gc.k3, (unsigned)gf.NS, sp.reg, (T)sp.beta_v, factor, 1.0 / (double)gf.N, v, partials);
+                           gc.k3, (unsigned)gf.NS, sp.reg, (T)sp.beta_v, factor, (T)alpha, 1.0 / (double)gf.N, v,
+                           partials);
     }
     HookScope hs(K_REDUCE, 8.0 * kRedBlocks);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, kRedBlocks, partials, out);
@@ -1045,16 +1090,17 @@ void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, co
     template void krylov_hessian<T>(const Grid &, const T *const *, const cx<T> *const *, cx<T> *const *,         \
                                     cx<T> *, const Twiddles<T> &, const SpecParams &, int, hipStream_t);         \
     template void krylov_direction<T>(const Grid &, const cx<T> *const *, cx<T> *const *, double, int,           \
-                                      T *const *, cx<T> *, const Twiddles<T> &, const SpecParams &, hipStream_t); \
+                                      cx<T> *const *, double, T *const *, cx<T> *, const Twiddles<T> &,          \
+                                      const SpecParams &, hipStream_t);                                          \
     template void twolevel_restrict<T>(const Grid &, const Grid &, const cx<T> *const *, cx<T> *const *,          \
                                        cx<T> *const *, const SpecParams &, hipStream_t);                          \
     template void twolevel_combine<T>(const Grid &, const Grid &, const cx<T> *const *, const cx<T> *const *,     \
-                                      cx<T> *const *, const SpecParams &, double *, double *, hipStream_t);       \
-    template void krylov_inverse<T>(const Grid &, const cx<T> *const *, T *const *, cx<T> *, const Twiddles<T> &, \
-                                    hipStream_t);                                                                \
-    template void krylov_update<T>(const Grid &, double, bool, cx<T> *const *, cx<T> *const *,                   \
-                                   const cx<T> *const *, const cx<T> *const *, const SpecParams &, double *,     \
-                                   double *, hipStream_t);
+                                      const cx<T> *const *, double, cx<T> *const *, const SpecParams &, double *, \
+                                      double *, hipStream_t);                                                    \
+    template void krylov_inverse<T>(const Grid &, const cx<T> *const *, const cx<T> *const *, double, T *const *, \
+                                    cx<T> *, const Twiddles<T> &, hipStream_t);                                  \
+    template void krylov_update<T>(const Grid &, double, bool, cx<T> *const *, const cx<T> *const *,             \
+                                   const SpecParams &, double *, double *, hipStream_t);
 MIREG_KRYLOV(float)
 MIREG_KRYLOV(double)
 #undef MIREG_KRYLOV
