@@ -384,6 +384,7 @@ struct KrylovPtrs {
     const void *a[3];  // spectral operand
     void *o[3];        // spectral output (read first in KP_DIR; read only, the old direction, in KP_INV)
     void *x[3];        // iterate updated with the old direction (KP_DIR with KF_XUPD)
+    const double *alpha;  // device step length of the KF_XUPD updates
 };
 
 // x1 passes of the Krylov iteration (flags: KF_*, kernels.hpp):
@@ -417,10 +418,11 @@ constexpr int krylov_bound() {
 }
 template <typename T, int L, int PASS>
 __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc,
-                                                                      T mu, T alpha, int flags,
+                                                                      T mu, int flags,
                                                                       const cx<T> *__restrict__ tw) {
     const bool first = flags & KF_FIRST, sqrt_scaled = flags & KF_SQRT, zraw = flags & KF_ZRAW;
     const bool xupd = flags & KF_XUPD;
+    const T alpha = xupd ? (T)*f.alpha : (T)0;
     constexpr int V = 1;
     constexpr int NT = krylov_threads<T, L>();
     using S = FftShape<T, L, V, NT>;
@@ -558,17 +560,23 @@ struct KrylovSet {
     cx<T> *p[12];
 };
 
-// Pointwise step of the spectral PCG: r -= alpha Hs (when write; the iterate
-// takes alpha s in the next direction pass), then per-workgroup partials of
-// sum_x r . M^{-1} r (part[b]) and sum_x r . r (part[nb + b]) from the
-// updated r.  Grid-stride over the NS modes with a fixed grid, so the sums
-// are reproducible.
+// Pointwise step of the spectral PCG: with update, alpha = res[num] / res[0]
+// (the step length from the sums of the previous passes, on the device) and,
+// when res[0] > 0, r -= alpha Hs (the iterate takes alpha s in the next
+// direction pass; res[3] = alpha, or 0 when res[0] <= 0 and r is kept);
+// then per-workgroup partials of sum_x r . M^{-1} r (part[b]) and
+// sum_x r . r (part[nb + b]) from r.  Grid-stride over the NS modes with a
+// fixed grid, so the sums are reproducible.
 template <typename T>
 __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int n2, int n3, int k3, int reg,
-                                                       T beta_v, T alpha, int write, KrylovSet<T> v,
+                                                       T beta_v, int update, int num, double *res, KrylovSet<T> v,
                                                        double norm, double *__restrict__ part) {
     cx<T> *const *r = v.p;
     const cx<T> *const *h = v.p + 3;
+    const double den = update ? res[0] : 0.0, step = update ? res[num] / den : 0.0;
+    const bool write = update && den > 0;
+    const T alpha = (T)step;
+    if (update && blockIdx.x == 0 && threadIdx.x == 0) res[3] = write ? step : 0.0;
     double rz = 0, rr = 0;
     for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NS; j += gridDim.x * 256u) {
         const unsigned i3 = j % (unsigned)k3, row = j / (unsigned)k3;
@@ -827,7 +835,7 @@ template void spectral_resample<double>(const Grid &, const Grid &, int, const d
 
 // ---- Krylov host passes ----
 template <typename T, int PASS>
-static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, T alpha, int flags,
+static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int flags,
                              const cx<T> *tw, hipStream_t s, int *blocks) {
     const long long Q = (long long)g.n2 * g.k3;
     // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3;
@@ -843,7 +851,7 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
         dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, alpha, flags, tw); \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw);    \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -883,7 +891,7 @@ void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *
     launch_x2<T, -1>(g, fw, 3, tw.t[1], s);
     SpecParams sp{};
     sp.reg = 1;
-    launch_x1_krylov<T, KP_FWD>(g, kp, krylov_const<T>(g, sp), (T)0, (T)0, 0, tw.t[0], s, nullptr);
+    launch_x1_krylov<T, KP_FWD>(g, kp, krylov_const<T>(g, sp), (T)0, 0, tw.t[0], s, nullptr);
 }
 
 template <typename T>
@@ -903,7 +911,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
     OpConst<T> oc = krylov_const<T>(g, sp);
     oc.red = sp.red;
     int blocks = 0;
-    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
+    launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
@@ -912,7 +920,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
 
 template <typename T>
 void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, int flags,
-                      cx<T> *const *xhat, double alpha, T *const *s_out, cx<T> *work, const Twiddles<T> &tw,
+                      cx<T> *const *xhat, const double *alpha, T *const *s_out, cx<T> *work, const Twiddles<T> &tw,
                       const SpecParams &sp, hipStream_t s) {
     FieldPtrs fw{}, fout{};
     KrylovPtrs kp{};
@@ -924,15 +932,16 @@ void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *sha
         kp.o[a] = shat[a];
         kp.x[a] = xhat ? xhat[a] : nullptr;
     }
-    if (xhat && !(flags & KF_FIRST)) flags |= KF_XUPD;
-    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, (T)alpha, flags, tw.t[0], s, nullptr);
+    kp.alpha = alpha;
+    if (xhat && alpha && !(flags & KF_FIRST)) flags |= KF_XUPD;
+    launch_x1_krylov<T, KP_DIR>(g, kp, krylov_const<T>(g, sp), (T)mu, flags, tw.t[0], s, nullptr);
     launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
     launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
 }
 
 template <typename T>
-void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *shat, double alpha, T *const *u,
-                    cx<T> *work, const Twiddles<T> &tw, hipStream_t s) {
+void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *shat, const double *alpha,
+                    T *const *u, cx<T> *work, const Twiddles<T> &tw, hipStream_t s) {
     FieldPtrs fw{}, fout{};
     KrylovPtrs kp{};
     for (int a = 0; a < 3; ++a) {
@@ -942,17 +951,18 @@ void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *
         kp.a[a] = hat[a];
         kp.o[a] = shat ? const_cast<cx<T> *>(shat[a]) : nullptr;
     }
+    kp.alpha = alpha;
     SpecParams sp{};
     sp.reg = 1;
-    launch_x1_krylov<T, KP_INV>(g, kp, krylov_const<T>(g, sp), (T)0, (T)alpha, shat ? KF_XUPD : 0, tw.t[0], s,
+    launch_x1_krylov<T, KP_INV>(g, kp, krylov_const<T>(g, sp), (T)0, shat && alpha ? KF_XUPD : 0, tw.t[0], s,
                                 nullptr);
     launch_x2<T, +1>(g, fw, 3, tw.t[1], s);
     launch_c2r<T>(g, fw, fout, 3, tw.t[2], s);
 }
 
 template <typename T>
-void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *rhat, const cx<T> *const *hhat,
-                   const SpecParams &sp, double *partials, double *out2, hipStream_t s) {
+void krylov_update(const Grid &g, bool update, int num, double *res, cx<T> *const *rhat, const cx<T> *const *hhat,
+                   const SpecParams &sp, double *partials, hipStream_t s) {
     KrylovSet<T> v{};
     for (int a = 0; a < 3; ++a) {
         v.p[a] = rhat[a];
@@ -960,14 +970,14 @@ void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *rhat, 
     }
     constexpr int nb = kRedBlocks;
     {
-        HookScope hs(K_KRYLOV_UPDATE, (write ? 9.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
+        HookScope hs(K_KRYLOV_UPDATE, (update ? 9.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
         hipLaunchKernelGGL((k_krylov_update<T>), dim3(nb), dim3(256), 0, s, (unsigned)g.NS, g.n1, g.n2, g.n3, g.k3,
-                           sp.reg, (T)sp.beta_v, (T)alpha, write ? 1 : 0, v,
+                           sp.reg, (T)sp.beta_v, update ? 1 : 0, num, res, v,
                            1.0 / ((double)g.n1 * g.n2 * g.n3), partials);
     }
     HookScope hs(K_REDUCE, 16.0 * nb);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials, out2);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, out2 + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials, res + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, res + 2);
 }
 
 // ---- Two-level preconditioner on Krylov spectra (fine grid n, coarse n/2) ----
@@ -1011,13 +1021,14 @@ __global__ __launch_bounds__(256) void k_tl_restrict(int n1f, int n2f, int k3f, 
 // Fine preconditioned residual z = c (F_H c r + Q_P u): on the modes below
 // n_a/4 on every axis c(k) (Nf/Nc) u(k), elsewhere sigma(k) r(k); partials
 // of sum_x r . z (part[b], fixed grid of kRedBlocks workgroups).  u is
-// u + alpha p (the nested CG's last update, pending) when alpha != 0.
+// u + alpha p (the nested CG's last update, pending) when palpha is given.
 template <typename T>
 __global__ __launch_bounds__(256) void k_tl_combine(int n1f, int n2f, int n3f, int k3f, int n2c, int k3c, unsigned NSf,
-                                                    int reg, T beta_v, T factor, T alpha, double norm,
-                                                    KrylovSet<T> v, double *__restrict__ part) {
+                                                    int reg, T beta_v, T factor, const double *palpha,
+                                                    double norm, KrylovSet<T> v, double *__restrict__ part) {
     cx<T> *const *rf = v.p, *const *uc = v.p + 3, *const *zf = v.p + 6;
     const cx<T> *const *pc = v.p + 9;
+    const T alpha = palpha ? (T)*palpha : (T)0;
     const int n1c = n1f / 2;
     double acc = 0;
     for (unsigned j = blockIdx.x * 256u + threadIdx.x; j < NSf; j += gridDim.x * 256u) {
@@ -1064,7 +1075,7 @@ void twolevel_restrict(const Grid &gf, const Grid &gc, const cx<T> *const *rf, c
 
 template <typename T>
 void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, const cx<T> *const *uc,
-                      const cx<T> *const *pc, double alpha, cx<T> *const *zf, const SpecParams &sp,
+                      const cx<T> *const *pc, const double *alpha, cx<T> *const *zf, const SpecParams &sp,
                       double *partials, double *out, hipStream_t s) {
     KrylovSet<T> v{};
     for (int a = 0; a < 3; ++a) {
@@ -1077,7 +1088,7 @@ void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, co
     {
         HookScope hs(K_VECTOR, 6.0 * sizeof(cx<T>) * gf.NS);
         hipLaunchKernelGGL((k_tl_combine<T>), dim3(kRedBlocks), dim3(256), 0, s, gf.n1, gf.n2, gf.n3, gf.k3, gc.n2,
-                           gc.k3, (unsigned)gf.NS, sp.reg, (T)sp.beta_v, factor, (T)alpha, 1.0 / (double)gf.N, v,
+                           gc.k3, (unsigned)gf.NS, sp.reg, (T)sp.beta_v, factor, alpha, 1.0 / (double)gf.N, v,
                            partials);
     }
     HookScope hs(K_REDUCE, 8.0 * kRedBlocks);
@@ -1090,17 +1101,17 @@ void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, co
     template void krylov_hessian<T>(const Grid &, const T *const *, const cx<T> *const *, cx<T> *const *,         \
                                     cx<T> *, const Twiddles<T> &, const SpecParams &, int, hipStream_t);         \
     template void krylov_direction<T>(const Grid &, const cx<T> *const *, cx<T> *const *, double, int,           \
-                                      cx<T> *const *, double, T *const *, cx<T> *, const Twiddles<T> &,          \
+                                      cx<T> *const *, const double *, T *const *, cx<T> *, const Twiddles<T> &,  \
                                       const SpecParams &, hipStream_t);                                          \
     template void twolevel_restrict<T>(const Grid &, const Grid &, const cx<T> *const *, cx<T> *const *,          \
                                        cx<T> *const *, const SpecParams &, hipStream_t);                          \
     template void twolevel_combine<T>(const Grid &, const Grid &, const cx<T> *const *, const cx<T> *const *,     \
-                                      const cx<T> *const *, double, cx<T> *const *, const SpecParams &, double *, \
-                                      double *, hipStream_t);                                                    \
-    template void krylov_inverse<T>(const Grid &, const cx<T> *const *, const cx<T> *const *, double, T *const *, \
-                                    cx<T> *, const Twiddles<T> &, hipStream_t);                                  \
-    template void krylov_update<T>(const Grid &, double, bool, cx<T> *const *, const cx<T> *const *,             \
-                                   const SpecParams &, double *, double *, hipStream_t);
+                                      const cx<T> *const *, const double *, cx<T> *const *, const SpecParams &,   \
+                                      double *, double *, hipStream_t);                                          \
+    template void krylov_inverse<T>(const Grid &, const cx<T> *const *, const cx<T> *const *, const double *,     \
+                                    T *const *, cx<T> *, const Twiddles<T> &, hipStream_t);                      \
+    template void krylov_update<T>(const Grid &, bool, int, double *, cx<T> *const *, const cx<T> *const *,      \
+                                   const SpecParams &, double *, hipStream_t);
 MIREG_KRYLOV(float)
 MIREG_KRYLOV(double)
 #undef MIREG_KRYLOV

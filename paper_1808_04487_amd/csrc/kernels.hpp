@@ -95,35 +95,38 @@ void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *
 template <typename T>
 void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
                     const Twiddles<T> &tw, const SpecParams &sp, int flags, hipStream_t s);
-// xhat += alpha shat (when xhat is given and not KF_FIRST: the iterate's
-// update of the previous iteration, from the old direction), then
-// shat = z + mu shat (shat not read with KF_FIRST), z = M^{-1} rhat (rhat
-// itself with KF_ZRAW); s_out = F^{-1} shat (F^{-1} c shat with KF_SQRT)
+// xhat += alpha shat (when xhat and alpha are given and not KF_FIRST: the
+// iterate's update of the previous iteration, from the old direction; alpha
+// a device scalar), then shat = z + mu shat (shat not read with KF_FIRST),
+// z = M^{-1} rhat (rhat itself with KF_ZRAW); s_out = F^{-1} shat
+// (F^{-1} c shat with KF_SQRT)
 template <typename T>
 void krylov_direction(const Grid &g, const cx<T> *const *rhat, cx<T> *const *shat, double mu, int flags,
-                      cx<T> *const *xhat, double alpha, T *const *s_out, cx<T> *work, const Twiddles<T> &tw,
+                      cx<T> *const *xhat, const double *alpha, T *const *s_out, cx<T> *work, const Twiddles<T> &tw,
                       const SpecParams &sp, hipStream_t s);
 // Two-level preconditioner on spectra: rc = pc = Q_R c rf (coarse grid gc =
-// gf / 2); zf = c (F_H c rf + Q_P (uc + alpha pc)) and *out = sum_x r . z
-// (partials: kRedBlocks)
+// gf / 2); zf = c (F_H c rf + Q_P (uc + alpha pc)) (alpha a device scalar,
+// none when null) and *out = sum_x r . z (partials: kRedBlocks)
 template <typename T>
 void twolevel_restrict(const Grid &gf, const Grid &gc, const cx<T> *const *rf, cx<T> *const *rc, cx<T> *const *pc,
                        const SpecParams &sp, hipStream_t s);
 template <typename T>
 void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, const cx<T> *const *uc,
-                      const cx<T> *const *pc, double alpha, cx<T> *const *zf, const SpecParams &sp,
+                      const cx<T> *const *pc, const double *alpha, cx<T> *const *zf, const SpecParams &sp,
                       double *partials, double *out, hipStream_t s);
-// u = F^{-1} hat, or F^{-1} (hat + alpha shat) when shat is given
+// u = F^{-1} hat, or F^{-1} (hat + alpha shat) when shat and the device
+// scalar alpha are given
 template <typename T>
-void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *shat, double alpha, T *const *u,
-                    cx<T> *work, const Twiddles<T> &tw, hipStream_t s);
-// rhat -= alpha hhat (when write; the iterate is updated by the next
-// krylov_direction or the final krylov_inverse); then out2[0] =
-// sum_x r . M^{-1} r and out2[1] = sum_x r . r (device); partials holds
-// 2 kRedBlocks doubles
+void krylov_inverse(const Grid &g, const cx<T> *const *hat, const cx<T> *const *shat, const double *alpha,
+                    T *const *u, cx<T> *work, const Twiddles<T> &tw, hipStream_t s);
+// res: device doubles.  With update: alpha = res[num] / res[0] and, when
+// res[0] > 0, rhat -= alpha hhat, res[3] = alpha (0 when res[0] <= 0; the
+// iterate is updated by the next krylov_direction or the final
+// krylov_inverse).  Then res[1] = sum_x r . M^{-1} r and res[2] = sum_x r . r.
+// partials holds 2 kRedBlocks doubles.
 template <typename T>
-void krylov_update(const Grid &g, double alpha, bool write, cx<T> *const *rhat, const cx<T> *const *hhat,
-                   const SpecParams &sp, double *partials, double *out2, hipStream_t s);
+void krylov_update(const Grid &g, bool update, int num, double *res, cx<T> *const *rhat, const cx<T> *const *hhat,
+                   const SpecParams &sp, double *partials, hipStream_t s);
 
 // Spectral resampling between two grids (each axis the same or half/double
 // the size): out = the trigonometric interpolant of in, truncated to the

@@ -784,43 +784,45 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
         Phase ph(ctx, 0);  // r = p = Q_R c r_fine, u = 0
         twolevel_restrict<T>(ctx->g, c->g, rf, rcs, pc, sp, c->stream);
         fill<T>(6 * c->g.NS, (T)0, reinterpret_cast<T *>(uc[0]), c->stream);
-        krylov_update<T>(c->g, 0.0, false, rcs, qc, sp, c->partials, c->dres + 1, c->stream);
+        krylov_update<T>(c->g, false, 2, c->dres, rcs, qc, sp, c->partials, c->stream);
     }
     if ((rc = readback(c, 3))) return rc;
     double rr = h3c * c->hres[2];
     const double tol = ctx->pc_kappa * eps_h * std::sqrt(rr);
     if (rr > 0) {
         Phase ph(ctx, 0);
-        krylov_direction<T>(c->g, rcs, pc, 0.0, KF_FIRST | KF_ZRAW | KF_SQRT, uc, 0.0, wp, cwork, tw, sp,
+        krylov_direction<T>(c->g, rcs, pc, 0.0, KF_FIRST | KF_ZRAW | KF_SQRT, uc, nullptr, wp, cwork, tw, sp,
                             c->stream);
     }
     c->use_graphs = ctx->use_graphs;
-    double pending = 0;  // u takes alpha p in the next direction pass, or in the combine
+    // The step length alpha = rr / pq is formed on the device (c->dres[3]) by
+    // the update, so an iteration reads back once; u takes alpha p in the
+    // next direction pass, or in the combine when the loop stops on the
+    // tolerance.
+    bool pending = false;
     for (int it = 0; it < ctx->pc_max_inner && std::sqrt(rr) > tol; ++it) {
-        if ((rc = matvec_graph<T, S>(c, w, nullptr, true, KF_SQRT))) return rc;  // S p into KV_H
+        if ((rc = matvec_graph<T, S>(c, w, nullptr, true, KF_SQRT))) return rc;  // S p into KV_H, pq
         ctx->coarse_matvecs += 1;
-        if ((rc = readback(c, 1))) return rc;
-        const double pq = h3c * c->hres[0];
-        if (!(pq > 0)) break;
-        const double alpha = rr / pq;
-        krylov_update<T>(c->g, alpha, true, rcs, qc, sp, c->partials, c->dres + 1, c->stream);
+        krylov_update<T>(c->g, true, 2, c->dres, rcs, qc, sp, c->partials, c->stream);
         if ((rc = readback(c, 3))) return rc;
+        const double pq = h3c * c->hres[0];
+        if (!(pq > 0)) break;  // r was left unchanged
         const double rr_new = h3c * c->hres[2];
         if (std::sqrt(rr_new) <= tol) {
-            pending = alpha;
+            pending = true;
             break;
         }
         {
             Phase ph(ctx, 0);  // u += alpha p, then p = r + beta p
-            krylov_direction<T>(c->g, rcs, pc, rr_new / rr, KF_ZRAW | KF_SQRT, uc, alpha, wp, cwork, tw, sp,
+            krylov_direction<T>(c->g, rcs, pc, rr_new / rr, KF_ZRAW | KF_SQRT, uc, c->dres + 3, wp, cwork, tw, sp,
                                 c->stream);
         }
         rr = rr_new;
     }
     {
         Phase ph(ctx, 0);
-        twolevel_combine<T>(ctx->g, c->g, rf, uc, pc, pending, zf, spec_params<T>(ctx), ctx->partials,
-                            ctx->dres + 1, ctx->stream);
+        twolevel_combine<T>(ctx->g, c->g, rf, uc, pc, pending ? c->dres + 3 : nullptr, zf, spec_params<T>(ctx),
+                            ctx->partials, ctx->dres + 1, ctx->stream);
     }
     if ((rc = readback(ctx, 2))) return rc;
     *rz = ctx->cell() * ctx->hres[1];
@@ -860,7 +862,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
         Phase ph(ctx, 0);
         krylov_forward<T>(ctx->g, rp, rh, work, tw, ctx->stream);  // r = rhs, x = 0
         fill<T>(6 * ctx->g.NS, (T)0, reinterpret_cast<T *>(xh[0]), ctx->stream);
-        krylov_update<T>(ctx->g, 0.0, false, rh, hh, sp, ctx->partials, ctx->dres + 1, ctx->stream);
+        krylov_update<T>(ctx->g, false, 1, ctx->dres, rh, hh, sp, ctx->partials, ctx->stream);
     }
     if ((rc = readback(ctx, 3))) return rc;
     const double r0 = std::sqrt(h3 * ctx->hres[2]);
@@ -868,31 +870,35 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     int it = 0;
     double rnorm = r0;
     bool x_is_s = false;
-    double pending = 0;  // x takes alpha s in the next direction pass, or in the final transform
+    // The step length alpha = rz / sHs is formed on the device (dres[3]) by
+    // the update, so an iteration reads back once; x takes alpha s in the next
+    // direction pass, or in the final transform when the loop stops on the
+    // tolerance.
+    bool pending = false;
     if (r0 > 0) {
         if (two_level && (rc = two_level_spectral<T, S>(ctx, rtol, &rz))) return rc;
         {
             Phase ph(ctx, 0);  // s = z = M^{-1} r
-            krylov_direction<T>(ctx->g, zsrc, sh, 0.0, KF_FIRST | zflag, xh, 0.0, sp3, work, tw, sp, ctx->stream);
+            krylov_direction<T>(ctx->g, zsrc, sh, 0.0, KF_FIRST | zflag, xh, nullptr, sp3, work, tw, sp,
+                                ctx->stream);
         }
         while (it < maxit) {
-            if ((rc = matvec_graph<T, S>(ctx, s, nullptr, true))) return rc;
-            if ((rc = readback(ctx, 1))) return rc;
+            if ((rc = matvec_graph<T, S>(ctx, s, nullptr, true))) return rc;  // H s, sHs
+            {
+                Phase ph(ctx, 2);
+                krylov_update<T>(ctx->g, true, 1, ctx->dres, rh, hh, sp, ctx->partials, ctx->stream);
+            }
+            if ((rc = readback(ctx, 3))) return rc;
             const double sHs = h3 * ctx->hres[0];
-            if (!(sHs > 0)) {  // non-positive curvature: keep the current iterate (z on the first)
+            if (!(sHs > 0)) {  // non-positive curvature (r was left unchanged): keep the current
+                               // iterate (z on the first)
                 x_is_s = it == 0;
                 break;
             }
-            const double alpha = rz / sHs;
-            {
-                Phase ph(ctx, 2);
-                krylov_update<T>(ctx->g, alpha, true, rh, hh, sp, ctx->partials, ctx->dres + 1, ctx->stream);
-            }
-            if ((rc = readback(ctx, 3))) return rc;
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[2]);
             if (rnorm <= rtol * r0) {
-                pending = alpha;
+                pending = true;
                 break;
             }
             double rz_new = h3 * ctx->hres[1];
@@ -901,7 +907,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
             rz = rz_new;
             {
                 Phase ph(ctx, 0);  // x += alpha s, then s = z + mu s
-                krylov_direction<T>(ctx->g, zsrc, sh, mu, zflag, xh, alpha, sp3, work, tw, sp, ctx->stream);
+                krylov_direction<T>(ctx->g, zsrc, sh, mu, zflag, xh, ctx->dres + 3, sp3, work, tw, sp, ctx->stream);
             }
         }
     }
@@ -909,7 +915,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
         HIP_OK(hipMemcpyAsync(x, s, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     } else if (it > 0) {
         Phase ph(ctx, 0);
-        krylov_inverse<T>(ctx->g, xh, pending != 0 ? sh : nullptr, pending, xp, work, tw, ctx->stream);
+        krylov_inverse<T>(ctx->g, xh, pending ? sh : nullptr, ctx->dres + 3, xp, work, tw, ctx->stream);
     } else {
         fill<T>(3 * N, (T)0, x, ctx->stream);
     }
