@@ -28,7 +28,10 @@ tolerance; kappa 0.1 as in the paper, and 0.5).
 and autotuned tiles, against one stream without either.
 "warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
 trained network's prediction (paper_1808_04487_amd/weights) to the same
-absolute gradient tolerance.
+absolute gradient tolerance.  "analytic_32" gives the time to tolerance of
+the paper's analytic problem at 32^3 in FP64, on the GPU and (with the CPU
+baseline) by the FP64 oracle on the host cores, with their iteration
+counters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -139,6 +142,59 @@ def cpu_baseline(args):
 
 
 OPTS = dict(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+ANALYTIC_OPTS = dict(grad_rtol=1e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+ANALYTIC_KEYS = ("status", "gn_iters", "matvecs", "pde_solves", "ls_trials")
+
+
+def analytic_gpu(args, torch, mireg):
+    """The paper's analytic problem at 32^3 in FP64 (H1-div, beta_v = 1e-2,
+    beta_w = 1, nt = 4, tricubic, relative gradient 1e-2): the reference is
+    the template transported by the library; median time to tolerance of 5
+    solves from v = 0 after one untimed."""
+    from paper_1808_04487_amd import synth
+
+    n = (32, 32, 32)
+    ctx = mireg.Context(n, nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=1e-2, beta_w=1.0,
+                        dtype=torch.float64)
+    mT = torch.from_numpy(synth.trig_template(n)).to(ctx.device)
+    ctx.set_velocity(torch.from_numpy(synth.trig_velocity(n)).to(ctx.device))
+    mR = ctx.op("transport_state", mT)
+    ctx.set_velocity(torch.zeros((3,) + n, dtype=torch.float64, device=ctx.device))
+    ctx.set_images(mT, mR)
+    ctx.gn_solve(**ANALYTIC_OPTS)
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = ctx.gn_solve(**ANALYTIC_OPTS)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ctx.close()
+    out = {k: rep[k] for k in ANALYTIC_KEYS + ("mismatch_rel", "gnorm_rel")}
+    out["time_to_tol_s"] = round(sorted(ts)[2], 5)
+    return out
+
+
+def analytic_cpu(args):
+    """The same problem solved by the FP64 oracle on the host cores (its own
+    reference image), for the CPU baseline."""
+    import numpy as np
+
+    from oracle import core, prep, solver
+    from paper_1808_04487_amd import synth
+
+    n = (32, 32, 32)
+    g = core.Grid(n)
+    mT = synth.trig_template(n)
+    mR = prep.transport(g, mT, synth.trig_velocity(n))
+    p = core.Params(n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=1e-2, beta_w=1.0)
+    R = core.Registration(p, mT, mR)
+    t0 = time.perf_counter()
+    _, rep = solver.gn_solve(R, np.zeros((3,) + n), **ANALYTIC_OPTS)
+    t = time.perf_counter() - t0
+    out = {k: getattr(rep, k) for k in ANALYTIC_KEYS + ("mismatch_rel",)}
+    out["time_to_tol_s"] = round(t, 4)
+    return out
 
 
 def timed_solves(args, ctx, torch, warmup, steps):
@@ -372,10 +428,17 @@ def main():
         log(args, "FP16-storage variant")
         prec = precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, reps[-1])
 
+    log(args, "analytic problem, 32^3 FP64")
+    analytic = {"workload": "the paper's analytic problem (Sec. 4.2) at 32^3 FP64, H1-div beta_v=1e-2 beta_w=1, "
+                            "nt=4 tricubic, spectral PC, relative gradient 1e-2",
+                "gpu": analytic_gpu(args, torch, mireg)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log(args, "timing the CPU oracle sample")
         cpu = cpu_baseline(args)
+        analytic["cpu_oracle"] = analytic_cpu(args)
+        analytic["same_counters"] = all(analytic["gpu"][k] == analytic["cpu_oracle"][k] for k in ANALYTIC_KEYS)
 
     solve_s = wall / max(1, args.steps)
     line = {
@@ -409,6 +472,7 @@ def main():
         "two_level": two,
         "batched": bat,
         "warm_start": warm,
+        "analytic_32": analytic,
         "kernels": kernels,
     }
     ctx.close()
