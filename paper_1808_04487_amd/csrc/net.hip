@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -110,6 +111,99 @@ __global__ __launch_bounds__(kNetThreads) void k_conv(ConvGeom g, const __bf16 *
             const unsigned v = vbase + 4 * (lane >> 4) + i;
             if (v < g.V) {
                 float x = acc[j][i] + bj;
+                if (res) x += (float)res[(size_t)v * COUT + co];
+                if (relu) x = fmaxf(x, 0.f);
+                out[(size_t)v * COUT + co] = (OT)x;
+            }
+        }
+    }
+}
+
+// Block-tiled variant of k_conv for grids of 64^3 and up: a workgroup owns a
+// 4 x 4 x 16 (x1, x2, x3) tile of output voxels, stages the input it reads
+// (the tile and a one-voxel halo, or the 4 x 4 x 10 coarse voxels behind it
+// when the input is upsampled) once in LDS, and each wave computes four rows
+// of 16 voxels (x1 = tile + wave, x2 = tile + row) x all COUT channels, so a
+// B fragment serves four MFMAs and the A fragments are 16-byte LDS reads
+// instead of per-tap global gathers.  Same reduction chunks in the same
+// order as k_conv, hence the same results.
+template <int CIN, bool UP>
+struct ConvTile {
+    static constexpr int E1 = UP ? 4 : 6, E2 = UP ? 4 : 6, E3 = UP ? 10 : 18;
+    static constexpr int NVOX = E1 * E2 * E3;
+    static constexpr int BYTES = NVOX * CIN * 2;
+    // tile-relative fine index (0 .. extent + 1, halo included) -> staged index
+    static __device__ __forceinline__ int at(int x) { return UP ? (x + 1) >> 1 : x; }
+};
+template <int CIN, int COUT, bool UP, typename OT>
+__global__ __launch_bounds__(kNetThreads) void k_conv_tile(ConvGeom g, const __bf16 *__restrict__ in,
+                                                          const __bf16 *__restrict__ W,
+                                                          const float *__restrict__ bias,
+                                                          const __bf16 *__restrict__ res, int relu,
+                                                          OT *__restrict__ out) {
+    using TL = ConvTile<CIN, UP>;
+    constexpr int KPAD = conv_kpad<CIN>();
+    constexpr int NT = COUT / 16;
+    constexpr int CH = CIN / 8;  // 16-byte chunks per staged voxel
+    __shared__ __align__(16) __bf16 tile[TL::NVOX * CIN];
+    const int lg = g.lg, n = 1 << lg;
+    const int tx3 = n >> 4, tx2 = n >> 2;
+    const int b = (int)blockIdx.x;
+    const int o3 = (b % tx3) << 4, o2 = ((b / tx3) % tx2) << 2, o1 = (b / (tx3 * tx2)) << 2;
+    // 1. stage: staged voxel (z, y, x) is input voxel base + (z, y, x), wrapped
+    {
+        const int lgi = g.lg_in, mi = (1 << lgi) - 1;
+        const int b1 = (UP ? o1 >> 1 : o1) - 1, b2 = (UP ? o2 >> 1 : o2) - 1, b3 = (UP ? o3 >> 1 : o3) - 1;
+        for (int q = (int)threadIdx.x; q < TL::NVOX * CH; q += kNetThreads) {
+            const int vox = q / CH, part = q % CH;
+            const int z = vox / (TL::E2 * TL::E3), y = (vox / TL::E3) % TL::E2, x = vox % TL::E3;
+            const unsigned src = ((unsigned)((b1 + z) & mi) << (2 * lgi)) | ((unsigned)((b2 + y) & mi) << lgi) |
+                                 (unsigned)((b3 + x) & mi);
+            *reinterpret_cast<bf16x8 *>(tile + vox * CIN + 8 * part) =
+                *reinterpret_cast<const bf16x8 *>(in + (size_t)src * CIN + 8 * part);
+        }
+    }
+    __syncthreads();
+    // 2. implicit GEMM: lane l holds A rows of voxel x3 = l % 16, k-slice 8 (l / 16)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = 8 * (lane >> 4), x3 = lane & 15;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __bf16 *wrow = W + (size_t)(lane & 15) * KPAD + kq;
+    for (int c = 0; c < KPAD / 32; ++c) {
+        const int k0 = 32 * c + kq;
+        const int tap = k0 / CIN, ci = k0 % CIN;
+        const bool tapok = tap < 27;
+        const int d1 = tap / 9, d2 = (tap / 3) % 3, d3 = tap % 3;
+        bf16x8 bw[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bw[j] = *reinterpret_cast<const bf16x8 *>(wrow + (size_t)16 * j * KPAD + 32 * c);
+        const int zx = TL::at(wave + d1) * TL::E2;
+        const int xx = TL::at(x3 + d3);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bf16x8 a = {};
+            if (tapok)
+                a = *reinterpret_cast<const bf16x8 *>(tile + ((zx + TL::at(r + d2)) * TL::E3 + xx) * CIN + ci);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[r][j] = mfma16(a, bw[j], acc[r][j]);
+        }
+    }
+    // 3. bias, skip, ReLU; D row 4 (l / 16) + i is voxel x3 = that row
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned vrow = ((unsigned)(o1 + wave) << (2 * lg)) | ((unsigned)(o2 + r) << lg) | (unsigned)o3;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = 16 * j + (lane & 15);
+            const float bj = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned v = vrow + 4 * (lane >> 4) + i;
+                float x = acc[r][j][i] + bj;
                 if (res) x += (float)res[(size_t)v * COUT + co];
                 if (relu) x = fmaxf(x, 0.f);
                 out[(size_t)v * COUT + co] = (OT)x;
@@ -465,9 +559,24 @@ __global__ void k_voronoi(int lg, int ns, const float *__restrict__ seeds, const
 inline unsigned nblocks(size_t n, int t = kNetThreads) { return (unsigned)((n + t - 1) / t); }
 
 // ---- template dispatch over channel counts ----
+// The block-tiled kernel on cubic grids of 64^3 and up (at least 1024 tiles)
+// whose staged input fits 64 KB of LDS; k_conv otherwise, or always with
+// MIREG_CONV_TILE=0 in the environment (the two give identical results).
+inline bool conv_tile_enabled() {
+    const char *e = getenv("MIREG_CONV_TILE");
+    return !(e && e[0] == '0');
+}
 template <int CIN, int COUT, bool UP, typename OT>
 void conv_go(ConvGeom g, const __bf16 *in, const __bf16 *W, const float *b, const __bf16 *res, int relu, OT *out,
              hipStream_t s) {
+    if constexpr (ConvTile<CIN, UP>::BYTES <= 65536) {
+        if (g.lg >= 6 && conv_tile_enabled()) {
+            const unsigned ntiles = g.V / 256u;
+            hipLaunchKernelGGL((k_conv_tile<CIN, COUT, UP, OT>), dim3(ntiles), dim3(kNetThreads), 0, s, g, in, W, b,
+                               res, relu, out);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_conv<CIN, COUT, UP, OT>), dim3(nblocks(g.V, 64)), dim3(kNetThreads), 0, s, g, in, W, b, res,
                        relu, out);
 }

@@ -64,6 +64,29 @@ def test_forward_and_gradient_match_oracle(n, ch):
     assert o == theta.size
 
 
+def test_tiled_convolutions_equal_the_gather_kernel(monkeypatch):
+    """At 64^3 the finest level's convolutions (forward and data adjoint) run
+    the block-tiled kernel; with MIREG_CONV_TILE=0 they run the per-tap
+    gather kernel.  Same reduction order: identical forward and gradient.
+    The forward stays within the FP64 bound of the other sizes."""
+    need_gpu()
+    n, ch = 64, (16, 32, 64, 128)
+    net, theta, (mT, mR, _), (mT_t, mR_t, vt_t) = setup(n, ch, seed=7)
+    v1 = net.forward(mT_t, mR_t).clone()
+    e64 = rel_l2(v1, onet.Net(n, ch, 2.0).forward(theta.astype(np.float64), mT, mR))
+    print("64^3 forward vs FP64 %.2e" % e64, flush=True)
+    assert e64 < 3e-2
+    l1, g1 = net.loss_grad(mT_t, mR_t, vt_t)
+    g1 = np.array(g1, copy=True)
+    monkeypatch.setenv("MIREG_CONV_TILE", "0")
+    v0 = net.forward(mT_t, mR_t).clone()
+    l0, g0 = net.loss_grad(mT_t, mR_t, vt_t)
+    print("tiled vs gather: forward max diff %.3e, loss %.9e / %.9e" % ((v1 - v0).abs().max().item(), l1, l0),
+          flush=True)
+    assert torch.equal(v1, v0)
+    assert l1 == l0 and np.array_equal(g1, np.asarray(g0))
+
+
 def test_adam_step_and_training_reduce_the_loss():
     """First Adam step moves each parameter by about lr sign(g); a few
     steps on one pair reduce its loss."""
