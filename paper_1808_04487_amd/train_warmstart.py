@@ -5,7 +5,11 @@ warm-started and zero-initialised solves on held-out pairs.
       --out paper_1808_04487_amd/weights/warmstart_128.npz
 
 Pairs use seeds 0..pairs-1; held-out pairs use seeds from 1000000 on.  One
-line of progress is printed at least every few seconds.
+line of progress is printed at least every few seconds.  With --init WEIGHTS
+and --steps 0 only the held-out evaluation of those weights runs:
+
+  python -m paper_1808_04487_amd.train_warmstart --init paper_1808_04487_amd/weights/warmstart_128.npz \
+      --pairs 0 --steps 0 --eval 256 --report eval.json
 """
 import argparse
 import json
@@ -78,10 +82,16 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=16, help="held-out pairs")
     ap.add_argument("--out", default=os.path.join(warmstart.WEIGHTS_DIR, "warmstart_128.npz"))
     ap.add_argument("--report", default=None, help="JSON file for the evaluation")
+    ap.add_argument("--init", default=None, help="start from these weights (with --steps 0: evaluate them only)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    net = warmstart.WarmStartNet(args.n)
-    net.set_params(warmstart.init_params(warmstart.CHANNELS, args.seed))
+    if args.init:
+        net = warmstart.WarmStartNet.load(args.init)
+        if net.n != args.n:
+            raise SystemExit("weights are for n = %d, not %d" % (net.n, args.n))
+    else:
+        net = warmstart.WarmStartNet(args.n)
+        net.set_params(warmstart.init_params(warmstart.CHANNELS, args.seed))
     ctx = warmstart.registration_context(args.n)
     log("network %d parameters, n = %d" % (net.param_count, args.n))
     pairs = generate(net, ctx, range(args.pairs))
@@ -95,9 +105,10 @@ def main(argv=None):
         if time.perf_counter() - last > 10 or s == args.steps - 1:
             last = time.perf_counter()
             log("step %d/%d loss %.4e lr %.2e (%.1f s)" % (s + 1, args.steps, loss, lr, last - t0))
-    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    net.save(args.out)
-    log("saved", args.out)
+    if args.steps > 0:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        net.save(args.out)
+        log("saved", args.out)
     del pairs
     rows = evaluate(net, ctx, range(HELD_OUT_SEED, HELD_OUT_SEED + args.eval))
     summ = summary(rows)
