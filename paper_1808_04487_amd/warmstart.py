@@ -184,7 +184,7 @@ def init_params(channels, seed):
 
 # ---- training data ----
 def registration_context(n, device=None):
-    """The solver configuration that produces and judges the targets."""
+    """The solver configuration that labels the training pairs and evaluates the warm start."""
     return mireg.Context((n, n, n), nt=4, order=3, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0,
                          dtype=torch.float32, device=device)
 
