@@ -43,3 +43,30 @@ def test_trained_warm_start_beats_zero_init():
     assert a[:, 3].sum() < 0.7 * a[:, 2].sum()    # 30% fewer matvecs
     assert a[:, 5].sum() < 0.85 * a[:, 4].sum()   # 15% less wall time
     assert np.median(a[:, 7] / a[:, 6]) <= 1.05   # mismatch no worse
+
+
+@pytest.mark.timeout(600)
+def test_trained_network_at_128_matches_oracle():
+    """The production configuration: trained weights on a phantom pair at
+    128^3 (block-tiled convolutions on the two finest levels), against the
+    oracle's BF16 storage model and plain FP64.  A trained network is far
+    less sensitive to BF16 rounding ties than a randomly initialised one, so
+    the model bound of the smaller parity cases holds here."""
+    need_gpu()
+    from oracle import net as onet
+
+    net = warmstart.WarmStartNet.load(WEIGHTS)
+    theta = net.get_params().astype(np.float64)
+    ctx = warmstart.registration_context(128)
+    mT, mR, _, _, _ = warmstart.make_pair(net, ctx, 3000001, solve=False)
+    v = net.forward(mT, mR).double().cpu().numpy()
+    ctx.close()
+    O = onet.Net(128, net.channels, net.skip_sigma)
+    a, b = mT.cpu().numpy(), mR.cpu().numpy()
+    print("oracle forward at 128^3 (BF16 model, then FP64)", flush=True)
+    v16 = O.forward(theta, a, b, bf16=True)
+    v64 = O.forward(theta, a, b)
+    e16 = np.linalg.norm(v - v16) / np.linalg.norm(v16)
+    e64 = np.linalg.norm(v - v64) / np.linalg.norm(v64)
+    print("trained network 128^3: vs BF16 model %.2e, vs FP64 %.2e" % (e16, e64), flush=True)
+    assert e16 < 2e-3 and e64 < 3e-2
