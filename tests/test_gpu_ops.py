@@ -122,6 +122,17 @@ def test_errors_are_reported():
     assert e.value.code == mireg.E_NONFINITE
     with pytest.raises(ValueError):
         ctx.set_velocity(torch.zeros((3, 8, 8, 8), dtype=torch.float32, device="cuda"))
+    vinf = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
+    vinf[2, 0, 0, 0] = float("inf")
+    with pytest.raises(mireg.MiregError) as e:
+        ctx.set_velocity(vinf)
+    assert e.value.code == mireg.E_NONFINITE
+    # straight through the C ABI: null pointers and an aliased matvec output
+    v = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
+    assert ctx.lib.mireg_hessian_matvec(ctx.h, None, None) == mireg.E_ARG
+    assert ctx.lib.mireg_hessian_matvec(ctx.h, v.data_ptr(), v.data_ptr()) == mireg.E_ARG
+    assert ctx.lib.mireg_gradient(ctx.h, None, None) == mireg.E_ARG
+    ctx.close()
 
 
 def test_tile_shapes_agree_bitwise(monkeypatch):
