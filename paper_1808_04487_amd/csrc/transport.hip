@@ -329,6 +329,14 @@ __device__ __forceinline__ bool block_box(int *box, int mn1, int mn2, int mn3, i
     return box[0] != INT_MAX;
 }
 
+// One-field FP32 ops whose staged value is the loaded value (the state and
+// incremental-state steps): their box goes from global memory straight into
+// LDS (global_load_lds_dword), without passing through registers.
+template <class Op>
+struct DirectStage {
+    static constexpr bool value = false;
+};
+
 // Generic tiled semi-Lagrangian sweep.  Op provides:
 //   void disp(unsigned idx, T *d)       displacement of point idx (cells, 3 values)
 //   void stage(unsigned plane, unsigned rc, T *v)
@@ -421,6 +429,24 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             }
             auto planes = [&](auto cols) {
                 constexpr int JJ = decltype(cols)::value;
+                if constexpr (DirectStage<Op>::value) {
+                    // lane l of a wave writes the LDS word at a wave-uniform base + l: the
+                    // wave's 64 consecutive plane positions; lanes past the plane are
+                    // masked off (no spare node), the loads complete before the barrier
+                    const int wave = (int)threadIdx.x >> 6;
+                    for (int z = 0; z < E1; ++z) {
+                        const unsigned plane = __umul24(wrap(lo1 + z, g.n1, g.m1), n23);
+                        const float *srcp = op.direct_src(plane);
+#pragma unroll
+                        for (int j = 0; j < JJ; ++j) {
+                            const int base = z * E23 + 64 * wave + kSlThreads * j;
+                            if (rk[j] >= 0)
+                                __builtin_amdgcn_global_load_lds(srcp + rc[j], lds + base, 4, 0, 0);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    return;
+                }
                 unsigned src[JJ];
 #pragma unroll
                 for (int j = 0; j < JJ; ++j) src[j] = rk[j] >= 0 ? rc[j] : rc[0];
@@ -644,6 +670,7 @@ struct InterpOp {
     }
     __device__ void stage(unsigned pl, unsigned i, T *x) const { x[0] = ld<T>(f + pl, i); }
     __device__ void staged(T *) const {}
+    __device__ const SI *direct_src(unsigned pl) const { return f + pl; }
     struct Pre {};
     __device__ Pre pre(unsigned) const { return Pre{}; }
     __device__ void finish(unsigned i, const Pre &, const T *a) const { st(out, i, a[0]); }
@@ -737,6 +764,7 @@ struct IncStateOp {
     }
     __device__ void stage(unsigned pl, unsigned i, T *x) const { x[0] = ld<T>(qin + pl, i); }
     __device__ void staged(T *) const {}
+    __device__ const SQ *direct_src(unsigned pl) const { return qin + pl; }
     struct Pre {
         T f;
     };
@@ -745,6 +773,15 @@ struct IncStateOp {
                      ld<T>(gm, 2 * N + i) * ld<T>(vt, 2 * N + i))};
     }
     __device__ void finish(unsigned i, const Pre &p, const T *a) const { st(qout, i, sign * (a[0] + coef * p.f)); }
+};
+
+template <>
+struct DirectStage<InterpOp<float, float, float>> {
+    static constexpr bool value = true;
+};
+template <>
+struct DirectStage<IncStateOp<float, float>> {
+    static constexpr bool value = true;
 };
 
 // Final condition of the adjoint: lambda(1) = mR - m(1).
