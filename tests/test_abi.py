@@ -45,3 +45,15 @@ def test_network_binding_signatures_cover_its_header():
     names = declared_functions(NET_HEADER)
     assert "mireg_net_train_step" in names and "mireg_net_forward" in names
     assert sorted(warmstart.SIGNATURES) == names
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
