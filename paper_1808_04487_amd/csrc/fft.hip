@@ -114,6 +114,18 @@ __global__ __launch_bounds__(kLineThreads) void k_c2r_x3(FieldPtrs src, FieldPtr
 // Strided complex pass: columns q < Q, column base (q / inner) * ostride +
 // q % inner, element p of a column at base + p * pstride.
 // ---------------------------------------------------------------------------
+// Workgroup -> (field, column group) with contiguous runs of column groups
+// per XCD (workgroups are dispatched round-robin over the 8 XCDs): the rows
+// of neighbouring groups share cache lines at their unaligned ends, and
+// neighbours on one XCD share its L2.
+__device__ __forceinline__ void xcd_block(int &bx, int &by) {
+    const int nb = (int)(gridDim.x * gridDim.y), lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int q = nb / 8, r = nb % 8, x = lin % 8, j = lin / 8;
+    const int g = x * q + (x < r ? x : r) + j;
+    bx = g % (int)gridDim.x;
+    by = g / (int)gridDim.x;
+}
+
 template <typename T, int L, int DIR>
 __global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
                                                           long long ostride, long long pstride,
@@ -123,10 +135,12 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long
     using Lay = LayoutCols<W>;
     __shared__ cx<T> lds[Lay::size(L)];
     const int c = threadIdx.x % W, t = threadIdx.x / W;
-    const long long q = (long long)blockIdx.x * W + c;
+    int bx, by;
+    xcd_block(bx, by);
+    const long long q = (long long)bx * W + c;
     const bool ok = q < Q;
     const long long base = ok ? (q / inner) * ostride + (q % inner) : 0;
-    cx<T> *p = reinterpret_cast<cx<T> *>(f.p[blockIdx.y]) + base;
+    cx<T> *p = reinterpret_cast<cx<T> *>(f.p[by]) + base;
     cx<T> reg[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) reg[e] = ok ? p[(long long)(t + TPC * e) * pstride] : make_cx<T>(0, 0);
