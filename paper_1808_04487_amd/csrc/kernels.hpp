@@ -138,42 +138,57 @@ void spectral_resample(const Grid &gs, const Grid &gd, int nf, const T *const *i
                        cx<T> *spec_d, const Twiddles<T> &tws, const Twiddles<T> &twd, hipStream_t s);
 
 // ---- semi-Lagrangian transport (transport.hip) ----
-// Every step kernel takes `box`: the largest stencil box (nodes) of its
-// displacement field, as sl_box_volume measures it; the launch sizes its LDS
-// for that box (at most 64 KB), and tiles with a larger box gather from
-// global memory, so any value is correct and only the speed depends on it.
+// Every step kernel takes `box`: box.cap is the largest stencil box (nodes)
+// of its displacement field, as sl_box_volume measures it; the launch sizes
+// its LDS for that box (at most 64 KB), and tiles with a larger box gather
+// from global memory, so any cap is correct and only the speed depends on
+// it.  box.tiles, when not null, holds every tile's box as sl_box_volume
+// wrote it for this displacement field and the current tile shape (the
+// kernel then reads its box instead of reducing it); it must be exactly
+// that, since a smaller box would leave stencil nodes outside the staged
+// copy.
+struct SlBox {
+    int cap;
+    const int *tiles;
+    SlBox(int c = 0, const int *t = nullptr) : cap(c), tiles(t) {}
+};
+// Words of per-tile box storage for a grid under any tile shape.
+long long sl_box_words(const Grid &g);
 
 // *out (device) = largest stencil box over the transport tiles for the
-// displacement (a D_a) b_a in cell units; slots: 1024 device words of scratch.
+// displacement (a D_a) b_a in cell units; slots: 1024 device words of
+// scratch; tiles (device, sl_box_words(g) ints, or null): every tile's box,
+// 8 ints per tile (lowest base node per axis, highest base node per axis, 2
+// unused).
 template <typename T>
 void sl_box_volume(const Grid &g, int order, const T *D, double a, const double b[3], unsigned *out,
-                   unsigned *slots, hipStream_t s);
+                   unsigned *slots, int *tiles, hipStream_t s);
 // disp = sign dt/2 (v + I[v](x + sign dt v)) / h  (cell units); the
 // predictor displacement is (sign dt v_a) n_a / (2 pi)
 template <typename T>
-void departure(const Grid &g, int order, int sign, double dt, const T *v, T *disp, int box, hipStream_t s);
+void departure(const Grid &g, int order, int sign, double dt, const T *v, T *disp, SlBox box, hipStream_t s);
 // out = I[f](x + disp); f and out in storage types SI, SO (arithmetic in T)
 template <typename T, typename SI, typename SO>
-void interp_field(const Grid &g, int order, const SI *f, const T *disp, SO *out, int box, hipStream_t s);
+void interp_field(const Grid &g, int order, const SI *f, const T *disp, SO *out, SlBox box, hipStream_t s);
 // Adjoint final condition: lam = mR - m(1)   (lam in storage type S)
 template <typename T, typename S>
 void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s);
 // One adjoint step: lam_out = L + dt/2 (S + (L + dt S) d), L = I[lam_in](Y), S = I[lam_in d](Y)
 template <typename T, typename S>
 void adjoint_step(const Grid &g, int order, double dt, const S *lam_in, const T *d, const T *Y,
-                  S *lam_out, int box, hipStream_t s);
+                  S *lam_out, SlBox box, hipStream_t s);
 // Last adjoint step fused with the time integral: lam^0 from lam^1 (in the
 // history), then b = sum_j a_j lam^j grad m^j (lam^0 is not stored)
 template <typename T, typename S>
 void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const S *lam, const T *d,
-                             const T *Y, const T *gradm, T *b, int box, hipStream_t s);
+                             const T *Y, const T *gradm, T *b, SlBox box, hipStream_t s);
 // Incremental state: q0 = -dt/2 grad m^0 . vt
 template <typename T, typename S>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q, hipStream_t s);
 // q_out = sign (I[q_in](X) + coef f^{j+1}), f = -grad m^{j+1} . vt
 template <typename T, typename S>
 void incstate_step(const Grid &g, int order, double coef, double sign, const S *q_in, const T *X,
-                   const T *gradm_next, const T *vt, S *q_out, int box, hipStream_t s);
+                   const T *gradm_next, const T *vt, S *q_out, SlBox box, hipStream_t s);
 
 // ---- vector kernels and FP64 reductions (vec.hip) ----
 // result[k] (device doubles) for k < nres; see the individual descriptions.

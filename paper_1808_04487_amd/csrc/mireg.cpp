@@ -135,7 +135,9 @@ struct mireg_ctx {
 
     bool have_images = false;
     bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
-    int box_X = 0, box_Y = 0;  // largest stencil box (nodes) of X and Y
+    SlBox box_X, box_Y;                    // stencil boxes of X and Y (largest, per tile)
+    int *tbox_X = nullptr, *tbox_Y = nullptr;  // per-tile box storage of X and Y
+    bool tile_boxes = true;  // hand the per-tile boxes to the transport kernels
     // two-level preconditioner: the n/2 context, its freshness, counters
     int pc_kind = MIREG_PC_SPECTRAL;
     double pc_kappa = 0.1;
@@ -312,12 +314,12 @@ void op_tail(mireg_ctx *ctx, double alpha, const T *u, const T *b, T *out) {
 // tiles, read back to the host (synchronises the stream); it sizes the LDS
 // of the transport launches that use D.  0 when staging is switched off.
 template <typename T>
-int measure_box(mireg_ctx *ctx, const T *D, double a, const double b[3]) {
+int measure_box(mireg_ctx *ctx, const T *D, double a, const double b[3], int *tiles = nullptr) {
     if (ctx->g.lds_cap == 0) return 0;
     unsigned *dev = reinterpret_cast<unsigned *>(ctx->dres);
     // the reduction partials (4 kRedBlocks doubles) serve as the 1024 slots
     sl_box_volume<T>(ctx->g, ctx->p.interp_order, D, a, b, dev, reinterpret_cast<unsigned *>(ctx->partials),
-                     ctx->stream);
+                     tiles, ctx->stream);
     if (readback(ctx, 1) != MIREG_OK) return INT_MAX;  // every tile then takes the largest LDS
     unsigned v = 0;
     memcpy(&v, ctx->hres, sizeof v);
@@ -327,6 +329,16 @@ template <typename T>
 int box_of_displacement(mireg_ctx *ctx, const T *D) {
     const double one[3] = {1.0, 1.0, 1.0};
     return measure_box<T>(ctx, D, 1.0, one);
+}
+// Largest box and every tile's box of a displacement field kept for the
+// velocity (X or Y), for the current tile shape.  The per-tile boxes are
+// handed to the kernels only when the measurement ran to completion.
+template <typename T>
+SlBox tile_boxes(mireg_ctx *ctx, const T *D, int *tiles) {
+    const double one[3] = {1.0, 1.0, 1.0};
+    if (!ctx->tile_boxes) tiles = nullptr;
+    const int cap = measure_box<T>(ctx, D, 1.0, one, tiles);
+    return SlBox(cap, (cap > 0 && cap < INT_MAX) ? tiles : nullptr);
 }
 // Characteristic feet of one step (sign -1: X, +1: Y) from velocity v.
 template <typename T>
@@ -342,14 +354,14 @@ template <typename T, typename S = T>
 void ensure_X(mireg_ctx *ctx) {
     if (ctx->have_X) return;
     compute_departure<T>(ctx, -1, ctx->f<T>(ctx->v), ctx->f<T>(ctx->X));
-    ctx->box_X = box_of_displacement<T>(ctx, ctx->f<T>(ctx->X));
+    ctx->box_X = tile_boxes<T>(ctx, ctx->f<T>(ctx->X), ctx->tbox_X);
     ctx->have_X = true;
 }
 template <typename T, typename S = T>
 void ensure_Y(mireg_ctx *ctx) {
     if (ctx->have_Y) return;
     compute_departure<T>(ctx, +1, ctx->f<T>(ctx->v), ctx->f<T>(ctx->Y));
-    ctx->box_Y = box_of_displacement<T>(ctx, ctx->f<T>(ctx->Y));
+    ctx->box_Y = tile_boxes<T>(ctx, ctx->f<T>(ctx->Y), ctx->tbox_Y);
     ctx->have_Y = true;
 }
 // State equation forward in time: m^0 = mT, m^{j+1} = I[m^j](X).  The state
@@ -694,8 +706,8 @@ int two_level_apply(mireg_ctx *ctx, const T *r, T *z, double eps_h) {
 template <typename T, typename S = T>
 void set_tile(mireg_ctx *ctx, int shape) {
     ctx->g.sl_tile = shape;
-    if (ctx->have_X) ctx->box_X = box_of_displacement<T>(ctx, ctx->f<T>(ctx->X));
-    if (ctx->have_Y) ctx->box_Y = box_of_displacement<T>(ctx, ctx->f<T>(ctx->Y));
+    if (ctx->have_X) ctx->box_X = tile_boxes<T>(ctx, ctx->f<T>(ctx->X), ctx->tbox_X);
+    if (ctx->have_Y) ctx->box_Y = tile_boxes<T>(ctx, ctx->f<T>(ctx->Y), ctx->tbox_Y);
     if (ctx->mv_exec) {
         hipGraphExecDestroy(ctx->mv_exec);
         ctx->mv_exec = nullptr;
@@ -1088,7 +1100,8 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
             // intermediate slices in T, as the state history is held
             T *a = ctx->vec<T>(7), *b = a + N;
             const T *X = ctx->f<T>(ctx->X);
-            const int nt = ctx->p.nt, ord = ctx->p.interp_order, box = ctx->box_X;
+            const int nt = ctx->p.nt, ord = ctx->p.interp_order;
+            const SlBox box = ctx->box_X;
             Phase ph(ctx, 1);
             if (nt == 1) {
                 interp_field<T, T, T>(ctx->g, ord, in, X, out, box, ctx->stream);
@@ -1236,6 +1249,10 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
         const char *t = getenv("MIREG_SL_TILE");
         ctx->g.sl_tile = t ? atoi(t) : 1;
         if (ctx->g.sl_tile < 0 || ctx->g.sl_tile > 2) ctx->g.sl_tile = 1;
+        // MIREG_TILE_BOXES=0: each transport launch reduces its tiles' stencil
+        // boxes itself instead of reading the ones measured with X and Y.
+        const char *b = getenv("MIREG_TILE_BOXES");
+        ctx->tile_boxes = !(b && atoi(b) == 0);
     }
     ctx->elem = p->dtype == MIREG_F64 ? 8 : 4;
     const size_t F = (size_t)ctx->g.N * ctx->elem;
@@ -1261,6 +1278,8 @@ int mireg_create(const mireg_params *p, void *stream, mireg_ctx **out) {
     if (!rc) rc = alloc(ctx, (void **)&ctx->partials, 4 * kRedBlocks * sizeof(double));
     if (!rc) rc = alloc(ctx, (void **)&ctx->xpart, ((size_t)ctx->g.n2 * ctx->g.k3 / 8 + 16) * sizeof(double));
     if (!rc) rc = alloc(ctx, (void **)&ctx->dres, 8 * sizeof(double));
+    if (!rc) rc = alloc(ctx, (void **)&ctx->tbox_X, (size_t)sl_box_words(ctx->g) * sizeof(int));
+    if (!rc) rc = alloc(ctx, (void **)&ctx->tbox_Y, (size_t)sl_box_words(ctx->g) * sizeof(int));
     if (!rc && hipHostMalloc((void **)&ctx->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         rc = ctx->fail(MIREG_E_NOMEM, "hipHostMalloc failed");
     if (!rc) rc = DISPATCH(ctx, (make_twiddles<T, S>(ctx)));

@@ -36,6 +36,7 @@ struct PGrid {
     int ltx, lty;    // log2(tx), log2(ty) when both are powers of two, else -1
     int lds_cap;     // largest box (nodes) staged in LDS in this launch; 0 disables staging
     int shape;       // tile shape (SlTile)
+    const int *tbox; // every tile's stencil box (8 ints per tile), or null: reduce it in the kernel
 };
 
 // Tile shapes (x1 x x2 x x3 points) of the semi-Lagrangian kernels.
@@ -93,6 +94,7 @@ static PGrid pgrid(const Grid &g) {
     p.ltx = pow2_tiles ? __builtin_ctz((unsigned)p.tx) : -1;
     p.lty = pow2_tiles ? __builtin_ctz((unsigned)p.ty) : -1;
     p.lds_cap = g.lds_cap;
+    p.tbox = nullptr;
     return p;
 }
 
@@ -186,14 +188,15 @@ __device__ __forceinline__ void contract(const AxisW<T, ORDER> &a1, const AxisW<
     }
 }
 
-// Same contraction over an unwrapped box: node (p, q, r) at
-// base + p s1 + q s2 + r, so the r taps of a row use immediate offsets.  All
-// taps of a plane p are read before any arithmetic, so a wave keeps 16
-// (NF = 1) or 32 (NF = 2) LDS words in flight instead of waiting row by row.
+// Same contraction over an unwrapped box: row (p, q) at base + p s1 + q s2
+// (byte offsets: one add per row, the r taps of a row at immediate
+// offsets).  All taps of a plane p are read before any arithmetic, so a wave
+// keeps 16 (NF = 1) or 32 (NF = 2) LDS words in flight instead of waiting row
+// by row.
 template <typename T, int ORDER, int NF, class Get>
 __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const AxisW<T, ORDER> &a2,
-                                             const AxisW<T, ORDER> &a3, int base, int s1, int s2,
-                                             const Get &get, T *acc) {
+                                             const AxisW<T, ORDER> &a3, unsigned base, unsigned s1,
+                                             unsigned s2, const Get &get, T *acc) {
     constexpr int NP = AxisW<T, ORDER>::NP;
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = 0;
@@ -202,7 +205,7 @@ __device__ __forceinline__ void contract_box(const AxisW<T, ORDER> &a1, const Ax
         T v[NP][NP][NF];
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int row = base + p * s1 + q * s2;
+            const unsigned row = base + (unsigned)p * s1 + (unsigned)q * s2;
 #pragma unroll
             for (int r = 0; r < NP; ++r) get(row, r, v[q][r]);
         }
@@ -358,25 +361,30 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
     extern __shared__ __align__(16) unsigned char sl_smem[];
     T *lds = reinterpret_cast<T *>(sl_smem);
     __shared__ int box[6];
-    const TP tp(g, xcd_tile(blockIdx.x, g.tx * g.ty * g.tz));
-    if (threadIdx.x == 0) {
+    const int tile = xcd_tile(blockIdx.x, g.tx * g.ty * g.tz);
+    const TP tp(g, tile);
+    // box of the base nodes (lowest, highest per axis) in unwrapped grid
+    // coordinates (block-uniform): the stored one, or reduced over the
+    // block.  The stored box is one vector load per wave (lane l reads word
+    // l & 7), issued with the displacement loads and waited for with them.
+    const bool stored = g.tbox != nullptr;  // uniform
+    int tbw = 0;
+    if (stored) {
+        tbw = g.tbox[8 * tile + ((int)threadIdx.x & 7)];
+    } else if (threadIdx.x == 0) {
         box[0] = box[1] = box[2] = INT_MAX;
         box[3] = box[4] = box[5] = INT_MIN;
     }
-    // 1. displacements -> base node and fractional position per axis; the
-    //    operands of the point update are loaded now so their latency hides
-    //    under the staging
+    // 1. displacements -> base node and fractional position per axis
     T t1[kPPT], t2[kPPT], t3[kPPT];
     int b1[kPPT], b2[kPPT], b3[kPPT];
     typename Op::Pre pre[kPPT];
-    int mn1 = INT_MAX, mn2 = INT_MAX, mn3 = INT_MAX, mx1 = INT_MIN, mx2 = INT_MIN, mx3 = INT_MIN;
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
         if (tp.ok(g, p)) {
             const unsigned idx = tp.idx(g, p);
             T d[3];
             op.disp(idx, d);
-            pre[p] = op.pre(idx);
             const T f1 = floor(d[0]), f2 = floor(d[1]), f3 = floor(d[2]);
             t1[p] = frac_part(d[0], f1);
             t2[p] = frac_part(d[1], f2);
@@ -384,20 +392,44 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             b1[p] = tp.i1(p) + (int)f1;
             b2[p] = tp.i2 + (int)f2;
             b3[p] = tp.i3 + (int)f3;
-            mn1 = min(mn1, b1[p]);
-            mx1 = max(mx1, b1[p]);
-            mn2 = min(mn2, b2[p]);
-            mx2 = max(mx2, b2[p]);
-            mn3 = min(mn3, b3[p]);
-            mx3 = max(mx3, b3[p]);
         }
     }
-    __syncthreads();  // box initialised
-    if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
-    // box of every stencil node, in unwrapped grid coordinates (block-uniform)
-    const int c0 = __builtin_amdgcn_readfirstlane(box[0]), c1 = __builtin_amdgcn_readfirstlane(box[1]),
-              c2 = __builtin_amdgcn_readfirstlane(box[2]), c3 = __builtin_amdgcn_readfirstlane(box[3]),
-              c4 = __builtin_amdgcn_readfirstlane(box[4]), c5 = __builtin_amdgcn_readfirstlane(box[5]);
+    int c0, c1, c2, c3, c4, c5;
+    if (stored) {
+        c0 = __builtin_amdgcn_readlane(tbw, 0);
+        c1 = __builtin_amdgcn_readlane(tbw, 1);
+        c2 = __builtin_amdgcn_readlane(tbw, 2);
+        c3 = __builtin_amdgcn_readlane(tbw, 3);
+        c4 = __builtin_amdgcn_readlane(tbw, 4);
+        c5 = __builtin_amdgcn_readlane(tbw, 5);
+        if (c0 == INT_MAX) return;  // no point of the grid in this tile
+    } else {
+        int mn1 = INT_MAX, mn2 = INT_MAX, mn3 = INT_MAX, mx1 = INT_MIN, mx2 = INT_MIN, mx3 = INT_MIN;
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) {
+            if (tp.ok(g, p)) {
+                mn1 = min(mn1, b1[p]);
+                mx1 = max(mx1, b1[p]);
+                mn2 = min(mn2, b2[p]);
+                mx2 = max(mx2, b2[p]);
+                mn3 = min(mn3, b3[p]);
+                mx3 = max(mx3, b3[p]);
+            }
+        }
+        __syncthreads();  // box initialised
+        if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
+        c0 = __builtin_amdgcn_readfirstlane(box[0]);
+        c1 = __builtin_amdgcn_readfirstlane(box[1]);
+        c2 = __builtin_amdgcn_readfirstlane(box[2]);
+        c3 = __builtin_amdgcn_readfirstlane(box[3]);
+        c4 = __builtin_amdgcn_readfirstlane(box[4]);
+        c5 = __builtin_amdgcn_readfirstlane(box[5]);
+    }
+    // the operands of the point update, loaded now so that their latency
+    // hides under the staging
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p)
+        if (tp.ok(g, p)) pre[p] = op.pre(tp.idx(g, p));
     const int lo1 = c0 + FIRST, lo2 = c1 + FIRST, lo3 = c2 + FIRST;
     const long long e1 = (long long)c3 - c0 + NP, e2 = (long long)c4 - c1 + NP, e3 = (long long)c5 - c2 + NP;
     const long long vol = e1 * e2 * e3;
@@ -524,13 +556,21 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
             const A a1 = axis_weights<T, ORDER>(b1[p], t1[p]);
             const A a2 = axis_weights<T, ORDER>(b2[p], t2[p]);
             const A a3 = axis_weights<T, ORDER>(b3[p], t3[p]);
-            const int base = ((b1[p] + FIRST - lo1) * E2 + (b2[p] + FIRST - lo2)) * E3 + (b3[p] + FIRST - lo3);
+            // byte offsets into the box: U bytes per node of the interleaved
+            // layout (NF <= 2), one quantity's array at a time for NF = 3
+            constexpr unsigned U = NF <= 2 ? NF * sizeof(T) : sizeof(T);
+            const unsigned node =
+                __umul24(__umul24((unsigned)(b1[p] + FIRST - lo1), (unsigned)E2) + (unsigned)(b2[p] + FIRST - lo2),
+                         (unsigned)E3) +
+                (unsigned)(b3[p] + FIRST - lo3);
             T acc[NF];
             contract_box<T, ORDER, NF>(
-                a1, a2, a3, base, E23, E3,
-                [&](int row, int r, T *v) {
+                a1, a2, a3, node * U, (unsigned)E23 * U, (unsigned)E3 * U,
+                [&](unsigned row, int r, T *v) {
+                    const char *at = reinterpret_cast<const char *>(lds) + row + r * U;
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) v[f] = lds[box_at<NF>(row + r, f, stride)];
+                    for (int f = 0; f < NF; ++f)
+                        v[f] = *reinterpret_cast<const T *>(at + box_at<NF>(0, f, stride) * sizeof(T));
                 },
                 acc);
             op.finish(tp.idx(g, p), pre[p], acc);
@@ -566,15 +606,17 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
 // Largest stencil box (nodes) over the tiles of k_sl for the displacement
 // d_a = (a_a D_a) b_a, the same expression the step operators evaluate:
 // one block per tile, atomic maximum into one of kBoxSlots slots (so that
-// the blocks do not all serialise on one address), then k_max_slots.
+// the blocks do not all serialise on one address), then k_max_slots.  With
+// `tiles`, also each tile's box of base nodes, as k_sl would reduce it.
 constexpr int kBoxSlots = 1024;
 template <typename T, int ORDER, int SHAPE>
 __global__ __launch_bounds__(kSlThreads) void k_box(PGrid g, const T *__restrict__ D, T a, T b1, T b2, T b3,
-                                                    unsigned *__restrict__ slots) {
+                                                    unsigned *__restrict__ slots, int *__restrict__ tiles) {
     using TP = TilePoints<SHAPE>;
     constexpr int NP = AxisW<T, ORDER>::NP;
     __shared__ int box[6];
-    const TP tp(g, xcd_tile(blockIdx.x, g.tx * g.ty * g.tz));
+    const int tile = xcd_tile(blockIdx.x, g.tx * g.ty * g.tz);
+    const TP tp(g, tile);
     if (threadIdx.x == 0) {
         box[0] = box[1] = box[2] = INT_MAX;
         box[3] = box[4] = box[5] = INT_MIN;
@@ -597,7 +639,9 @@ __global__ __launch_bounds__(kSlThreads) void k_box(PGrid g, const T *__restrict
         }
     }
     __syncthreads();
-    if (!block_box(box, mn1, mn2, mn3, mx1, mx2, mx3)) return;
+    const bool any = block_box(box, mn1, mn2, mn3, mx1, mx2, mx3);
+    if (tiles && threadIdx.x < 8) tiles[8 * tile + (int)threadIdx.x] = threadIdx.x < 6 ? box[threadIdx.x] : 0;
+    if (!any) return;
     if (threadIdx.x == 0) {
         const long long vol = ((long long)box[3] - box[0] + NP) * ((long long)box[4] - box[1] + NP) *
                               ((long long)box[5] - box[2] + NP);
@@ -825,8 +869,9 @@ static void launch_sl_shape(const PGrid &g, int order, const Op &op, hipStream_t
 }
 
 template <typename T, int NF, class Op>
-static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) {
-    g.lds_cap = launch_cap<T, NF>(g, box);
+static void launch_sl(PGrid g, int order, SlBox box, const Op &op, hipStream_t s) {
+    g.lds_cap = launch_cap<T, NF>(g, box.cap);
+    g.tbox = box.tiles;
     switch (g.shape) {
         case TILE_8x8x16: launch_sl_shape<T, NF, TILE_8x8x16>(g, order, op, s); break;
         case TILE_8x16x16: launch_sl_shape<T, NF, TILE_8x16x16>(g, order, op, s); break;
@@ -834,16 +879,27 @@ static void launch_sl(PGrid g, int order, int box, const Op &op, hipStream_t s) 
     }
 }
 
+long long sl_box_words(const Grid &g) {
+    const int dims[3][3] = {{4, 8, 32}, {8, 8, 16}, {8, 16, 16}};
+    long long most = 0;
+    for (const auto &d : dims) {
+        const long long t = (long long)((g.n1 + d[0] - 1) / d[0]) * ((g.n2 + d[1] - 1) / d[1]) *
+                            ((g.n3 + d[2] - 1) / d[2]);
+        most = t > most ? t : most;
+    }
+    return 8 * most;
+}
+
 template <typename T>
 void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double b[3], unsigned *out,
-                   unsigned *slots, hipStream_t s) {
+                   unsigned *slots, int *tiles, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_VECTOR, 3.0 * sizeof(T) * g.N);
     const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
     hipLaunchKernelGGL(k_zero_slots, dim3(kBoxSlots / 256), dim3(256), 0, s, slots);
 #define MIREG_BOX(ORD, SH)                                                                                     \
     hipLaunchKernelGGL((k_box<T, ORD, SH>), dim3(nb), dim3(kSlThreads), 0, s, g, D, (T)a, (T)b[0], (T)b[1], \
-                       (T)b[2], slots)
+                       (T)b[2], slots, tiles)
     if (order == 3) {
         switch (g.shape) {
             case TILE_8x8x16: MIREG_BOX(3, TILE_8x8x16); break;
@@ -862,7 +918,7 @@ void sl_box_volume(const Grid &gg, int order, const T *D, double a, const double
 }
 
 template <typename T>
-void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *disp, int box, hipStream_t s) {
+void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *disp, SlBox box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_DEPARTURE, 6.0 * g.N * sizeof(T));
     DepartureOp<T> op{v, disp, (unsigned)g.N, (T)(sign * dt), (T)departure_ih(gg, 0), (T)departure_ih(gg, 1),
@@ -871,7 +927,7 @@ void departure(const Grid &gg, int order, int sign, double dt, const T *v, T *di
 }
 
 template <typename T, typename SI, typename SO>
-void interp_field(const Grid &gg, int order, const SI *f, const T *disp, SO *out, int box, hipStream_t s) {
+void interp_field(const Grid &gg, int order, const SI *f, const T *disp, SO *out, SlBox box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_INTERP, (3.0 * sizeof(T) + sizeof(SI) + sizeof(SO)) * g.N);
     InterpOp<T, SI, SO> op{f, disp, out, (unsigned)g.N};
@@ -886,7 +942,7 @@ void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s)
 
 template <typename T, typename S>
 void adjoint_step(const Grid &gg, int order, double dt, const S *lam_in, const T *d, const T *Y, S *lam_out,
-                  int box, hipStream_t s) {
+                  SlBox box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_ADJ_STEP, (4.0 * sizeof(T) + 2.0 * sizeof(S)) * g.N);
     AdjointOp<T, S> op{lam_in, d, Y, lam_out, (unsigned)g.N, (T)dt};
@@ -895,7 +951,7 @@ void adjoint_step(const Grid &gg, int order, double dt, const S *lam_in, const T
 
 template <typename T, typename S>
 void adjoint_step_accumulate(const Grid &gg, int order, double dt, int nt, const S *lam, const T *d,
-                             const T *Y, const T *gradm, T *b, int box, hipStream_t s) {
+                             const T *Y, const T *gradm, T *b, SlBox box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_ADJ_ACC, ((4.0 + 3.0 * (nt + 1) + 3.0) * sizeof(T) + (double)nt * sizeof(S)) * g.N);
     const unsigned N = (unsigned)g.N;
@@ -913,7 +969,7 @@ void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q,
 
 template <typename T, typename S>
 void incstate_step(const Grid &gg, int order, double coef, double sign, const S *q_in, const T *X,
-                   const T *gradm_next, const T *vt, S *q_out, int box, hipStream_t s) {
+                   const T *gradm_next, const T *vt, S *q_out, SlBox box, hipStream_t s) {
     const PGrid g = pgrid(gg);
     HookScope hs(K_INC_STEP, 9.0 * sizeof(T) * g.N + 2.0 * sizeof(S) * g.N);
     IncStateOp<T, S> op{q_in, X, gradm_next, vt, q_out, (unsigned)g.N, (T)coef, (T)sign};
@@ -921,19 +977,19 @@ void incstate_step(const Grid &gg, int order, double coef, double sign, const S 
 }
 
 #define MIREG_INST_T(T)                                                                                   \
-    template void departure<T>(const Grid &, int, int, double, const T *, T *, int, hipStream_t);        \
-    template void interp_field<T, T, T>(const Grid &, int, const T *, const T *, T *, int, hipStream_t); \
+    template void departure<T>(const Grid &, int, int, double, const T *, T *, SlBox, hipStream_t);      \
+    template void interp_field<T, T, T>(const Grid &, int, const T *, const T *, T *, SlBox, hipStream_t); \
     template void sl_box_volume<T>(const Grid &, int, const T *, double, const double *, unsigned *,     \
-                                   unsigned *, hipStream_t);
+                                   unsigned *, int *, hipStream_t);
 #define MIREG_INST(T, S)                                                                                  \
     template void adjoint_init<T, S>(const Grid &, const T *, const T *, S *, hipStream_t);              \
     template void adjoint_step<T, S>(const Grid &, int, double, const S *, const T *, const T *, S *,    \
-                                     int, hipStream_t);                                                   \
+                                     SlBox, hipStream_t);                                                 \
     template void adjoint_step_accumulate<T, S>(const Grid &, int, double, int, const S *, const T *,    \
-                                                const T *, const T *, T *, int, hipStream_t);            \
+                                                const T *, const T *, T *, SlBox, hipStream_t);          \
     template void incstate_init<T, S>(const Grid &, double, const T *, const T *, S *, hipStream_t);     \
     template void incstate_step<T, S>(const Grid &, int, double, double, const S *, const T *, const T *, \
-                                      const T *, S *, int, hipStream_t);
+                                      const T *, S *, SlBox, hipStream_t);
 MIREG_INST_T(float)
 MIREG_INST_T(double)
 MIREG_INST(float, float)

@@ -157,6 +157,38 @@ def test_tile_shapes_agree_bitwise(monkeypatch):
         assert torch.equal(h, outs[0][1])
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("order", [3, 1])
+@pytest.mark.parametrize("shape", ["0", "1"])
+def test_stored_tile_boxes_agree_bitwise(dtype, order, shape, monkeypatch):
+    """The stencil box of every transport tile, measured once per velocity
+    and read by the transport kernels, stages the same nodes as the box each
+    launch reduces itself (MIREG_TILE_BOXES=0): state transport, matvec and
+    gradient are bitwise identical, with displacements of several cells, on
+    axes of 48 and 80 points (wrapped by remainder) and, under the 4x8x32
+    tile shape, tiles ragged along x3."""
+    need_gpu()
+    n = (16, 48, 80)
+    g = core.Grid(n)
+    v_t, _ = as_input(smooth_vector(g, 31, amp=2.0, sigma=2.0), dtype)
+    f_t, _ = as_input(smooth_scalar(g, 32), dtype)
+    vt_t, _ = as_input(smooth_vector(g, 33), dtype)
+    monkeypatch.setenv("MIREG_SL_TILE", shape)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("MIREG_TILE_BOXES", flag)
+        print("tile boxes", flag, dtype, order, shape, flush=True)
+        ctx = mireg.Context(n, order=order, dtype=dtype, div=mireg.DIV_NEAR, beta_w=1.0)
+        ctx.set_images(f_t, f_t.flip(1).contiguous())
+        ctx.set_velocity(v_t)
+        grad, _ = ctx.gradient()
+        outs.append((ctx.op("transport_state", f_t), ctx.hessian_matvec(vt_t), grad))
+        ctx.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.isfinite(a).all()
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("nt", [1, 2, 3, 5])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, "f32h16"])
 def test_transport_state_time_steps(nt, dtype):
