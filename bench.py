@@ -394,8 +394,8 @@ def main():
             from paper_1808_04487_amd import build as hb
 
             t = json.load(open(tpath))
-            if t.get("kernel") == dom and t.get("source_sha") == hb.source_sha():
-                traffic = t.get("bytes_per_launch")
+            if t.get("source_sha") == hb.source_sha():
+                traffic = t.get("bytes_per_launch", {}).get(dom)
         except Exception:
             traffic = None
 
