@@ -10,27 +10,40 @@ outer loop with Armijo line search (Algorithm "Inexact Newton-Krylov method
   the text states, rather than the absolute test of the listing);
 * PCG caps at max_pcg iterations and stops on non-positive curvature
   <s, H s> <= 0, returning the current iterate (M^{-1} rhs if it is the first);
+  the matvec that found the curvature is counted, and the stop is reported
+  (status NEG_CURV of the solve, a count in the GN report);
 * GN stops when ||g_k|| <= eps_g ||g_0|| (the tables report ||g||/||g_0||
   just below eps_g, so the test is on the norm, not its square), or
   ||g_k|| <= grad_atol, or after max_gn iterations;
 * Armijo: J(v + a vt) <= J(v) + c1 a <g, vt>, a = 1, 1/2, ..., at most max_ls
   trials, c1 = 1e-4; a failed search keeps v and ends the solve;
 * norms and inner products are the trapezoidal L2 ones of the grid;
-* PDE-solve counter: 1 per state solve, 1 per adjoint solve, 2 per matvec.
+* PDE-solve counter in the convention of the paper's tables (Sec. 4.7: three
+  GN iterations with three matvecs take 15 PDE solves; Table S3:
+  #PDE = 2 #matvecs + 2 #iter + 3): 3 for the objective and gradient at the
+  initial velocity (a state solve for each and the adjoint solve), 2 per
+  matvec, 1 per line-search trial (a state solve) and 1 per accepted step
+  (the adjoint solve of the new gradient, whose state the accepted trial
+  computed).
 """
 import math
 import time
 
 import numpy as np
 
-CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL = 1, 2, 3, 4
+CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL, NEG_CURV = 1, 2, 3, 4, 5
 
 
-def pcg(apply_H, apply_Minv, rhs, rtol, maxit, inner):
-    """Solve H x = rhs approximately from x_0 = 0.  Returns (x, iters, relres)."""
+def pcg(apply_H, apply_Minv, rhs, rtol, maxit, inner, info=None):
+    """Solve H x = rhs approximately from x_0 = 0.  Returns (x, iters, relres);
+    ``info`` (a dict, optional) receives "matvecs" (applications of H, the
+    iterations plus one when the loop stops on non-positive curvature) and
+    "status" (CONVERGED_REL, MAXIT or NEG_CURV)."""
     x = np.zeros_like(rhs)
     r = rhs.copy()
     r0 = math.sqrt(inner(r, r))
+    if info is not None:
+        info["matvecs"], info["status"] = 0, CONVERGED_REL
     if r0 == 0.0:
         return x, 0, 0.0
     z = apply_Minv(r)
@@ -38,12 +51,16 @@ def pcg(apply_H, apply_Minv, rhs, rtol, maxit, inner):
     rz = inner(r, z)
     it = 0
     rnorm = r0
+    status = MAXIT
     while it < maxit:
         Hs = apply_H(s)
+        if info is not None:
+            info["matvecs"] += 1
         sHs = inner(s, Hs)
         if sHs <= 0.0:
             if it == 0:
                 x = z.copy()
+            status = NEG_CURV
             break
         kappa = rz / sHs
         x = x + kappa * s
@@ -51,12 +68,15 @@ def pcg(apply_H, apply_Minv, rhs, rtol, maxit, inner):
         it += 1
         rnorm = math.sqrt(inner(r, r))
         if rnorm <= rtol * r0:
+            status = CONVERGED_REL
             break
         z = apply_Minv(r)
         rz_new = inner(r, z)
         mu = rz_new / rz
         rz = rz_new
         s = z + mu * s
+    if info is not None:
+        info["status"] = status
     return x, it, rnorm / r0
 
 
@@ -73,12 +93,13 @@ class Report:
         self.gnorm0 = self.gnorm = self.gnorm_rel = 0.0
         self.seconds = 0.0
         self.coarse_matvecs = 0
+        self.neg_curv = 0
         self.history = []
 
     def as_dict(self):
         return {k: getattr(self, k) for k in (
             "status", "gn_iters", "matvecs", "pde_solves", "pcg_iters", "ls_trials", "J0", "J",
-            "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel", "seconds", "coarse_matvecs")}
+            "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel", "seconds", "coarse_matvecs", "neg_curv")}
 
 
 def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
@@ -95,9 +116,8 @@ def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
     v = np.array(v0, dtype=np.float64, copy=True)
     reg.set_velocity(v)
     J = reg.objective()[0]
-    rep.pde_solves += 1  # state
     grad = reg.gradient()
-    rep.pde_solves += 1  # adjoint
+    rep.pde_solves += 3  # the paper counts a state solve for J and for g, and the adjoint
     g0 = math.sqrt(inner(grad, grad))
     rep.J0, rep.gnorm0 = J, g0
     k = 0
@@ -115,10 +135,12 @@ def gn_solve(reg, v0, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
             break
         eps_h = min(0.5, math.sqrt(gnorm / g0))
         minv = reg.precond if precond is None else (lambda r, e=eps_h: precond.apply(r, e))
-        vt, its, _ = pcg(reg.hessian_matvec, minv, -grad, eps_h, max_pcg, inner)
-        rep.matvecs += its
+        info = {}
+        vt, its, _ = pcg(reg.hessian_matvec, minv, -grad, eps_h, max_pcg, inner, info)
+        rep.matvecs += info["matvecs"]
         rep.pcg_iters += its
-        rep.pde_solves += 2 * its
+        rep.pde_solves += 2 * info["matvecs"]
+        rep.neg_curv += info["status"] == NEG_CURV
         slope = inner(grad, vt)
         alpha = 1.0
         accepted = False

@@ -3,6 +3,8 @@ and GN loop (Sec. 2.2, 2.3.2, Algorithms "outer iteration" and "inner
 iteration"): closed forms at v = 0 and at the inverse-crime point,
 symmetry and positivity, brute-force assembly on tiny grids, finite
 differences under refinement, and solver behaviour."""
+import os
+
 import numpy as np
 import pytest
 
@@ -230,8 +232,118 @@ def test_gn_solve_synthetic_problem():
     assert all(Js[i + 1] <= Js[i] for i in range(len(Js) - 1))
     assert rep.gnorm_rel <= 1e-2
     assert rep.mismatch_rel < 0.2
-    # counters: 2 (first state+adjoint) + 2 per matvec + 1 per trial + 1 adjoint per step
-    assert rep.pde_solves == 2 + 2 * rep.matvecs + rep.ls_trials + rep.gn_iters
+    # every step here is accepted at the first trial, so the paper's identity holds exactly
+    assert rep.ls_trials == rep.gn_iters
+    assert rep.pde_solves == 2 * rep.matvecs + 2 * rep.gn_iters + 3
+    assert rep.neg_curv == 0
+
+
+def _published_counts():
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "pde_counts.txt")
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                src, pair, it, mv, pde = line.split()
+                rows.append((src, pair, int(it), int(mv), int(pde)))
+    return rows
+
+
+def test_published_pde_counts_follow_the_counter_convention():
+    """The paper's tables obey #PDE = 2 #matvecs + 2 #iter + 3 (one line-search
+    trial per iteration); the one exception, Table S3 na14, has six PDE
+    solves more, i.e. extra line-search trials (each one state solve)."""
+    rows = _published_counts()
+    assert len(rows) == 31
+    extra = {(s, p): pde - (2 * mv + 2 * it + 3) for s, p, it, mv, pde in rows}
+    assert extra.pop(("S3", "na14")) == 6
+    assert set(extra.values()) == {0}
+
+
+def test_gn_counters_reproduce_the_paper_identity_on_a_sec47_like_run():
+    """Sec. 4.7: three GN iterations, three matvecs, 15 PDE solves.  A solve
+    whose PCG takes one iteration per Newton step (constant-curvature data:
+    PCG converges in one step when H = M) and one trial per step must count
+    the same: 3 iterations and 3 matvecs give 15."""
+    g = core.Grid((8, 8, 8))
+
+    class Quadratic:
+        """J(v) = 1/2 <v - c, M (v - c)> with M the preconditioner's inverse:
+        g = M (v - c) and H = M, so PCG with M^{-1} takes one iteration."""
+        def __init__(self, c, scale):
+            self.g, self.c, self.scale = g, c, scale
+            self.v = np.zeros_like(c)
+
+        def set_velocity(self, v):
+            self.v = np.array(v, copy=True)
+
+        def _M(self, u):
+            return self.scale * u
+
+        def objective(self):
+            e = self.v - self.c
+            return (0.5 * g.inner(e, self._M(e)),)
+
+        def gradient(self):
+            return self._M(self.v - self.c)
+
+        def hessian_matvec(self, s):
+            # damped: the Newton step is half the error, so GN needs several steps
+            return 2.0 * self._M(s)
+
+        def precond(self, r):
+            return r / (2.0 * self.scale)
+
+        def mismatch_rel(self):
+            return 0.0
+
+    c = smooth_field(g, 3)
+    R = Quadratic(c, 3.0)
+    v, rep = solver.gn_solve(R, np.zeros_like(c), grad_rtol=0.2)
+    # |g_k| halves per step: 1 -> 1/2 -> 1/4 -> 1/8 <= 0.2 after three steps
+    assert rep.status == solver.CONVERGED_REL
+    assert (rep.gn_iters, rep.matvecs, rep.ls_trials) == (3, 3, 3)
+    assert rep.pde_solves == 15
+
+
+def test_pcg_reports_non_positive_curvature():
+    """An indefinite operator: PCG stops when <s, H s> <= 0, counts that
+    matvec, returns M^{-1} rhs if it is the first and reports NEG_CURV."""
+    rng = np.random.default_rng(5)
+    n = 6
+    rhs = rng.standard_normal(n)
+    inner = lambda a, b: float(a @ b)
+    # first direction M^{-1} rhs = rhs (M = I) has curvature -|rhs|^2
+    info = {}
+    x, it, _ = solver.pcg(lambda s: -s, lambda r: r, rhs, 1e-8, 10, inner, info)
+    assert (it, info["matvecs"], info["status"]) == (0, 1, solver.NEG_CURV)
+    assert np.array_equal(x, rhs)
+    # positive on the first direction, negative on the second: one step taken
+    d = np.array([4.0, 3.0, -1.0, -2.0, -0.5, 1.0])
+    Hd = np.diag(d)
+    rhs = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])  # <rhs, H rhs> = 6 > 0
+    info = {}
+    x, it, _ = solver.pcg(lambda s: Hd @ s, lambda r: r, rhs, 1e-12, 10, inner, info)
+    # the second direction s = r_1 + mu rhs has <s, H s> < 0 (worked by hand)
+    assert (it, info["matvecs"], info["status"]) == (1, 2, solver.NEG_CURV)
+    assert np.allclose(x, 0.5 * rhs, rtol=0, atol=1e-15)  # kappa = <r, r> / <rhs, H rhs> = 3 / 6
+    # an SPD operator converges with matvecs == iterations
+    info = {}
+    x, it, rel = solver.pcg(lambda s: np.abs(d) * s, lambda r: r, rhs, 1e-12, 10, inner, info)
+    assert info["status"] == solver.CONVERGED_REL and info["matvecs"] == it and rel <= 1e-12
+
+
+def test_relative_mismatch_is_one_at_zero_velocity():
+    """At v = 0 the departure points are the grid points (zero displacement,
+    weights exactly 0/1), so m(1) = mT bit for bit and the relative mismatch
+    ||m(1) - mR||^2 / ||mT - mR||^2 is exactly 1; at the inverse crime it
+    is exactly 0."""
+    for n, order in (((16, 12, 8), 3), ((8, 8, 16), 1)):
+        g, R, vs = problem(n, order=order)
+        R.set_velocity(np.zeros((3,) + g.n))
+        assert R.mismatch_rel() == 1.0
+        R.set_velocity(vs)
+        assert R.mismatch_rel() == 0.0
 
 
 def test_gn_line_search_failure_keeps_velocity():
