@@ -103,10 +103,11 @@ def make_inputs(ctx, n, torch):
 
 
 def cpu_baseline(args):
-    """FP64 oracle on the host cores: per-velocity setup, then Hessian matvecs
-    at --cpu-n^3 on the same recipe (one at the workload's own size, two on
-    smaller grids, whose rate is scaled by the point count: the matvec is
-    dominated by O(N) transport work)."""
+    """FP64 oracle on the host cores: per-velocity setup (departure points,
+    state history, state gradients, adjoint), then one Hessian matvec on the
+    workload itself at the default --cpu-n = 256; a smaller --cpu-n times two
+    matvecs there and scales their rate by the point count (the matvec is
+    O(N) transport work), and the unit says so."""
     import numpy as np
 
     from oracle import core, prep

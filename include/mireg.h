@@ -93,14 +93,22 @@ enum {
     MIREG_CONVERGED_REL = 1,
     MIREG_CONVERGED_ABS = 2,
     MIREG_MAXIT = 3,
-    MIREG_LS_FAIL = 4
+    MIREG_LS_FAIL = 4,
+    MIREG_NEG_CURV = 5  /* PCG met <s, H s> <= 0 (Algorithm "inner iteration" has no
+                           safeguard; the solve stops there and keeps its iterate) */
 };
 
 typedef struct {
-    int status;         /* MIREG_CONVERGED_REL / _ABS / MIREG_MAXIT / MIREG_LS_FAIL */
+    int status;         /* MIREG_CONVERGED_REL / _ABS / MIREG_MAXIT / MIREG_LS_FAIL: why the
+                           outer loop ended (a PCG stop on curvature is counted in neg_curv;
+                           GN goes on with the direction that PCG returned) */
     int gn_iters;       /* accepted GN steps */
-    int matvecs;        /* Hessian matvecs (= PCG iterations) */
-    int pde_solves;     /* state/adjoint solves: 1 each, 2 per matvec */
+    int matvecs;        /* Hessian matvecs: the PCG iterations, plus one for each PCG
+                           solve that stopped on non-positive curvature */
+    int pde_solves;     /* PDE solves as the paper's tables count them (Sec. 4.7, Table
+                           S3: #PDE = 2 #matvecs + 2 #iter + 3 with one trial per step):
+                           3 for J and g at the initial velocity, 2 per matvec, 1 per
+                           line-search trial, 1 per accepted step (the new adjoint) */
     int pcg_iters;
     int ls_trials;      /* objective evaluations in the line search */
     double J0, J;       /* objective at the initial and final velocity */
@@ -108,6 +116,7 @@ typedef struct {
     double gnorm0, gnorm, gnorm_rel;
     double seconds;     /* wall time of the solve */
     int coarse_matvecs; /* coarse-grid Hessian matvecs of the two-level preconditioner */
+    int neg_curv;       /* Newton steps whose PCG stopped on <s, H s> <= 0 */
 } mireg_report;
 
 typedef struct mireg_ctx mireg_ctx;
@@ -193,10 +202,14 @@ int mireg_set_graphs(mireg_ctx *ctx, int on);
 int mireg_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape);
 
 /* PCG (Algorithm "inner iteration") for H x = rhs at the current v, x0 = 0;
- * stops when ||r|| <= rtol ||rhs||, after maxit iterations, or on
- * non-positive curvature.  *iters and *relres (host, may be NULL). */
+ * stops when ||r|| <= rtol ||rhs|| (*status = MIREG_CONVERGED_REL, also for
+ * rhs = 0), after maxit iterations (MIREG_MAXIT), or on non-positive
+ * curvature <s, H s> <= 0 (MIREG_NEG_CURV: x is the iterate so far, or
+ * M^{-1} rhs if the first direction had it).  *iters counts the completed
+ * iterations (the matvec that found the curvature is not one); iters,
+ * relres and status are host pointers and may be NULL. */
 int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit,
-                    int *iters, double *relres);
+                    int *iters, double *relres, int *status);
 
 /* Inexact GN-Krylov solve (Algorithm "outer iteration", Sec. 2.3.2) with
  * forcing eps_H = min(0.5, sqrt(||g_k||/||g_0||)) and Armijo line search,
@@ -223,7 +236,12 @@ enum {
     MIREG_OP_INTERP = 12,        /* scalar f -> scalar I[f](x + d): `in` holds f
                                     followed by the displacement field d */
     MIREG_OP_RESCALE01 = 13,     /* scalar -> scalar, (u - min u)/(max u - min u) */
-    MIREG_OP_SCALE_MAXNORM = 14  /* vector -> vector scaled so max_x |v(x)|_2 = arg */
+    MIREG_OP_SCALE_MAXNORM = 14, /* vector -> vector scaled so max_x |v(x)|_2 = arg */
+    MIREG_OP_TRANSPORT_ADJOINT = 15 /* scalar lam(1) -> scalar lam(0) at the current v: the
+                                    adjoint equation (eq. "adj", Sec. 2.2) solved backward over
+                                    nt semi-Lagrangian steps along Y with its source lam div v
+                                    (explicit Heun); F32_H16 holds the steps in FP16 as the
+                                    gradient does.  `in` and `out` may alias. */
 };
 int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg);
 

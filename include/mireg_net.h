@@ -2,7 +2,7 @@
  * mireg_net -- learned warm start for the Gauss-Newton-Krylov registration
  * solver of mireg.h, on one MI355X (gfx950).
  *
- * The solver starts each solve from a velocity (Sec. 3.2 of the paper uses
+ * The solver starts each solve from a velocity (Sec. 3.6 of the paper uses
  * v = 0, or the previous solution while it continues in beta_v).  This
  * library predicts that starting velocity from the image pair with a small
  * convolutional network and trains the network on pairs the solver itself

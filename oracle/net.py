@@ -3,7 +3,7 @@ pass, hand-written backward pass and loss of the velocity-predicting network.
 
 The paper has no learning component; its solver starts each Gauss-Newton
 solve from a given velocity (v = 0, or the previous solution during the
-beta_v continuation, Sec. 3.2).  The network maps an image pair (mT, mR) on
+beta_v continuation, Sec. 3.6).  The network maps an image pair (mT, mR) on
 the periodic n^3 grid to such an initial velocity:
 
   x  = (mT, mR)                                     2 channels, n^3

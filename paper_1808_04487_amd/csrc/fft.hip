@@ -13,6 +13,8 @@
 //   4. x2 inverse, 5. x3 complex-to-real.
 // Odd symbols (i k_a: gradient, divergence and the wavenumbers inside K)
 // vanish at the Nyquist index; even symbols (|k|^2, |k|^4, Gaussian) keep it.
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "kernels.hpp"
 
@@ -35,7 +37,9 @@ constexpr int col_threads() {
     return is_pow2(L) ? kColThreads : (sizeof(T) == 4 ? 32 : 16) * (L / FftCfg<T, L, V>::EPT);
 }
 
-template <typename T, int M>
+// SI: element type of the real input (FP32 input of an FP64 transform is
+// widened at the load)
+template <typename T, int M, typename SI = T>
 __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
                                                          long long lines,
                                                          const cx<T> *__restrict__ tw) {
@@ -48,9 +52,12 @@ __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtr
     const bool ok = line < lines;
     cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * (M + 1);
     cx<T> reg[EPT];
-    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * M;
+    const cx<SI> *in = reinterpret_cast<const cx<SI> *>(src.p[blockIdx.y]) + line * M;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) reg[e] = ok ? in[t + TPC * e] : make_cx<T>(0, 0);
+    for (int e = 0; e < EPT; ++e) {
+        const cx<SI> z = ok ? in[t + TPC * e] : make_cx<SI>(0, 0);
+        reg[e] = make_cx<T>((T)z.re, (T)z.im);
+    }
     fft_line<T, M, 0, -1, Lay>(reg, t, c, tw, 2, lds);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) lds[Lay::at(c, t + TPC * e)] = reg[e];
@@ -430,7 +437,9 @@ template <typename T, int L>
 constexpr int krylov_bound() {
     return krylov_threads<T, L>() > kColThreads ? krylov_threads<T, L>() : kColThreads;
 }
-template <typename T, int L, int PASS>
+// SA: element type of the spectral operand a_in of KP_HESS (an FP64
+// spectrum read by an FP32 pass is rounded at the load)
+template <typename T, int L, int PASS, typename SA = T>
 __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc,
                                                                       T mu, int flags,
                                                                       const cx<T> *__restrict__ tw) {
@@ -496,7 +505,16 @@ __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             cx<T>(&ba)[EPT] = a == 0 ? b0 : (a == 1 ? b1 : b2);
-            load(f.a[a], reg);
+            if constexpr (std::is_same<SA, T>::value) {
+                load(f.a[a], reg);
+            } else {
+                const cx<SA> *p = reinterpret_cast<const cx<SA> *>(f.a[a]) + qq;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const cx<SA> z = ok ? p[(long long)(t + TPC * e) * Q] : make_cx<SA>(0, 0);
+                    reg[e] = make_cx<T>((T)z.re, (T)z.im);
+                }
+            }
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const cx<T> sh = reg[e];
@@ -666,17 +684,17 @@ __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int 
         default: break;             \
     }
 
-template <typename T>
+template <typename T, typename SI = T>
 static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
                        hipStream_t s) {
     const long long lines = (long long)g.n1 * g.n2;
-    HookScope hs(K_R2C, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
+    HookScope hs(K_R2C, (double)nf * (sizeof(SI) * g.N + 2.0 * sizeof(T) * g.NS));
 #define MIREG_L(M)                                                                                     \
     {                                                                                                  \
         constexpr int NT = line_threads<T, M>();                                                       \
         constexpr int W = FftShape<T, M, 0, NT>::W;                                                    \
         dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_r2c_x3<T, M>), grid, dim3(NT), 0, s, src, dst, lines, tw);               \
+        hipLaunchKernelGGL((k_r2c_x3<T, M, SI>), grid, dim3(NT), 0, s, src, dst, lines, tw);           \
     }
     MIREG_SWITCH_LINE(g.n3 / 2, MIREG_L)
 #undef MIREG_L
@@ -848,14 +866,14 @@ template void spectral_resample<double>(const Grid &, const Grid &, int, const d
                                         const Twiddles<double> &, hipStream_t);
 
 // ---- Krylov host passes ----
-template <typename T, int PASS>
+template <typename T, int PASS, typename SA = T>
 static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int flags,
                              const cx<T> *tw, hipStream_t s, int *blocks) {
     const long long Q = (long long)g.n2 * g.k3;
     // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3;
     // KF_XUPD adds x read and written (DIR) or the old direction read (INV)
     const bool xupd = flags & KF_XUPD;
-    const double fields = PASS == KP_HESS ? 9.0
+    const double fields = PASS == KP_HESS ? 6.0 + 3.0 * sizeof(SA) / sizeof(T)
                           : PASS == KP_DIR ? (xupd ? 18.0 : 12.0)
                                            : (PASS == KP_INV && xupd ? 9.0 : 6.0);
     HookScope hs(K_X1_KRYLOV, fields * 2.0 * sizeof(T) * g.NS);
@@ -865,7 +883,7 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
         dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw);    \
+        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS, SA>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw); \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -930,6 +948,40 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
         HookScope hs(K_REDUCE, 8.0 * blocks);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
     }
+}
+
+void krylov_forward_wide(const Grid &g, const float *const *u, cx<double> *const *hat, cx<double> *work,
+                         const Twiddles<double> &tw, hipStream_t s) {
+    FieldPtrs fin{}, fw{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fin.p[a] = const_cast<float *>(u[a]);
+        fw.p[a] = work + (long long)a * g.NS;
+        kp.w[a] = fw.p[a];
+        kp.o[a] = hat[a];
+    }
+    launch_r2c<double, float>(g, fin, fw, 3, tw.t[2], s);
+    launch_x2<double, -1>(g, fw, 3, tw.t[1], s);
+    SpecParams sp{};
+    sp.reg = 1;
+    launch_x1_krylov<double, KP_FWD>(g, kp, krylov_const<double>(g, sp), 0.0, 0, tw.t[0], s, nullptr);
+}
+
+void krylov_hessian_wide(const Grid &g, const float *const *b, const cx<double> *const *shat,
+                         cx<float> *const *hhat, cx<float> *work, const Twiddles<float> &tw, const SpecParams &sp,
+                         hipStream_t s) {
+    FieldPtrs fin{}, fw{};
+    KrylovPtrs kp{};
+    for (int a = 0; a < 3; ++a) {
+        fin.p[a] = const_cast<float *>(b[a]);
+        fw.p[a] = work + (long long)a * g.NS;
+        kp.w[a] = fw.p[a];
+        kp.a[a] = shat[a];
+        kp.o[a] = hhat[a];
+    }
+    launch_r2c<float>(g, fin, fw, 3, tw.t[2], s);
+    launch_x2<float, -1>(g, fw, 3, tw.t[1], s);
+    launch_x1_krylov<float, KP_HESS, double>(g, kp, krylov_const<float>(g, sp), 0.0f, 0, tw.t[0], s, nullptr);
 }
 
 template <typename T>

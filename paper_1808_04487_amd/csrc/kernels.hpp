@@ -95,6 +95,16 @@ void krylov_forward(const Grid &g, const T *const *u, cx<T> *const *hat, cx<T> *
 template <typename T>
 void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat, cx<T> *work,
                     const Twiddles<T> &tw, const SpecParams &sp, int flags, hipStream_t s);
+// The same two passes across precisions, for the tail beta_v A u + K b of an
+// FP32 problem whose u spectrum must be accurate mode by mode: hat = F u
+// with FP64 arithmetic from FP32 u (work: 3 FP64 half spectra), and
+// hhat = beta_v a(k) shat + K F b in FP32 with the FP64 shat rounded at the
+// load (no reduction).
+void krylov_forward_wide(const Grid &g, const float *const *u, cx<double> *const *hat, cx<double> *work,
+                         const Twiddles<double> &tw, hipStream_t s);
+void krylov_hessian_wide(const Grid &g, const float *const *b, const cx<double> *const *shat,
+                         cx<float> *const *hhat, cx<float> *work, const Twiddles<float> &tw, const SpecParams &sp,
+                         hipStream_t s);
 // xhat += alpha shat (when xhat and alpha are given and not KF_FIRST: the
 // iterate's update of the previous iteration, from the old direction; alpha
 // a device scalar), then shat = z + mu shat (shat not read with KF_FIRST),
@@ -173,6 +183,9 @@ void interp_field(const Grid &g, int order, const SI *f, const T *disp, SO *out,
 // Adjoint final condition: lam = mR - m(1)   (lam in storage type S)
 template <typename T, typename S>
 void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s);
+// out[i] = in[i] for i < n, converted from type SI to SO (through T)
+template <typename T, typename SI, typename SO>
+void convert_field(long long n, const SI *in, SO *out, hipStream_t s);
 // One adjoint step: lam_out = L + dt/2 (S + (L + dt S) d), L = I[lam_in](Y), S = I[lam_in d](Y)
 template <typename T, typename S>
 void adjoint_step(const Grid &g, int order, double dt, const S *lam_in, const T *d, const T *Y,

@@ -129,6 +129,10 @@ struct mireg_ctx {
     void *spec = nullptr;   // 6 half spectra
     void *kspec = nullptr;  // 15 half spectra: x, r, s, Hs, z of the spectral PCG
     void *tw[3] = {nullptr, nullptr, nullptr};
+    // FP32 contexts: FP64 twiddles and 6 FP64 half spectra for the accurate
+    // spectrum of u in beta_v A u + K b, allocated on first use
+    void *tw64[3] = {nullptr, nullptr, nullptr};
+    cx<double> *spec64 = nullptr;
     double *partials = nullptr, *dres = nullptr;  // device reduction buffers
     double *xpart = nullptr;                      // partials of the fused spectral dot products
     double *hres = nullptr;                       // pinned host mirror of dres
@@ -467,6 +471,61 @@ int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
     return check_launch(ctx);
 }
 
+int alloc(mireg_ctx *ctx, void **p, size_t bytes);
+template <typename T>
+int make_twiddles_into(mireg_ctx *ctx, void *const *dst);
+
+// out = beta_v A u + K b, the tail of the reduced gradient (u = v) and of
+// the matvec entry point (u = vt).  An FP32 forward transform of u leaves
+// roundoff of about eps ||u|| on every mode, which A multiplies by up to
+// 3 (n/2)^2 (H1; its square for H2): at 256^3 that alone is 2.5e-5 of the
+// gradient.  In FP32 contexts the spectrum of u is therefore formed with
+// FP64 arithmetic (from the FP32 field) and read by the FP32 operator pass
+// mode by mode; the spectrum of b, the multipliers and the inverse
+// transform stay FP32, whose errors are relative to their own output.  The
+// FP64 twiddles and 6 FP64 half spectra are allocated on first use; the
+// Krylov slot KV_H is scratch outside PCG.  (PCG keeps its directions as
+// spectra and never transforms them forward.)
+template <typename T>
+int ensure_tail64(mireg_ctx *ctx) {
+    if (std::is_same<T, double>::value || ctx->spec64) return MIREG_OK;
+    const long long NS = ctx->g.NS;
+    const int n[3] = {ctx->g.n1, ctx->g.n2, ctx->g.n3};
+    int rc;
+    for (int a = 0; a < 3; ++a)
+        if ((rc = alloc(ctx, &ctx->tw64[a], (size_t)n[a] * sizeof(cx<double>)))) return rc;
+    if ((rc = make_twiddles_into<double>(ctx, ctx->tw64))) return rc;
+    if ((rc = alloc(ctx, (void **)&ctx->spec64, (size_t)6 * NS * sizeof(cx<double>)))) return rc;
+    return MIREG_OK;
+}
+
+template <typename T, typename S = T>
+int accurate_tail(mireg_ctx *ctx, const T *u, const T *b, T *out) {
+    if constexpr (std::is_same<T, double>::value) {
+        op_tail<T, S>(ctx, ctx->p.beta_v, u, b, out);
+        return MIREG_OK;
+    } else {
+        const long long N = ctx->N(), NS = ctx->g.NS;
+        int rc;
+        if ((rc = ensure_tail64<T>(ctx))) return rc;
+        Phase ph(ctx, 0);
+        const T *up[3] = {u, u + N, u + 2 * N}, *bp[3] = {b, b + N, b + 2 * N};
+        cx<double> *uh[3] = {ctx->spec64 + 3 * NS, ctx->spec64 + 4 * NS, ctx->spec64 + 5 * NS};
+        Twiddles<double> tw64;
+        for (int a = 0; a < 3; ++a) tw64.t[a] = static_cast<const cx<double> *>(ctx->tw64[a]);
+        krylov_forward_wide(ctx->g, up, uh, ctx->spec64, tw64, ctx->stream);
+        cx<T> *hh[3] = {ctx->khat<T>(KV_H, 0), ctx->khat<T>(KV_H, 1), ctx->khat<T>(KV_H, 2)};
+        const cx<double> *uhc[3] = {uh[0], uh[1], uh[2]};
+        krylov_hessian_wide(ctx->g, bp, uhc, hh, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx),
+                            spec_params<T>(ctx), ctx->stream);
+        const cx<T> *hhc[3] = {hh[0], hh[1], hh[2]};
+        T *op[3] = {out, out + N, out + 2 * N};
+        krylov_inverse<T>(ctx->g, hhc, nullptr, nullptr, op, static_cast<cx<T> *>(ctx->spec), twiddles<T>(ctx),
+                          ctx->stream);
+        return MIREG_OK;
+    }
+}
+
 // ---- reduced gradient ----
 template <typename T, typename S = T>
 int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
@@ -484,11 +543,11 @@ int impl_gradient(mireg_ctx *ctx, T *g, double *gnorm) {
         adjoint_init<T, S>(ctx->g, ctx->f<T>(ctx->mR), ctx->f<T>(ctx->m) + nt * N, lam + nt * N, ctx->stream);
     }
     backward_sweep<T, S>(ctx, lam, b);
-    op_tail<T, S>(ctx, ctx->p.beta_v, ctx->f<T>(ctx->v), b, g);
+    int rc = accurate_tail<T, S>(ctx, ctx->f<T>(ctx->v), b, g);
+    if (rc) return rc;
     if (gnorm) {
         double gg = 0;
-        int rc = dot_h<T>(ctx, g, g, 3 * N, &gg);
-        if (rc) return rc;
+        if ((rc = dot_h<T>(ctx, g, g, 3 * N, &gg))) return rc;
         *gnorm = std::sqrt(gg);
     }
     return check_launch(ctx);
@@ -538,7 +597,8 @@ int impl_matvec(mireg_ctx *ctx, const T *vt, T *Hvt) {
     ensure_d<T, S>(ctx);
     ensure_Y<T, S>(ctx);
     matvec_transport<T, S>(ctx, vt);
-    op_tail<T, S>(ctx, ctx->p.beta_v, vt, ctx->f<T>(ctx->b), Hvt);
+    int rc = accurate_tail<T, S>(ctx, vt, ctx->f<T>(ctx->b), Hvt);
+    if (rc) return rc;
     return check_launch(ctx);
 }
 
@@ -583,6 +643,8 @@ template <typename T, typename S = T>
 int matvec_graph(mireg_ctx *ctx, const T *vt, T *Hvt, bool spectral = false, int flags = 0) {
     if (!ctx->use_graphs || ctx->tm.on || ctx->stats_on) return matvec_body<T, S>(ctx, vt, Hvt, spectral, flags);
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    int rc0 = ensure_tail64<T>(ctx);  // allocates: not inside the capture
+    if (rc0) return rc0;
     ensure_state<T, S>(ctx);
     ensure_gradm<T, S>(ctx);
     ensure_d<T, S>(ctx);
@@ -848,7 +910,8 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
 // needed only as a spectrum, and only the direction s is transformed back
 // (the transport needs it on the grid).  Inner products come from Parseval.
 template <typename T, typename S = T>
-int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
+int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres,
+                      int *status, int *matvecs) {
     const long long N = ctx->N();
     const double h3 = ctx->cell();
     T *s = ctx->vec<T>(2);
@@ -879,7 +942,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     if ((rc = readback(ctx, 3))) return rc;
     const double r0 = std::sqrt(h3 * ctx->hres[2]);
     double rz = h3 * ctx->hres[1];
-    int it = 0;
+    int it = 0, mv = 0, st = r0 > 0 ? MIREG_MAXIT : MIREG_CONVERGED_REL;
     double rnorm = r0;
     bool x_is_s = false;
     // The step length alpha = rz / sHs is formed on the device (dres[3]) by
@@ -896,6 +959,7 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
         }
         while (it < maxit) {
             if ((rc = matvec_graph<T, S>(ctx, s, nullptr, true))) return rc;  // H s, sHs
+            ++mv;
             {
                 Phase ph(ctx, 2);
                 krylov_update<T>(ctx->g, true, 1, ctx->dres, rh, hh, sp, ctx->partials, ctx->stream);
@@ -905,12 +969,14 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
             if (!(sHs > 0)) {  // non-positive curvature (r was left unchanged): keep the current
                                // iterate (z on the first)
                 x_is_s = it == 0;
+                st = MIREG_NEG_CURV;
                 break;
             }
             ++it;
             rnorm = std::sqrt(h3 * ctx->hres[2]);
             if (rnorm <= rtol * r0) {
                 pending = true;
+                st = MIREG_CONVERGED_REL;
                 break;
             }
             double rz_new = h3 * ctx->hres[1];
@@ -933,12 +999,15 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     }
     if (iters) *iters = it;
     if (relres) *relres = r0 > 0 ? rnorm / r0 : 0.0;
+    if (status) *status = st;
+    if (matvecs) *matvecs = mv;
     return check_launch(ctx);
 }
 
 template <typename T, typename S = T>
-int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres) {
-    return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres);
+int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres,
+             int *status = nullptr, int *matvecs = nullptr) {
+    return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres, status, matvecs);
 }
 
 template <typename T, typename S = T>
@@ -959,10 +1028,12 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     HIP_OK(hipMemcpyAsync(vk, v_io, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     double J = 0;
     if ((rc = impl_objective<T, S>(ctx, &J, nullptr, nullptr))) return rc;
-    R.pde_solves += 1;
     double gn = 0;
     if ((rc = impl_gradient<T, S>(ctx, g, &gn))) return rc;
-    R.pde_solves += 1;
+    // counted as the paper's tables count them (Sec. 4.7: 3 iterations, 3
+    // matvecs, 15 PDE solves): a state solve for J and one for g, and the
+    // adjoint solve, although the gradient reuses the objective's state here
+    R.pde_solves += 3;
     const double g0 = gn;
     R.J0 = J;
     R.gnorm0 = g0;
@@ -986,11 +1057,12 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
         // rhs = -g in vector 7
         T *rhs = ctx->vec<T>(7);
         affine<T>(n, g, -1.0, 0.0, rhs, ctx->stream);
-        int its = 0;
-        if ((rc = impl_pcg<T, S>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr))) return rc;
-        R.matvecs += its;
+        int its = 0, pst = 0, mv = 0;
+        if ((rc = impl_pcg<T, S>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr, &pst, &mv))) return rc;
+        R.matvecs += mv;
         R.pcg_iters += its;
-        R.pde_solves += 2 * its;
+        R.pde_solves += 2 * mv;
+        R.neg_curv += pst == MIREG_NEG_CURV;
         double slope = 0;
         if ((rc = dot_h<T>(ctx, g, vt, n, &slope))) return rc;
         double alpha = 1.0, Jt = 0;
@@ -1116,6 +1188,28 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
             }
             break;
         }
+        case MIREG_OP_TRANSPORT_ADJOINT: {
+            // lam^nt = in, then nt backward steps along Y in the storage type
+            // of the adjoint history (its buffer is scratch between sweeps)
+            ensure_Y<T, S>(ctx);
+            ensure_d<T, S>(ctx);
+            const int nt = ctx->p.nt;
+            const double dt = 1.0 / nt;
+            S *lam = ctx->f<S>(ctx->lam);
+            Phase ph(ctx, 1);
+            if constexpr (std::is_same<S, T>::value)
+                HIP_OK(hipMemcpyAsync(lam + nt * N, in, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+            else
+                convert_field<T, T, S>(N, in, lam + nt * N, ctx->stream);
+            for (int j = nt - 1; j >= 0; --j)
+                adjoint_step<T, S>(ctx->g, ctx->p.interp_order, dt, lam + (j + 1) * N, ctx->f<T>(ctx->d),
+                                   ctx->f<T>(ctx->Y), lam + j * N, ctx->box_Y, ctx->stream);
+            if constexpr (std::is_same<S, T>::value)
+                HIP_OK(hipMemcpyAsync(out, lam, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+            else
+                convert_field<T, S, T>(N, lam, out, ctx->stream);
+            break;
+        }
         case MIREG_OP_INTERP: {
             const int box = box_of_displacement<T>(ctx, in + N);
             Phase ph(ctx, 1);
@@ -1145,8 +1239,8 @@ int impl_op(mireg_ctx *ctx, int opcode, const T *in, T *out, double arg) {
     return check_launch(ctx);
 }
 
-template <typename T, typename S = T>
-int make_twiddles(mireg_ctx *ctx) {
+template <typename T>
+int make_twiddles_into(mireg_ctx *ctx, void *const *dst) {
     const int n[3] = {ctx->g.n1, ctx->g.n2, ctx->g.n3};
     for (int a = 0; a < 3; ++a) {
         std::vector<cx<T>> h(n[a]);
@@ -1157,10 +1251,15 @@ int make_twiddles(mireg_ctx *ctx) {
         }
         // on the context's stream: a copy on the legacy stream would invalidate
         // a graph capture running in another thread
-        HIP_OK(hipMemcpyAsync(ctx->tw[a], h.data(), n[a] * sizeof(cx<T>), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipMemcpyAsync(dst[a], h.data(), n[a] * sizeof(cx<T>), hipMemcpyHostToDevice, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
     return MIREG_OK;
+}
+
+template <typename T, typename S = T>
+int make_twiddles(mireg_ctx *ctx) {
+    return make_twiddles_into<T>(ctx, ctx->tw);
 }
 
 int alloc(mireg_ctx *ctx, void **p, size_t bytes) {
@@ -1403,11 +1502,11 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner) {
 }
 
 int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int maxit, int *iters,
-                    double *relres) {
+                    double *relres, int *status) {
     if (!ctx || !rhs || !x) return ctx ? ctx->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
     if (maxit < 0 || !(rtol >= 0)) return ctx->fail(MIREG_E_ARG, "invalid rtol/maxit");
     if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    return DISPATCH(ctx, (impl_pcg<T, S>(ctx, (const T *)rhs, (T *)x, rtol, maxit, iters, relres)));
+    return DISPATCH(ctx, (impl_pcg<T, S>(ctx, (const T *)rhs, (T *)x, rtol, maxit, iters, relres, status)));
 }
 
 int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts, mireg_report *rep) {

@@ -1,6 +1,6 @@
 // Learned warm start: a periodic 3D convolutional encoder-decoder that maps
 // an image pair to an initial velocity, with its training (not part of the
-// paper; the solver's warm-start input is what it feeds, Sec. 3.2).
+// paper; the solver's warm-start input is what it feeds, Sec. 3.6).
 //
 // Dense layers run on the matrix cores: every 3x3x3 convolution is an
 // implicit GEMM (rows: 16 voxels, columns: output channels, reduction: 27

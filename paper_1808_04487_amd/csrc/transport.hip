@@ -7,8 +7,10 @@
 //
 // Every step is one kernel over tiles of points (16 x3 x 8 x2 x 8 x1 by
 // default; 32 x 8 x 4 and 16 x 16 x 8 selectable), 256 threads:
-//   1. each thread reads the displacement of its points (coalesced rows of
-//      along x3) and the block reduces the bounding box of all stencils;
+//   1. each thread reads the displacement of its points (coalesced rows
+//      along x3) and the block reads its tile's bounding box of all
+//      stencils, measured once per displacement field (k_box; without the
+//      stored boxes the block reduces it from the displacements);
 //   2. if the box fits the LDS budget, the block copies the box of the
 //      gathered field(s) from HBM/L2 into LDS once (rows along x3, periodic
 //      wrap applied here) and every 64-node stencil is read from LDS;
@@ -837,6 +839,14 @@ __global__ __launch_bounds__(kSlThreads) void k_adjoint_init(long long N, const 
     store_as(lam, idx, mR[idx] - m[idx]);
 }
 
+// out = in, converted between storage types (FP16 storage <-> the boundary type)
+template <typename T, typename SI, typename SO>
+__global__ __launch_bounds__(kSlThreads) void k_convert(long long N, const SI *__restrict__ in, SO *__restrict__ out) {
+    const long long idx = (long long)blockIdx.x * kSlThreads + threadIdx.x;
+    if (idx >= N) return;
+    store_as(out, idx, load_as<T>(in, idx));
+}
+
 template <typename T, typename S>
 __global__ __launch_bounds__(kSlThreads) void k_incstate_init(long long N, T hdt, const T *__restrict__ gm,
                                                               const T *__restrict__ vt, S *__restrict__ q) {
@@ -940,6 +950,12 @@ void adjoint_init(const Grid &g, const T *mR, const T *m, S *lam, hipStream_t s)
     hipLaunchKernelGGL((k_adjoint_init<T, S>), dim3(blocks_for(g.N)), dim3(kSlThreads), 0, s, g.N, mR, m, lam);
 }
 
+template <typename T, typename SI, typename SO>
+void convert_field(long long n, const SI *in, SO *out, hipStream_t s) {
+    HookScope hs(K_VECTOR, (double)(sizeof(SI) + sizeof(SO)) * n);
+    hipLaunchKernelGGL((k_convert<T, SI, SO>), dim3(blocks_for(n)), dim3(kSlThreads), 0, s, n, in, out);
+}
+
 template <typename T, typename S>
 void adjoint_step(const Grid &gg, int order, double dt, const S *lam_in, const T *d, const T *Y, S *lam_out,
                   SlBox box, hipStream_t s) {
@@ -995,6 +1011,8 @@ MIREG_INST_T(double)
 MIREG_INST(float, float)
 MIREG_INST(double, double)
 MIREG_INST(float, __half)
+template void convert_field<float, float, __half>(long long, const float *, __half *, hipStream_t);
+template void convert_field<float, __half, float>(long long, const __half *, float *, hipStream_t);
 #undef MIREG_INST
 #undef MIREG_INST_T
 

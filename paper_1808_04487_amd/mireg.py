@@ -17,20 +17,20 @@ OK, E_ARG, E_SHAPE, E_STATE, E_HIP, E_NOMEM, E_NONFINITE = 0, -1, -2, -3, -4, -5
 F32, F64, F32_H16 = 0, 1, 2
 H1, H2 = 1, 2
 DIV_NONE, DIV_NEAR, DIV_LERAY = 0, 1, 2
-CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL = 1, 2, 3, 4
+CONVERGED_REL, CONVERGED_ABS, MAXIT, LS_FAIL, NEG_CURV = 1, 2, 3, 4, 5
 PC_SPECTRAL, PC_TWO_LEVEL = 0, 1
 
 OPS = {
     "grad": 1, "div": 2, "laplace": 3, "apply_A": 4, "apply_K": 5, "leray": 6, "precond": 7,
     "gauss": 8, "departure_X": 9, "departure_Y": 10, "transport_state": 11, "interp": 12,
-    "rescale01": 13, "scale_maxnorm": 14,
+    "rescale01": 13, "scale_maxnorm": 14, "transport_adjoint": 15,
 }
 # (input components, output components); interp takes f and a displacement (1 + 3)
 _OP_SHAPES = {
     "grad": (1, 3), "div": (3, 1), "laplace": (1, 1), "apply_A": (3, 3), "apply_K": (3, 3),
     "leray": (3, 3), "precond": (3, 3), "gauss": (1, 1), "departure_X": (3, 3),
     "departure_Y": (3, 3), "transport_state": (1, 1), "interp": (4, 1), "rescale01": (1, 1),
-    "scale_maxnorm": (3, 3),
+    "scale_maxnorm": (3, 3), "transport_adjoint": (1, 1),
 }
 
 
@@ -59,7 +59,8 @@ class Report(ctypes.Structure):
                 ("ls_trials", ctypes.c_int), ("J0", ctypes.c_double), ("J", ctypes.c_double),
                 ("mismatch_rel", ctypes.c_double), ("gnorm0", ctypes.c_double),
                 ("gnorm", ctypes.c_double), ("gnorm_rel", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("coarse_matvecs", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("coarse_matvecs", ctypes.c_int),
+                ("neg_curv", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -91,7 +92,7 @@ SIGNATURES = {
     "mireg_gradient": ([_vp, _vp, _dp], ctypes.c_int),
     "mireg_hessian_matvec": ([_vp, _vp, _vp], ctypes.c_int),
     "mireg_precond_apply": ([_vp, _vp, _vp], ctypes.c_int),
-    "mireg_pcg_solve": ([_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp], ctypes.c_int),
+    "mireg_pcg_solve": ([_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp, _ip], ctypes.c_int),
     "mireg_gn_solve": ([_vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)], ctypes.c_int),
     "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
     "mireg_set_precond": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
@@ -253,12 +254,14 @@ class Context:
         self._check(self.lib.mireg_precond_apply(self.h, self._arg(r, 3, "r"), self._arg(out, 3, "z")))
         return out
 
-    def pcg(self, rhs, rtol=1e-3, maxit=100, out=None):
+    def pcg(self, rhs, rtol=1e-3, maxit=100, out=None, with_status=False):
+        """Returns (x, iterations, relative residual[, status])."""
         out = self.empty(3) if out is None else out
-        it, rel = ctypes.c_int(), ctypes.c_double()
+        it, rel, st = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
         self._check(self.lib.mireg_pcg_solve(self.h, self._arg(rhs, 3, "rhs"), self._arg(out, 3, "x"),
-                                             float(rtol), int(maxit), ctypes.byref(it), ctypes.byref(rel)))
-        return out, it.value, rel.value
+                                             float(rtol), int(maxit), ctypes.byref(it), ctypes.byref(rel),
+                                             ctypes.byref(st)))
+        return (out, it.value, rel.value, st.value) if with_status else (out, it.value, rel.value)
 
     def gn_solve(self, v0=None, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100,
                  armijo_c1=1e-4, max_ls=10, log_level=0):

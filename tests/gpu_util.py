@@ -47,32 +47,18 @@ def assert_close(got, ref, dtype, factor=1.0, what=""):
     return e
 
 
-def fp32_reg_tol(g, reg, beta_v, u_in, ref_out):
-    """L2-relative bound for an FP32 result containing beta_v A u.
-
-    The FP32 forward FFT of u leaves random roundoff of RMS size about
-    eps sqrt(log2 N) ||u|| spread evenly over the modes; A = |k|^2 (H1) or
-    |k|^4 (H2) multiplies it by rms_k a(k).  Relative to the output this is
-    eps sqrt(log2 N) beta_v rms(a) ||u|| / ||out||, which for H2 on fine grids
-    exceeds the 1e-5 field tolerance.  The bound is the larger of 1e-5 and
-    four times that estimate."""
-    eps = 2.0 ** -24
-    arms = float(np.sqrt(np.mean(np.broadcast_to(g.ksq ** reg, g.n) ** 2)))
-    amp = beta_v * arms * np.linalg.norm(u_in) / np.linalg.norm(ref_out)
-    return max(TOL[torch.float32], 4.0 * eps * np.sqrt(np.log2(g.N)) * amp)
-
-
-def assert_close_composite(got, ref, dtype, what="", tol32=None):
-    """Composite operators (gradient, matvec): FP64 max-relative 5 TOL; FP32
-    L2-relative tol32 (default TOL, see fp32_reg_tol) and max-relative
-    10 tol32."""
+def assert_close_composite(got, ref, dtype, what=""):
+    """Composite operators (gradient, matvec): FP64 max-relative 5 TOL
+    (rounding of a few hundred chained operations); FP32 the field tolerance
+    1e-5 itself, both in the L2-relative and the max-relative sense."""
     if dtype == torch.float64:
         return assert_close(got, ref, dtype, factor=5, what=what)
-    tol = TOL[dtype] if tol32 is None else tol32
+    tol = TOL[dtype]
     e2 = rel_err_l2(got, ref)
-    assert e2 <= tol, "%s: L2 rel error %.3e > %.1e" % (what, e2, tol)
     e = rel_err(got, ref)
-    assert e <= 10 * tol, "%s: max rel error %.3e > %.1e" % (what, e, 10 * tol)
+    print("%s: L2 rel %.2e, max rel %.2e (bound %.0e)" % (what, e2, e, tol), flush=True)
+    assert e2 <= tol, "%s: L2 rel error %.3e > %.1e" % (what, e2, tol)
+    assert e <= tol, "%s: max rel error %.3e > %.1e" % (what, e, tol)
     return e
 
 

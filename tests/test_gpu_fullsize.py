@@ -12,8 +12,8 @@ import torch
 from oracle import core, prep, solver
 from paper_1808_04487_amd import mireg, synth
 
-from gpu_util import (as_input, assert_close, assert_close_composite, fp32_reg_tol, need_gpu,
-                      rel_err_l2, smooth_scalar, smooth_vector)
+from gpu_util import (as_input, assert_close, need_gpu, rel_err, rel_err_l2, smooth_scalar,
+                      smooth_vector)
 
 pytestmark = pytest.mark.gpu
 
@@ -68,13 +68,17 @@ def test_fullsize_transport_gradient_matvec(workload256):
     ctx.set_velocity(vw_t)
     R = core.Registration(workload_params(g), mT, mR)
     R.set_velocity(vw)
+    # H1 at 256^3: the field tolerance 1e-5 itself, in L2 and element by element
     gr, _ = ctx.gradient()
     go = R.gradient()
-    assert_close_composite(gr, go, dt, what="gradient 256^3", tol32=fp32_reg_tol(g, 1, 5e-3, vw, go))
+    eg2, eg = rel_err_l2(gr, go), rel_err(gr, go)
     Hv = ctx.hessian_matvec(p_t)
     Ho = R.hessian_matvec(p)
-    e = assert_close_composite(Hv, Ho, dt, what="matvec 256^3", tol32=fp32_reg_tol(g, 1, 5e-3, p, Ho))
-    print("256^3 matvec rel err %.2e (L2 %.2e)" % (e, rel_err_l2(Hv, Ho)), flush=True)
+    eh2, eh = rel_err_l2(Hv, Ho), rel_err(Hv, Ho)
+    print("256^3 gradient L2 rel %.2e max rel %.2e; matvec L2 rel %.2e max rel %.2e" % (eg2, eg, eh2, eh),
+          flush=True)
+    assert eg2 <= 1e-5 and eg <= 1e-5, "gradient 256^3"
+    assert eh2 <= 1e-5 and eh <= 1e-5, "matvec 256^3"
     # PCG on Krylov spectra (the solve's path), three iterations on both sides
     rhs_t, rhs = as_input(-go, dt)
     x, it, rel = ctx.pcg(rhs_t, rtol=1e-12, maxit=3)
@@ -118,8 +122,8 @@ def test_fullsize_gn_solve_reaches_tolerance(workload256):
     assert abs(g0 - rep["gnorm0"]) <= 1e-4 * g0
     assert abs(gk / g0 - rep["gnorm_rel"]) <= 1e-2 * rep["gnorm_rel"]
     assert gk / g0 <= 5e-2 * 1.01
-    assert abs(J - rep["J"]) <= 2e-3 * abs(J) and J < 0.1 * J0
-    assert abs(mis - rep["mismatch_rel"]) <= 1e-2 * mis
+    assert abs(J - rep["J"]) <= 1e-3 * abs(J) and J < 0.1 * J0
+    assert abs(mis - rep["mismatch_rel"]) <= 1e-3 * mis
 
 
 def test_max_grid_properties():
@@ -216,9 +220,9 @@ def test_constant_template_degenerate(dtype):
     rhs = smooth_vector(g, 52)
     rhs -= rhs.mean(axis=(1, 2, 3), keepdims=True)
     rhs_t, rhs = as_input(rhs, dtype)
-    # one PCG iteration solves H x = rhs; in FP32 the residual floor is the
-    # FFT roundoff of H M^-1 r, amplified by beta_v |k|^4 at the top modes
+    # one PCG iteration solves H x = rhs: the direction M^-1 r and H of it are
+    # formed mode by mode on the kept spectrum, so the residual is rounding
     x, it, rel = ctx.pcg(rhs_t, rtol=0.0, maxit=1)
+    print("constant template, one PCG iteration: relres %.2e" % rel, flush=True)
     assert it == 1
-    z = core.apply_Hreg_inverse(g, rhs, core.REG_H2, 1e-2)
-    assert rel < (1e-10 if dtype == torch.float64 else fp32_reg_tol(g, 2, 1e-2, z, rhs))
+    assert rel < (1e-10 if dtype == torch.float64 else 1e-5)

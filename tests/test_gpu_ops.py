@@ -8,7 +8,7 @@ import torch
 from oracle import core, prep
 from paper_1808_04487_amd import mireg, synth
 
-from gpu_util import as_input, assert_close, need_gpu, smooth_scalar, smooth_vector
+from gpu_util import as_input, assert_close, need_gpu, rel_err_l2, smooth_scalar, smooth_vector
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +210,39 @@ def test_transport_state_time_steps(nt, dtype):
     else:
         assert_close(m1, ref, dtype, factor=4, what="state m(1) nt=%d" % nt)
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (32, 16, 64), (48, 96, 80)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, "f32h16"])
+@pytest.mark.parametrize("order", [3, 1])
+def test_transport_adjoint_op(n, dtype, order):
+    """The adjoint equation (eq. "adj") on its own: lam(0) from lam(1) over
+    nt backward steps along Y with the source lam div v, at a compressible
+    velocity of several cells per step, against the oracle's steps.  FP64
+    1e-12, FP32 1e-5 (max-relative), FP16 storage of the steps 1e-3 (L2)."""
+    need_gpu()
+    g = core.Grid(n)
+    tdt = torch.float32 if dtype == "f32h16" else dtype
+    ctx = mireg.Context(n, order=order, dtype=dtype)
+    v_t, v = as_input(smooth_vector(g, 21, amp=1.2, sigma=max(1.5, n[0] / 16)), tdt)
+    l_t, l1 = as_input(smooth_scalar(g, 22), tdt)
+    ctx.set_velocity(v_t)
+    l0 = ctx.op("transport_adjoint", l_t)
+    Y = core.departure_points(g, v, 4, order, +1)
+    d = core.div(g, v)
+    assert np.abs(d).max() > 0.1  # the source term matters
+    lo = l1
+    for _ in range(4):
+        lo = core.adjoint_step(g, lo, Y, d, 4, order)
+    # in place (in and out alias)
+    l_in = l_t.clone()
+    ctx.op("transport_adjoint", l_in, out=l_in)
+    ctx.close()
+    assert torch.equal(l_in, l0)
+    if dtype == "f32h16":
+        e = rel_err_l2(l0, lo)
+        print("adjoint op", n, order, "f32h16 L2 rel %.2e" % e, flush=True)
+        assert e <= 1e-3
+    else:
+        e = assert_close(l0, lo, dtype, what="lam(0)")
+        print("adjoint op", n, dtype, order, "max rel %.2e" % e, flush=True)

@@ -12,7 +12,7 @@ import torch
 from oracle import core, prep, solver, twolevel
 from paper_1808_04487_amd import mireg, synth
 
-from gpu_util import (as_input, assert_close, assert_close_composite, fp32_reg_tol, need_gpu, rel_err,
+from gpu_util import (as_input, assert_close, assert_close_composite, need_gpu, rel_err,
                       smooth_scalar, smooth_vector)
 
 pytestmark = pytest.mark.gpu
@@ -99,10 +99,10 @@ def test_objective_gradient_matvec_pcg_radix35(case, dtype):
     assert abs(rg - rgo) <= 10 * tol * abs(rgo)
     gr, gn = ctx.gradient()
     go = R.gradient()
-    assert_close_composite(gr, go, dtype, what="gradient", tol32=fp32_reg_tol(g, reg, bv, v, go))
+    assert_close_composite(gr, go, dtype, what="gradient")
     vt_t, vt = as_input(smooth_vector(g, 12, amp=1.0), dtype)
     Ho = R.hessian_matvec(vt)
-    assert_close_composite(ctx.hessian_matvec(vt_t), Ho, dtype, what="matvec", tol32=fp32_reg_tol(g, reg, bv, vt, Ho))
+    assert_close_composite(ctx.hessian_matvec(vt_t), Ho, dtype, what="matvec")
     rhs_t, rhs = as_input(-go, dtype)
     x, it, rel = ctx.pcg(rhs_t, rtol=1e-3, maxit=50)
     xo, ito, relo = solver.pcg(R.hessian_matvec, R.precond, rhs, 1e-3, 50, g.inner)
