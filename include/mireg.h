@@ -245,6 +245,27 @@ enum {
 };
 int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg);
 
+/* Allocation-free interpolation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): out = I[f](x + disp), the result of mireg_op(ctx,
+ * MIREG_OP_INTERP, ...) bit for bit, without a context.  n: grid as in
+ * mireg_params (at most 512 per axis); order 3 (tricubic) or 1 (trilinear);
+ * dtype MIREG_F32 or MIREG_F64 (element type of f, disp and out); f a scalar
+ * field, disp a displacement field [3][n1][n2][n3] in cell units, out a
+ * scalar field, all device pointers owned by the caller; stream a
+ * hipStream_t or NULL.  The call enqueues its kernels on `stream` and
+ * returns without synchronising; it calls no allocator.  Its scratch (every
+ * tile's stencil box and the box-measurement slots, 4 MiB) is one static
+ * device array per GPU, held until the process ends and shared by every
+ * call on that GPU, each call overwriting what the last one left: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Errors: MIREG_E_ARG (null pointer, order,
+ * dtype), MIREG_E_SHAPE (unsupported axis, or a grid beyond the scratch),
+ * MIREG_E_HIP; mireg_last_error(NULL) gives the message of the last failed
+ * call in the calling thread. */
+int mireg_interp_noalloc(const int n[3], int order, int dtype, const void *f, const void *disp, void *out,
+                         void *stream);
+
 /* Per-phase GPU time accumulated since the last reset (milliseconds), for
  * the FFT / interpolation split the paper reports. */
 typedef struct {

@@ -164,6 +164,8 @@ struct SlBox {
 };
 // Words of per-tile box storage for a grid under any tile shape.
 long long sl_box_words(const Grid &g);
+// Message of the last failed mireg_interp_noalloc call in this thread.
+const char *noalloc_error();
 
 // *out (device) = largest stencil box over the transport tiles for the
 // displacement (a D_a) b_a in cell units; slots: 1024 device words of

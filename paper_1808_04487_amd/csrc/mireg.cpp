@@ -1414,7 +1414,7 @@ int mireg_destroy(mireg_ctx *ctx) {
     return MIREG_OK;
 }
 
-const char *mireg_last_error(const mireg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *mireg_last_error(const mireg_ctx *ctx) { return ctx ? ctx->err.c_str() : mireg::noalloc_error(); }
 
 size_t mireg_workspace_bytes(const mireg_ctx *ctx) { return ctx ? ctx->bytes : 0; }
 

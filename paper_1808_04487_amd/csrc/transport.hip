@@ -23,9 +23,12 @@
 // (Sec. 3.5: only time histories are kept, no full space-time Newton).
 #include <limits.h>
 
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "mireg.h"
 
 namespace mireg {
 
@@ -1016,4 +1019,103 @@ template void convert_field<float, __half, float>(long long, const __half *, flo
 #undef MIREG_INST
 #undef MIREG_INST_T
 
+// ---------------------------------------------------------------------------
+// Allocation-free interpolation (mireg_interp_noalloc): the per-tile stencil
+// boxes and the box-measurement slots live in one file-scope device array
+// sized for the largest supported grid (512^3: 131072 tiles of 8 ints under
+// any tile shape), so a call allocates nothing.  Host code reaches the array
+// only through the device address hipGetSymbolAddress returns, taken once
+// per device with that device current.
+constexpr long long kNoAllocTileWords = 8LL * 131072;
+constexpr long long kNoAllocWords = kNoAllocTileWords + kBoxSlots + 64;
+static __device__ __align__(256) int scratch[kNoAllocWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int *g_scratch_ptr[kMaxDevices];
+thread_local std::string g_noalloc_err;
+
+int noalloc_fail(int code, const std::string &msg) {
+    g_noalloc_err = msg;
+    return code;
+}
+
+bool noalloc_axis(int n) {
+    return (n >= 8 && n <= 512 && (n & (n - 1)) == 0) || n == 48 || n == 80 || n == 96 || n == 160;
+}
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_ptr(int **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return noalloc_fail(MIREG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return noalloc_fail(MIREG_E_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return noalloc_fail(MIREG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<int *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MIREG_OK;
+}
+
+template <typename T>
+void interp_noalloc(const Grid &g, int order, const T *f, const T *disp, T *out, int *scr, hipStream_t s) {
+    int *tiles = scr;
+    unsigned *slots = reinterpret_cast<unsigned *>(scr + kNoAllocTileWords);
+    unsigned *vol = slots + kBoxSlots;
+    const double one[3] = {1.0, 1.0, 1.0};
+    // every tile's box (written tile by tile, nothing to clear); the slots
+    // are cleared by a kernel inside sl_box_volume
+    sl_box_volume<T>(g, order, disp, 1.0, one, vol, slots, tiles, s);
+    // LDS sized for the largest box the launch allows; larger tiles gather
+    // from global memory, as in every transport launch
+    interp_field<T, T, T>(g, order, f, disp, out, SlBox(INT_MAX, tiles), s);
+}
+}  // namespace
+
+const char *noalloc_error() { return g_noalloc_err.c_str(); }
+
 }  // namespace mireg
+
+extern "C" int mireg_interp_noalloc(const int n[3], int order, int dtype, const void *f, const void *disp,
+                                    void *out, void *stream) {
+    using namespace mireg;
+    if (!n || !f || !disp || !out) return noalloc_fail(MIREG_E_ARG, "null pointer");
+    for (int a = 0; a < 3; ++a)
+        if (!noalloc_axis(n[a]))
+            return noalloc_fail(MIREG_E_SHAPE, "grid axis " + std::to_string(n[a]) +
+                                                   " unsupported (powers of two 8..512, or 48, 80, 96, 160)");
+    if (order != 1 && order != 3) return noalloc_fail(MIREG_E_ARG, "interpolation order must be 1 or 3");
+    if (dtype != MIREG_F32 && dtype != MIREG_F64) return noalloc_fail(MIREG_E_ARG, "dtype must be F32 or F64");
+    Grid g{};
+    g.n1 = n[0];
+    g.n2 = n[1];
+    g.n3 = n[2];
+    g.k3 = n[2] / 2 + 1;
+    g.N = (long long)n[0] * n[1] * n[2];
+    g.NS = (long long)n[0] * n[1] * g.k3;
+    g.lds_cap = INT_MAX;
+    g.sl_tile = TILE_8x8x16;
+    const long long need = sl_box_words(g);
+    if (need > kNoAllocTileWords)
+        return noalloc_fail(MIREG_E_SHAPE, "grid needs " + std::to_string(need) + " box words, scratch holds " +
+                                               std::to_string(kNoAllocTileWords));
+    int *scr = nullptr;
+    int rc = scratch_ptr(&scr);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == MIREG_F32)
+        interp_noalloc<float>(g, order, static_cast<const float *>(f), static_cast<const float *>(disp),
+                              static_cast<float *>(out), scr, s);
+    else
+        interp_noalloc<double>(g, order, static_cast<const double *>(f), static_cast<const double *>(disp),
+                               static_cast<double *>(out), scr, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return noalloc_fail(MIREG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return MIREG_OK;
+}

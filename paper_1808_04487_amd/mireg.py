@@ -102,6 +102,7 @@ SIGNATURES = {
     "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
     "mireg_timers_read": ([_vp, ctypes.POINTER(Timers), ctypes.c_int], ctypes.c_int),
+    "mireg_interp_noalloc": ([ctypes.c_int * 3, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
 }
 
 _lib = None
@@ -301,3 +302,26 @@ class Context:
         t = Timers()
         self._check(self.lib.mireg_timers_read(self.h, ctypes.byref(t), int(bool(reset))))
         return {"fft_ms": t.fft_ms, "interp_ms": t.interp_ms, "other_ms": t.other_ms, "launches": t.launches}
+
+
+def interp_noalloc(f, disp, out, order=3):
+    """out = I[f](x + disp) through the allocation-free entry point (no
+    context; f, disp, out contiguous CUDA tensors of one dtype, shapes
+    [n1, n2, n3], [3, n1, n2, n3], [n1, n2, n3]); enqueued on the current
+    torch stream, not synchronised."""
+    lib = load_library()
+    n = tuple(f.shape)
+    if len(n) != 3 or tuple(disp.shape) != (3,) + n or tuple(out.shape) != n:
+        raise ValueError("shapes must be [n1, n2, n3], [3, n1, n2, n3], [n1, n2, n3]")
+    if not (f.dtype == disp.dtype == out.dtype) or f.dtype not in (torch.float32, torch.float64):
+        raise ValueError("f, disp and out must share dtype float32 or float64")
+    for t in (f, disp, out):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("tensors must be contiguous CUDA tensors")
+    code = F32 if f.dtype == torch.float32 else F64
+    stream = torch.cuda.current_stream(f.device).cuda_stream
+    rc = lib.mireg_interp_noalloc((ctypes.c_int * 3)(*n), int(order), code, f.data_ptr(), disp.data_ptr(),
+                                  out.data_ptr(), stream)
+    if rc != OK:
+        raise MiregError(rc, lib.mireg_last_error(None).decode())
+    return out
