@@ -25,7 +25,9 @@ preconditioner (coarse grid 128^3, nested CG to kappa times the PCG
 tolerance; kappa 0.1 as in the paper, and 0.5).
 "batched" solves the uneven batch -- 16 pairs at 64^3, 16 at 96^3, 12 at
 128^3 and 4 at 160^3 -- with four concurrent streams, graph-captured matvecs
-and autotuned tiles, against one stream without either.
+and autotuned tiles, against one stream without either, and in lockstep
+(all 48 pairs in one mireg batch: one launch per transport step across the
+pairs, one launch per Krylov pass per grid size).
 "warm_start" compares solves of held-out 128^3 pairs from v = 0 and from the
 trained network's prediction (paper_1808_04487_amd/weights) to the same
 absolute gradient tolerance.  "analytic_32" gives the time to tolerance of
@@ -268,9 +270,10 @@ def precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, plain):
     }
 
 
-def batched_eval(args, torch):
+def batched_eval(args, torch, mireg):
     """Uneven batch: sequential (one stream, eager) vs batched (4 streams,
-    graphs, autotuner); each configuration runs once untimed first."""
+    graphs, autotuner) vs lockstep (all pairs in one batch: one launch per
+    transport step across them); each configuration runs once untimed first."""
     from paper_1808_04487_amd import batch
 
     sizes = batch.UNEVEN_BATCH
@@ -290,6 +293,27 @@ def batched_eval(args, torch):
                                                                    for r, p in zip(res, pairs)) / wall, 1)}
         log(args, "%s: %.3f s for %d pairs" % (key, wall, len(sizes)))
     out["speedup"] = round(out["sequential"]["wall_s"] / out["batched"]["wall_s"], 3)
+    # lockstep: one context per pair on one stream; each transport step of the
+    # Hessian matvec is one launch across all running pairs, each Krylov pass
+    # one launch per grid size, one PCG read-back per iteration for all
+    ctxs = [mireg.Context(tuple(p[0].shape), dtype=torch.float32, **batch.SOLVER) for p in pairs]
+    for c, (mT, mR) in zip(ctxs, pairs):
+        c.set_images(mT, mR)
+    B = mireg.Batch(ctxs)
+    B.gn_solve(grad_rtol=5e-2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, reps = B.gn_solve(grad_rtol=5e-2)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    B.close()
+    for c in ctxs:
+        c.close()
+    out["lockstep"] = {"wall_s": round(wall, 4), "pairs_per_s": round(len(sizes) / wall, 2),
+                       "matvecs": sum(r["matvecs"] for r in reps),
+                       "points_matvecs_per_s": round(sum(r["matvecs"] * p[0].numel()
+                                                         for r, p in zip(reps, pairs)) / wall, 1)}
+    log(args, "lockstep: %.3f s for %d pairs" % (wall, len(sizes)))
     return out
 
 
@@ -421,7 +445,7 @@ def main():
     bat = None
     if not args.no_batched:
         log(args, "batched uneven solves")
-        bat = batched_eval(args, torch)
+        bat = batched_eval(args, torch, mireg)
 
     warm = None
     if not args.no_warm_start:

@@ -219,6 +219,37 @@ int mireg_pcg_solve(mireg_ctx *ctx, const void *rhs, void *x, double rtol, int m
 int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts,
                    mireg_report *rep);
 
+/* Batched solves (not in the paper: many registration problems on one GPU).
+ * A batch groups n >= 1 distinct contexts of any supported grid sizes that
+ * share the dtype, nt, the interpolation order, the stream, the transport
+ * tile shape (mireg_autotune changes it) and the LDS switch; it does not own
+ * them (destroy the batch first).  Each problem keeps its context and
+ * follows its single-problem algorithm step for step -- results equal those
+ * of mireg_pcg_solve / mireg_gn_solve on each context alone up to rounding
+ * (the multi-problem kernels are separate compilations whose operation
+ * contraction may differ; FP64 iterates measured identical) -- but every
+ * transport step of the Hessian matvec (incremental state and adjoint
+ * sweeps) runs as one launch across all problems still iterating, each
+ * Krylov pass as one launch per grid size, and the PCG iteration reads its
+ * scalars back once for all of them.  Only the spectral preconditioner.  Returns MIREG_E_ARG for mismatched contexts,
+ * MIREG_E_NOMEM if its step tables cannot be allocated. */
+typedef struct mireg_batch mireg_batch;
+int mireg_batch_create(mireg_ctx *const *ctxs, int n, mireg_batch **out);
+int mireg_batch_destroy(mireg_batch *b);
+const char *mireg_batch_last_error(const mireg_batch *b);
+/* Lockstep PCG: for every problem i, H_i x_i = rhs_i at its current v, as
+ * mireg_pcg_solve does it (rtol[i], the common maxit); rhs, x: n device
+ * pointers; rtol: n host doubles; iters, relres, status: n host values each
+ * (may be NULL).  Synchronises the stream. */
+int mireg_batch_pcg_solve(mireg_batch *b, const void *const *rhs, void *const *x, const double *rtol, int maxit,
+                          int *iters, double *relres, int *status);
+/* Lockstep GN-Krylov: mireg_gn_solve for every problem (v_inout: n device
+ * pointers, warm starts or zeros, overwritten by the final velocities; reps:
+ * n reports, may be NULL; seconds is the batch's wall time).  The Newton
+ * steps of the problems that have not stopped form one batched PCG; the
+ * objectives, gradients and line searches run problem by problem. */
+int mireg_batch_gn_solve(mireg_batch *b, void *const *v_inout, const mireg_solve_opts *opts, mireg_report *reps);
+
 /* Individual operators for tests and input preparation.  `in` and `out`
  * are device fields of the context dtype; `arg` is an op parameter. */
 enum {

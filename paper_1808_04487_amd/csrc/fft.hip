@@ -39,10 +39,14 @@ constexpr int col_threads() {
 
 // SI: element type of the real input (FP32 input of an FP64 transform is
 // widened at the load)
-template <typename T, int M, typename SI = T>
+// tab (device, or null): problem blockIdx.z's (src, dst) pair at
+// tab[2 z], tab[2 z + 1] in place of src and dst (several problems of one
+// grid size in one launch); the same convention in the other passes.
+template <typename T, int M, typename SI = T, bool TAB = false>
 __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtrs dst,
                                                          long long lines,
-                                                         const cx<T> *__restrict__ tw) {
+                                                         const cx<T> *__restrict__ tw,
+                                                         const FieldPtrs *__restrict__ tab) {
     using S = FftShape<T, M, 0, line_threads<T, M>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
@@ -50,9 +54,11 @@ __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtr
     const int t = threadIdx.x % TPC, c = threadIdx.x / TPC;
     const long long line = (long long)blockIdx.x * W + c;
     const bool ok = line < lines;
-    cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * (M + 1);
+    void *dp = TAB ? tab[2 * blockIdx.z + 1].p[blockIdx.y] : dst.p[blockIdx.y];
+    const void *sp = TAB ? tab[2 * blockIdx.z].p[blockIdx.y] : src.p[blockIdx.y];
+    cx<T> *out = reinterpret_cast<cx<T> *>(dp) + line * (M + 1);
     cx<T> reg[EPT];
-    const cx<SI> *in = reinterpret_cast<const cx<SI> *>(src.p[blockIdx.y]) + line * M;
+    const cx<SI> *in = reinterpret_cast<const cx<SI> *>(sp) + line * M;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const cx<SI> z = ok ? in[t + TPC * e] : make_cx<SI>(0, 0);
@@ -80,10 +86,11 @@ __global__ __launch_bounds__(kLineThreads) void k_r2c_x3(FieldPtrs src, FieldPtr
     }
 }
 
-template <typename T, int M>
+template <typename T, int M, bool TAB = false>
 __global__ __launch_bounds__(kLineThreads) void k_c2r_x3(FieldPtrs src, FieldPtrs dst,
                                                          long long lines,
-                                                         const cx<T> *__restrict__ tw) {
+                                                         const cx<T> *__restrict__ tw,
+                                                         const FieldPtrs *__restrict__ tab) {
     using S = FftShape<T, M, 0, line_threads<T, M>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutRows<W, M>;
@@ -91,8 +98,10 @@ __global__ __launch_bounds__(kLineThreads) void k_c2r_x3(FieldPtrs src, FieldPtr
     const int t = threadIdx.x % TPC, c = threadIdx.x / TPC;
     const long long line = (long long)blockIdx.x * W + c;
     const bool ok = line < lines;
-    const cx<T> *in = reinterpret_cast<const cx<T> *>(src.p[blockIdx.y]) + line * (M + 1);
-    cx<T> *out = reinterpret_cast<cx<T> *>(dst.p[blockIdx.y]) + line * M;
+    const void *sp = TAB ? tab[2 * blockIdx.z].p[blockIdx.y] : src.p[blockIdx.y];
+    void *dp = TAB ? tab[2 * blockIdx.z + 1].p[blockIdx.y] : dst.p[blockIdx.y];
+    const cx<T> *in = reinterpret_cast<const cx<T> *>(sp) + line * (M + 1);
+    cx<T> *out = reinterpret_cast<cx<T> *>(dp) + line * M;
     cx<T> reg[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -133,10 +142,11 @@ __device__ __forceinline__ void xcd_block(int &bx, int &by) {
     by = g / (int)gridDim.x;
 }
 
-template <typename T, int L, int DIR>
+template <typename T, int L, int DIR, bool TAB = false>
 __global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long Q, long long inner,
                                                           long long ostride, long long pstride,
-                                                          const cx<T> *__restrict__ tw) {
+                                                          const cx<T> *__restrict__ tw,
+                                                          const FieldPtrs *__restrict__ tab) {
     using S = FftShape<T, L, 0, col_threads<T, L, 0>()>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(kColThreads) void k_c2c_cols(FieldPtrs f, long long
     const long long q = (long long)bx * W + c;
     const bool ok = q < Q;
     const long long base = ok ? (q / inner) * ostride + (q % inner) : 0;
-    cx<T> *p = reinterpret_cast<cx<T> *>(f.p[by]) + base;
+    cx<T> *p = reinterpret_cast<cx<T> *>(TAB ? tab[blockIdx.z].p[by] : f.p[by]) + base;
     cx<T> reg[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) reg[e] = ok ? p[(long long)(t + TPC * e) * pstride] : make_cx<T>(0, 0);
@@ -377,7 +387,16 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
 }
 
 // out[0] = sum of n partials in a fixed order (one workgroup)
-__global__ __launch_bounds__(256) void k_sum_partials(int n, const double *__restrict__ part, double *__restrict__ out) {
+// out[0] = sum of part[0 .. n-1]; with jobs (device, or null), job
+// blockIdx.x's (part, out) in their place.
+struct SumJob {
+    const double *part;
+    double *out;
+};
+__global__ __launch_bounds__(256) void k_sum_partials(int n, const double *__restrict__ part_arg,
+                                                      double *__restrict__ out_arg, const SumJob *__restrict__ jobs) {
+    const double *part = jobs ? jobs[blockIdx.x].part : part_arg;
+    double *out = jobs ? jobs[blockIdx.x].out : out_arg;
     __shared__ double sh[4];
     double s = 0;
     for (int i = threadIdx.x; i < n; i += 256) s += part[i];
@@ -406,6 +425,8 @@ struct KrylovPtrs {
     void *o[3];        // spectral output (read first in KP_DIR; read only, the old direction, in KP_INV)
     void *x[3];        // iterate updated with the old direction (KP_DIR with KF_XUPD)
     const double *alpha;  // device step length of the KF_XUPD updates
+    double mu;            // KP_DIR's mu, when read from a table
+    double *red;          // KP_HESS's reduction partials, when read from a table
 };
 
 // x1 passes of the Krylov iteration (flags: KF_*, kernels.hpp):
@@ -439,10 +460,15 @@ constexpr int krylov_bound() {
 }
 // SA: element type of the spectral operand a_in of KP_HESS (an FP64
 // spectrum read by an FP32 pass is rounded at the load)
-template <typename T, int L, int PASS, typename SA = T>
-__global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs f, long long Q, OpConst<T> oc,
-                                                                      T mu, int flags,
-                                                                      const cx<T> *__restrict__ tw) {
+template <typename T, int L, int PASS, typename SA = T, bool TAB = false>
+__global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs farg, long long Q, OpConst<T> oc,
+                                                                      T mu_arg, int flags,
+                                                                      const cx<T> *__restrict__ tw,
+                                                                      const KrylovPtrs *__restrict__ tab) {
+    // problem blockIdx.z's operands (its mu and reduction partials) from tab
+    const KrylovPtrs f = TAB ? tab[blockIdx.z] : farg;
+    const T mu = TAB ? (T)f.mu : mu_arg;
+    double *const red = TAB ? f.red : oc.red;
     const bool first = flags & KF_FIRST, sqrt_scaled = flags & KF_SQRT, zraw = flags & KF_ZRAW;
     const bool xupd = flags & KF_XUPD;
     const T alpha = xupd ? (T)*f.alpha : (T)0;
@@ -571,7 +597,7 @@ __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs
         }
     }
     if constexpr (PASS == KP_HESS) {
-        if (oc.red) {
+        if (red) {
             __shared__ double red_sh[NT / 64];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
@@ -580,7 +606,7 @@ __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs
             if (threadIdx.x == 0) {
                 double tot = 0;
                 for (int w = 0; w < NT / 64; ++w) tot += red_sh[w];
-                oc.red[blockIdx.x] = tot * (double)oc.norm;
+                red[blockIdx.x] = tot * (double)oc.norm;
             }
         }
     }
@@ -599,10 +625,21 @@ struct KrylovSet {
 // then per-workgroup partials of sum_x r . M^{-1} r (part[b]) and
 // sum_x r . r (part[nb + b]) from r.  Grid-stride over the NS modes with a
 // fixed grid, so the sums are reproducible.
+// One problem of a multi-problem k_krylov_update (problem blockIdx.y).
 template <typename T>
+struct KrylovUpd {
+    KrylovSet<T> v;
+    double *res, *part;
+};
+
+template <typename T, bool TAB = false>
 __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int n2, int n3, int k3, int reg,
-                                                       T beta_v, int update, int num, double *res, KrylovSet<T> v,
-                                                       double norm, double *__restrict__ part) {
+                                                       T beta_v, int update, int num, double *res_arg,
+                                                       KrylovSet<T> v_arg, double norm, double *__restrict__ part_arg,
+                                                       const KrylovUpd<T> *__restrict__ tab) {
+    const KrylovSet<T> v = TAB ? tab[blockIdx.y].v : v_arg;
+    double *res = TAB ? tab[blockIdx.y].res : res_arg;
+    double *part = TAB ? tab[blockIdx.y].part : part_arg;
     cx<T> *const *r = v.p;
     const cx<T> *const *h = v.p + 3;
     const double den = update ? res[0] : 0.0, step = update ? res[num] / den : 0.0;
@@ -686,15 +723,18 @@ __global__ __launch_bounds__(256) void k_krylov_update(unsigned NS, int n1, int 
 
 template <typename T, typename SI = T>
 static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
-                       hipStream_t s) {
+                       hipStream_t s, const FieldPtrs *tab = nullptr, int np = 1) {
     const long long lines = (long long)g.n1 * g.n2;
-    HookScope hs(K_R2C, (double)nf * (sizeof(SI) * g.N + 2.0 * sizeof(T) * g.NS));
+    HookScope hs(K_R2C, (double)np * nf * (sizeof(SI) * g.N + 2.0 * sizeof(T) * g.NS));
 #define MIREG_L(M)                                                                                     \
     {                                                                                                  \
         constexpr int NT = line_threads<T, M>();                                                       \
         constexpr int W = FftShape<T, M, 0, NT>::W;                                                    \
-        dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_r2c_x3<T, M, SI>), grid, dim3(NT), 0, s, src, dst, lines, tw);           \
+        dim3 grid((unsigned)((lines + W - 1) / W), nf, np);                                            \
+        if (tab)                                                                                       \
+            hipLaunchKernelGGL((k_r2c_x3<T, M, SI, true>), grid, dim3(NT), 0, s, src, dst, lines, tw, tab); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_r2c_x3<T, M, SI>), grid, dim3(NT), 0, s, src, dst, lines, tw, tab);  \
     }
     MIREG_SWITCH_LINE(g.n3 / 2, MIREG_L)
 #undef MIREG_L
@@ -702,32 +742,40 @@ static void launch_r2c(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, cons
 
 template <typename T>
 static void launch_c2r(const Grid &g, FieldPtrs src, FieldPtrs dst, int nf, const cx<T> *tw,
-                       hipStream_t s) {
+                       hipStream_t s, const FieldPtrs *tab = nullptr, int np = 1) {
     const long long lines = (long long)g.n1 * g.n2;
-    HookScope hs(K_C2R, (double)nf * sizeof(T) * (g.N + 2.0 * g.NS));
+    HookScope hs(K_C2R, (double)np * nf * sizeof(T) * (g.N + 2.0 * g.NS));
 #define MIREG_L(M)                                                                                     \
     {                                                                                                  \
         constexpr int NT = line_threads<T, M>();                                                       \
         constexpr int W = FftShape<T, M, 0, NT>::W;                                                    \
-        dim3 grid((unsigned)((lines + W - 1) / W), nf);                                                \
-        hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(NT), 0, s, src, dst, lines, tw);               \
+        dim3 grid((unsigned)((lines + W - 1) / W), nf, np);                                            \
+        if (tab)                                                                                       \
+            hipLaunchKernelGGL((k_c2r_x3<T, M, true>), grid, dim3(NT), 0, s, src, dst, lines, tw, tab); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_c2r_x3<T, M>), grid, dim3(NT), 0, s, src, dst, lines, tw, tab);      \
     }
     MIREG_SWITCH_LINE(g.n3 / 2, MIREG_L)
 #undef MIREG_L
 }
 
 template <typename T, int DIR>
-static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipStream_t s) {
+static void launch_x2(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, hipStream_t s,
+                      const FieldPtrs *tab = nullptr, int np = 1) {
     const long long Q = (long long)g.n1 * g.k3, inner = g.k3, ostride = (long long)g.n2 * g.k3,
                     pstride = g.k3;
-    HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)nf * sizeof(T) * 4.0 * g.NS);
+    HookScope hs(DIR < 0 ? K_C2C_FWD : K_C2C_INV, (double)np * nf * sizeof(T) * 4.0 * g.NS);
 #define MIREG_L(L)                                                                           \
     {                                                                                        \
         constexpr int NT = col_threads<T, L, 0>();                                           \
         constexpr int W = FftShape<T, L, 0, NT>::W;                                          \
-        dim3 grid((unsigned)((Q + W - 1) / W), nf);                                          \
-        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, inner,       \
-                           ostride, pstride, tw);                                            \
+        dim3 grid((unsigned)((Q + W - 1) / W), nf, np);                                      \
+        if (tab)                                                                             \
+            hipLaunchKernelGGL((k_c2c_cols<T, L, DIR, true>), grid, dim3(NT), 0, s, f, Q, inner, \
+                               ostride, pstride, tw, tab);                                   \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, inner,   \
+                               ostride, pstride, tw, tab);                                   \
     }
     MIREG_SWITCH_COL(g.n2, MIREG_L)
 #undef MIREG_L
@@ -791,7 +839,7 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
     }
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out, nullptr);
     }
     launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
     launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
@@ -826,7 +874,8 @@ static void launch_x1_fft(const Grid &g, FieldPtrs f, int nf, const cx<T> *tw, h
         constexpr int NT = col_threads<T, L, 0>();                                                          \
         constexpr int W = FftShape<T, L, 0, NT>::W;                                                         \
         dim3 grid((unsigned)((Q + W - 1) / W), nf);                                                         \
-        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, Q, 0LL, Q, tw);           \
+        hipLaunchKernelGGL((k_c2c_cols<T, L, DIR>), grid, dim3(NT), 0, s, f, Q, Q, 0LL, Q, tw,            \
+                           (const FieldPtrs *)nullptr);                                                     \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -868,7 +917,8 @@ template void spectral_resample<double>(const Grid &, const Grid &, int, const d
 // ---- Krylov host passes ----
 template <typename T, int PASS, typename SA = T>
 static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T> &oc, T mu, int flags,
-                             const cx<T> *tw, hipStream_t s, int *blocks) {
+                             const cx<T> *tw, hipStream_t s, int *blocks, const KrylovPtrs *tab = nullptr,
+                             int np = 1) {
     const long long Q = (long long)g.n2 * g.k3;
     // operands moved per launch (complex modes): FWD 3 + 3, HESS 3 + 3 + 3, DIR 3 + 3 + 3 + 3, INV 3 + 3;
     // KF_XUPD adds x read and written (DIR) or the old direction read (INV)
@@ -876,14 +926,19 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
     const double fields = PASS == KP_HESS ? 6.0 + 3.0 * sizeof(SA) / sizeof(T)
                           : PASS == KP_DIR ? (xupd ? 18.0 : 12.0)
                                            : (PASS == KP_INV && xupd ? 9.0 : 6.0);
-    HookScope hs(K_X1_KRYLOV, fields * 2.0 * sizeof(T) * g.NS);
+    HookScope hs(K_X1_KRYLOV, np * fields * 2.0 * sizeof(T) * g.NS);
 #define MIREG_L(L)                                                                                       \
     {                                                                                                    \
         constexpr int NT = krylov_threads<T, L>();                                                       \
         constexpr int W = FftShape<T, L, 1, NT>::W;                                                      \
-        dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3);                                 \
+        dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3, np);                             \
         if (blocks) *blocks = (int)grid.x;                                                               \
-        hipLaunchKernelGGL((k_x1_krylov<T, L, PASS, SA>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw); \
+        if (tab)                                                                                         \
+            hipLaunchKernelGGL((k_x1_krylov<T, L, PASS, SA, true>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, \
+                               tw, tab);                                                                 \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_x1_krylov<T, L, PASS, SA>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw, \
+                               tab);                                                                     \
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L
@@ -946,7 +1001,7 @@ void krylov_hessian(const Grid &g, const T *const *b, const cx<T> *const *shat, 
     launch_x1_krylov<T, KP_HESS>(g, kp, oc, (T)0, flags & KF_SQRT, tw.t[0], s, &blocks);
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out, nullptr);
     }
 }
 
@@ -1039,11 +1094,122 @@ void krylov_update(const Grid &g, bool update, int num, double *res, cx<T> *cons
         HookScope hs(K_KRYLOV_UPDATE, (update ? 9.0 : 3.0) * 2.0 * sizeof(T) * g.NS);
         hipLaunchKernelGGL((k_krylov_update<T>), dim3(nb), dim3(256), 0, s, (unsigned)g.NS, g.n1, g.n2, g.n3, g.k3,
                            sp.reg, (T)sp.beta_v, update ? 1 : 0, num, res, v,
-                           1.0 / ((double)g.n1 * g.n2 * g.n3), partials);
+                           1.0 / ((double)g.n1 * g.n2 * g.n3), partials, (const KrylovUpd<T> *)nullptr);
     }
     HookScope hs(K_REDUCE, 16.0 * nb);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials, res + 1);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, res + 2);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials, res + 1, nullptr);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partials + nb, res + 2, nullptr);
+}
+
+// ---- the Krylov passes of several problems of one grid size ----
+template <typename T>
+bool krylov_hessian_multi(const Grid &g, int np, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat,
+                          cx<T> *const *work, double *const *red, double *const *red_out, const Twiddles<T> &tw,
+                          const SpecParams &sp, TabArena &ar, hipStream_t s) {
+    const FieldPtrs *d_r2c, *d_x2;
+    const KrylovPtrs *d_x1;
+    const SumJob *d_sum;
+    FieldPtrs *r2c = ar.alloc(2 * np, &d_r2c), *x2 = ar.alloc(np, &d_x2);
+    KrylovPtrs *x1 = ar.alloc(np, &d_x1);
+    SumJob *sum = ar.alloc(np, &d_sum);
+    if (!r2c || !x2 || !x1 || !sum) return false;
+    for (int p = 0; p < np; ++p) {
+        r2c[2 * p] = FieldPtrs{};
+        r2c[2 * p + 1] = FieldPtrs{};
+        x1[p] = KrylovPtrs{};
+        for (int a = 0; a < 3; ++a) {
+            void *w = work[p] + (long long)a * g.NS;
+            r2c[2 * p].p[a] = const_cast<T *>(b[3 * p + a]);
+            r2c[2 * p + 1].p[a] = w;
+            x1[p].w[a] = w;
+            x1[p].a[a] = shat[3 * p + a];
+            x1[p].o[a] = hhat[3 * p + a];
+        }
+        x2[p] = r2c[2 * p + 1];
+        x1[p].red = red[p];
+        sum[p] = SumJob{red[p], red_out[p]};
+    }
+    ar.upload(s);
+    const FieldPtrs none{};
+    launch_r2c<T>(g, none, none, 3, tw.t[2], s, d_r2c, np);
+    launch_x2<T, -1>(g, none, 3, tw.t[1], s, d_x2, np);
+    OpConst<T> oc = krylov_const<T>(g, sp);
+    oc.red = red[0];  // the kernels take each problem's partials from the table
+    int blocks = 0;
+    launch_x1_krylov<T, KP_HESS>(g, KrylovPtrs{}, oc, (T)0, 0, tw.t[0], s, &blocks, d_x1, np);
+    HookScope hs(K_REDUCE, 8.0 * blocks * np);
+    hipLaunchKernelGGL(k_sum_partials, dim3(np), dim3(256), 0, s, blocks, nullptr, nullptr, d_sum);
+    return true;
+}
+
+template <typename T>
+bool krylov_update_multi(const Grid &g, int np, bool update, int num, double *const *res, cx<T> *const *rhat,
+                         const cx<T> *const *hhat, double *const *partials, const SpecParams &sp, TabArena &ar,
+                         hipStream_t s) {
+    constexpr int nb = kRedBlocks;
+    const KrylovUpd<T> *d_tab;
+    const SumJob *d_sum;
+    KrylovUpd<T> *tab = ar.alloc(np, &d_tab);
+    SumJob *sum = ar.alloc(2 * np, &d_sum);
+    if (!tab || !sum) return false;
+    for (int p = 0; p < np; ++p) {
+        for (int a = 0; a < 3; ++a) {
+            tab[p].v.p[a] = rhat[3 * p + a];
+            tab[p].v.p[3 + a] = const_cast<cx<T> *>(hhat[3 * p + a]);
+        }
+        for (int a = 6; a < 12; ++a) tab[p].v.p[a] = nullptr;
+        tab[p].res = res[p];
+        tab[p].part = partials[p];
+        sum[2 * p] = SumJob{partials[p], res[p] + 1};
+        sum[2 * p + 1] = SumJob{partials[p] + nb, res[p] + 2};
+    }
+    ar.upload(s);
+    {
+        HookScope hs(K_KRYLOV_UPDATE, (update ? 9.0 : 3.0) * 2.0 * sizeof(T) * g.NS * np);
+        hipLaunchKernelGGL((k_krylov_update<T, true>), dim3(nb, np), dim3(256), 0, s, (unsigned)g.NS, g.n1, g.n2, g.n3,
+                           g.k3, sp.reg, (T)sp.beta_v, update ? 1 : 0, num, nullptr, KrylovSet<T>{},
+                           1.0 / ((double)g.n1 * g.n2 * g.n3), nullptr, d_tab);
+    }
+    HookScope hs(K_REDUCE, 16.0 * nb * np);
+    hipLaunchKernelGGL(k_sum_partials, dim3(2 * np), dim3(256), 0, s, nb, nullptr, nullptr, d_sum);
+    return true;
+}
+
+template <typename T>
+bool krylov_direction_multi(const Grid &g, int np, const cx<T> *const *rhat, cx<T> *const *shat, const double *mu,
+                            int flags, cx<T> *const *xhat, const double *const *alpha, T *const *s_out,
+                            cx<T> *const *work, const Twiddles<T> &tw, const SpecParams &sp, TabArena &ar,
+                            hipStream_t s) {
+    const KrylovPtrs *d_x1;
+    const FieldPtrs *d_x2, *d_c2r;
+    KrylovPtrs *x1 = ar.alloc(np, &d_x1);
+    FieldPtrs *x2 = ar.alloc(np, &d_x2), *c2r = ar.alloc(2 * np, &d_c2r);
+    if (!x1 || !x2 || !c2r) return false;
+    const bool xupd = xhat && alpha && !(flags & KF_FIRST);
+    if (xupd) flags |= KF_XUPD;
+    for (int p = 0; p < np; ++p) {
+        x1[p] = KrylovPtrs{};
+        x2[p] = FieldPtrs{};
+        c2r[2 * p + 1] = FieldPtrs{};
+        for (int a = 0; a < 3; ++a) {
+            void *w = work[p] + (long long)a * g.NS;
+            x1[p].w[a] = w;
+            x1[p].a[a] = rhat[3 * p + a];
+            x1[p].o[a] = shat[3 * p + a];
+            x1[p].x[a] = xhat ? xhat[3 * p + a] : nullptr;
+            x2[p].p[a] = w;
+            c2r[2 * p + 1].p[a] = s_out[3 * p + a];
+        }
+        c2r[2 * p] = x2[p];
+        x1[p].alpha = alpha ? alpha[p] : nullptr;
+        x1[p].mu = mu ? mu[p] : 0.0;
+    }
+    ar.upload(s);
+    const FieldPtrs none{};
+    launch_x1_krylov<T, KP_DIR>(g, KrylovPtrs{}, krylov_const<T>(g, sp), (T)0, flags, tw.t[0], s, nullptr, d_x1, np);
+    launch_x2<T, +1>(g, none, 3, tw.t[1], s, d_x2, np);
+    launch_c2r<T>(g, none, none, 3, tw.t[2], s, d_c2r, np);
+    return true;
 }
 
 // ---- Two-level preconditioner on Krylov spectra (fine grid n, coarse n/2) ----
@@ -1158,7 +1324,7 @@ void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, co
                            partials);
     }
     HookScope hs(K_REDUCE, 8.0 * kRedBlocks);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, kRedBlocks, partials, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, kRedBlocks, partials, out, nullptr);
 }
 
 #define MIREG_KRYLOV(T)                                                                                          \
@@ -1177,7 +1343,17 @@ void twolevel_combine(const Grid &gf, const Grid &gc, const cx<T> *const *rf, co
     template void krylov_inverse<T>(const Grid &, const cx<T> *const *, const cx<T> *const *, const double *,     \
                                     T *const *, cx<T> *, const Twiddles<T> &, hipStream_t);                      \
     template void krylov_update<T>(const Grid &, bool, int, double *, cx<T> *const *, const cx<T> *const *,      \
-                                   const SpecParams &, double *, hipStream_t);
+                                   const SpecParams &, double *, hipStream_t);                                  \
+    template bool krylov_hessian_multi<T>(const Grid &, int, const T *const *, const cx<T> *const *,              \
+                                          cx<T> *const *, cx<T> *const *, double *const *, double *const *,       \
+                                          const Twiddles<T> &, const SpecParams &, TabArena &, hipStream_t);      \
+    template bool krylov_update_multi<T>(const Grid &, int, bool, int, double *const *, cx<T> *const *,            \
+                                         const cx<T> *const *, double *const *, const SpecParams &, TabArena &,   \
+                                         hipStream_t);                                                            \
+    template bool krylov_direction_multi<T>(const Grid &, int, const cx<T> *const *, cx<T> *const *,               \
+                                            const double *, int, cx<T> *const *, const double *const *,            \
+                                            T *const *, cx<T> *const *, const Twiddles<T> &, const SpecParams &,   \
+                                            TabArena &, hipStream_t);
 MIREG_KRYLOV(float)
 MIREG_KRYLOV(double)
 #undef MIREG_KRYLOV

@@ -138,6 +138,51 @@ template <typename T>
 void krylov_update(const Grid &g, bool update, int num, double *res, cx<T> *const *rhat, const cx<T> *const *hhat,
                    const SpecParams &sp, double *partials, hipStream_t s);
 
+// ---- the Krylov passes of several problems of one grid size ----
+// Pinned host and device staging for the launches' per-problem pointer
+// tables: alloc() hands out a chunk (host pointer; *dev its device twin),
+// upload() copies everything allocated since the last upload in one copy on
+// the stream.  The owner calls reset() only when every copy it issued has
+// completed (after a synchronisation of that stream).
+struct TabArena {
+    char *h = nullptr, *d = nullptr;
+    size_t cap = 0, off = 0, sent = 0;
+    bool overflow = false;
+    template <class E>
+    E *alloc(int n, const E **dev) {
+        const size_t a = (off + 255) / 256 * 256, b = a + sizeof(E) * (size_t)n;
+        if (b > cap) {
+            overflow = true;
+            return nullptr;
+        }
+        off = b;
+        *dev = reinterpret_cast<const E *>(d + a);
+        return reinterpret_cast<E *>(h + a);
+    }
+    void upload(hipStream_t s) {
+        if (off > sent) hipMemcpyAsync(d + sent, h + sent, off - sent, hipMemcpyHostToDevice, s);
+        sent = off;
+    }
+    void reset() { off = sent = 0; }
+};
+// For problems p < np (arrays of per-problem operands, three components each
+// where a vector is meant: index 3 p + a), exactly krylov_hessian (flags 0,
+// reduction into red[p] / red_out[p]), krylov_update and krylov_direction of
+// each problem, in one launch per pass.  tw: the grid's twiddles.
+template <typename T>
+bool krylov_hessian_multi(const Grid &g, int np, const T *const *b, const cx<T> *const *shat, cx<T> *const *hhat,
+                          cx<T> *const *work, double *const *red, double *const *red_out, const Twiddles<T> &tw,
+                          const SpecParams &sp, TabArena &ar, hipStream_t s);
+template <typename T>
+bool krylov_update_multi(const Grid &g, int np, bool update, int num, double *const *res, cx<T> *const *rhat,
+                         const cx<T> *const *hhat, double *const *partials, const SpecParams &sp, TabArena &ar,
+                         hipStream_t s);
+template <typename T>
+bool krylov_direction_multi(const Grid &g, int np, const cx<T> *const *rhat, cx<T> *const *shat, const double *mu,
+                            int flags, cx<T> *const *xhat, const double *const *alpha, T *const *s_out,
+                            cx<T> *const *work, const Twiddles<T> &tw, const SpecParams &sp, TabArena &ar,
+                            hipStream_t s);
+
 // Spectral resampling between two grids (each axis the same or half/double
 // the size): out = the trigonometric interpolant of in, truncated to the
 // modes both grids resolve below their Nyquist (|k_a| < min(n_a, m_a) / 2),
@@ -197,6 +242,31 @@ void adjoint_step(const Grid &g, int order, double dt, const S *lam_in, const T 
 template <typename T, typename S>
 void adjoint_step_accumulate(const Grid &g, int order, double dt, int nt, const S *lam, const T *d,
                              const T *Y, const T *gradm, T *b, SlBox box, hipStream_t s);
+// ---- batched GN matvec transport (several problems, one launch per step) ----
+// One problem's operands, as its context holds them: T fields gradm
+// ([nt+1][3][N]), vt, X, Y ([3][N]) and d; q (2 N) and lam ((nt+1) N) in the
+// storage type S; b ([3][N], T).  Every problem of a batch shares nt, the
+// interpolation order and the tile shape g.sl_tile.
+struct SlProblem {
+    Grid g;
+    const void *gradm, *vt, *X, *Y, *d;
+    void *q, *lam, *b;
+    SlBox boxX, boxY;
+};
+// Bytes of the step tables of a batch of nprob problems.
+template <typename T, typename S>
+size_t batch_table_bytes(int nprob, int nt);
+// Writes the step tables into htab (host, pinned) and copies them to dtab
+// (device) on s; htab must stay untouched until that copy has completed.
+template <typename T, typename S>
+void matvec_transport_tables(const SlProblem *pr, int nprob, int nt, void *htab, void *dtab, hipStream_t s);
+// The incremental state and adjoint sweeps of every problem (what
+// matvec_transport does for one): one launch per step across the problems,
+// each problem's results those of its own launches.  htab/dtab: the tables
+// above, for the same problems.
+template <typename T, typename S>
+void matvec_transport_batch(const SlProblem *pr, int nprob, int order, int nt, const void *htab, const void *dtab,
+                            hipStream_t s);
 // Incremental state: q0 = -dt/2 grad m^0 . vt
 template <typename T, typename S>
 void incstate_init(const Grid &g, double dt, const T *gradm0, const T *vt, S *q, hipStream_t s);

@@ -15,6 +15,7 @@
 #include <climits>
 #include <cstring>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -1290,6 +1291,481 @@ struct HookGuard {
 }  // namespace
 
 // ===========================================================================
+// Batched solves: several problems of any supported sizes in lockstep (not in
+// the paper; many registration pairs on one GPU).  Every problem keeps its
+// own context and follows exactly its single-problem arithmetic; what the
+// batch shares is the launch: each transport step of the Hessian matvec runs
+// once across all running problems (k_sl_multi over their tiles numbered one
+// after the other), and the per-iteration host read-back of the PCG scalars
+// is one synchronisation for all of them.
+// ===========================================================================
+struct mireg_batch {
+    std::vector<mireg_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    void *htab = nullptr;  // pinned host copy of the step tables
+    void *dtab = nullptr;  // device step tables
+    hipEvent_t tab_done = nullptr;  // the last table upload has completed after this event
+    bool tab_pending = false;
+    mireg::TabArena arena;  // pointer tables of the multi-problem Krylov passes
+    std::string err;
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+namespace {
+
+// nres results of every listed problem to its host mirror: the copies are
+// enqueued first, then one synchronisation of the common stream.
+int batch_readback(mireg_batch *B, const std::vector<int> &idx, int nres) {
+    for (int i : idx) {
+        mireg_ctx *c = B->ctx[i];
+        hipError_t e = hipMemcpyAsync(c->hres, c->dres, nres * sizeof(double), hipMemcpyDeviceToHost, B->stream);
+        if (e != hipSuccess) return B->fail(MIREG_E_HIP, "read-back: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return B->fail(MIREG_E_HIP, "read-back: %s", hipGetErrorString(e));
+    return MIREG_OK;
+}
+
+// Step tables of the batched matvec transport for the listed problems (their
+// PCG direction, vector 2, as the transported increment).
+template <typename T, typename S>
+int batch_tables(mireg_batch *B, const std::vector<int> &idx, std::vector<SlProblem> &pr) {
+    pr.clear();
+    for (int i : idx) {
+        mireg_ctx *c = B->ctx[i];
+        SlProblem q;
+        q.g = c->g;
+        q.gradm = c->gradm;
+        q.vt = c->vec<T>(2);
+        q.X = c->X;
+        q.Y = c->Y;
+        q.d = c->d;
+        q.q = c->q;
+        q.lam = c->lam;
+        q.b = c->b;
+        q.boxX = c->box_X;
+        q.boxY = c->box_Y;
+        pr.push_back(q);
+    }
+    if (pr.empty()) return MIREG_OK;
+    if (B->tab_pending) {  // the host tables are rewritten only after their last upload
+        hipError_t e = hipEventSynchronize(B->tab_done);
+        if (e != hipSuccess) return B->fail(MIREG_E_HIP, "table upload: %s", hipGetErrorString(e));
+    }
+    matvec_transport_tables<T, S>(pr.data(), (int)pr.size(), B->ctx[0]->p.nt, B->htab, B->dtab, B->stream);
+    hipError_t e = hipEventRecord(B->tab_done, B->stream);
+    if (e != hipSuccess) return B->fail(MIREG_E_HIP, "table upload: %s", hipGetErrorString(e));
+    B->tab_pending = true;
+    return MIREG_OK;
+}
+
+int batch_ctx_error(mireg_batch *B, mireg_ctx *c, int rc) {
+    return B->fail(rc, "%s", c->err.c_str());
+}
+
+// Problems of one grid size and one regularisation share the Krylov
+// passes' launches: key of a problem's class.
+std::tuple<int, int, int, int, int, double, double> krylov_class(const mireg_ctx *c) {
+    return std::make_tuple(c->g.n1, c->g.n2, c->g.n3, c->p.reg, c->p.div, c->p.beta_v, c->p.beta_w);
+}
+
+// Lockstep PCG (the spectral preconditioner; the iteration of
+// impl_pcg_spectral, problem by problem) for the problems idx: H_i x_i =
+// rhs_i to rtol[k] (k the position in idx), at most maxit iterations.  Per
+// iteration: one launch per transport step across the running problems, one
+// launch per Krylov pass per class of problems of one grid size, one
+// read-back.
+template <typename T, typename S>
+int batch_pcg(mireg_batch *B, const std::vector<int> &idx, const T *const *rhs, T *const *x, const double *rtol,
+              int maxit, int *iters, double *relres, int *status, int *matvecs) {
+    struct Run {
+        double r0 = 0, rz = 0, rnorm = 0, mu = 0;
+        int it = 0, mv = 0, st = MIREG_CONVERGED_REL;
+        bool x_is_s = false, pending = false;
+    };
+    const int n = (int)idx.size();
+    std::vector<Run> run(n);
+    TabArena &ar = B->arena;
+    int rc;
+    // positions k of idx grouped by Krylov class, in order of first appearance
+    std::vector<std::vector<int>> classes;
+    {
+        std::vector<std::tuple<int, int, int, int, int, double, double>> keys;
+        for (int k = 0; k < n; ++k) {
+            const auto key = krylov_class(B->ctx[idx[k]]);
+            size_t c = 0;
+            while (c < keys.size() && keys[c] != key) ++c;
+            if (c == keys.size()) {
+                keys.push_back(key);
+                classes.emplace_back();
+            }
+            classes[c].push_back(k);
+        }
+    }
+    // the members of the class listed in `ks` that `sel` keeps
+    auto members = [&](const std::vector<int> &ks, const std::vector<char> &sel) {
+        std::vector<int> out;
+        for (int k : ks)
+            if (sel[k]) out.push_back(k);
+        return out;
+    };
+    // one class's multi-problem passes; operand arrays built per call
+    auto hessian_update = [&](const std::vector<int> &ks, bool update, bool hess) -> int {
+        if (ks.empty()) return MIREG_OK;
+        const int np = (int)ks.size();
+        mireg_ctx *c0 = B->ctx[idx[ks[0]]];
+        std::vector<const T *> b(3 * np);
+        std::vector<const cx<T> *> sh(3 * np), hhc(3 * np);
+        std::vector<cx<T> *> hh(3 * np), rh(3 * np), work(np);
+        std::vector<double *> red(np), rout(np), res(np), part(np);
+        for (int j = 0; j < np; ++j) {
+            mireg_ctx *c = B->ctx[idx[ks[j]]];
+            const long long N = c->N();
+            const T *bb = c->f<T>(c->b);
+            for (int a = 0; a < 3; ++a) {
+                b[3 * j + a] = bb + a * N;
+                sh[3 * j + a] = c->khat<T>(KV_S, a);
+                hh[3 * j + a] = c->khat<T>(KV_H, a);
+                hhc[3 * j + a] = hh[3 * j + a];
+                rh[3 * j + a] = c->khat<T>(KV_R, a);
+            }
+            work[j] = static_cast<cx<T> *>(c->spec);
+            red[j] = c->xpart;
+            rout[j] = c->dres;
+            res[j] = c->dres;
+            part[j] = c->partials;
+        }
+        const SpecParams sp = spec_params<T>(c0);
+        bool ok = true;
+        if (hess) {
+            Phase ph(c0, 0);
+            ok = krylov_hessian_multi<T>(c0->g, np, b.data(), sh.data(), hh.data(), work.data(), red.data(),
+                                         rout.data(), twiddles<T>(c0), sp, ar, B->stream);
+        }
+        if (ok) {
+            Phase ph(c0, 2);
+            ok = krylov_update_multi<T>(c0->g, np, update, 1, res.data(), rh.data(), hhc.data(), part.data(), sp, ar,
+                                        B->stream);
+        }
+        return ok ? MIREG_OK : B->fail(MIREG_E_NOMEM, "table arena exhausted");
+    };
+    auto direction = [&](const std::vector<int> &ks, bool first) -> int {
+        if (ks.empty()) return MIREG_OK;
+        const int np = (int)ks.size();
+        mireg_ctx *c0 = B->ctx[idx[ks[0]]];
+        std::vector<const cx<T> *> rh(3 * np);
+        std::vector<cx<T> *> sh(3 * np), xh(3 * np), work(np);
+        std::vector<T *> so(3 * np);
+        std::vector<const double *> alpha(np);
+        std::vector<double> mu(np);
+        for (int j = 0; j < np; ++j) {
+            mireg_ctx *c = B->ctx[idx[ks[j]]];
+            const long long N = c->N();
+            T *sg = c->vec<T>(2);
+            for (int a = 0; a < 3; ++a) {
+                rh[3 * j + a] = c->khat<T>(KV_R, a);
+                sh[3 * j + a] = c->khat<T>(KV_S, a);
+                xh[3 * j + a] = c->khat<T>(KV_X, a);
+                so[3 * j + a] = sg + a * N;
+            }
+            work[j] = static_cast<cx<T> *>(c->spec);
+            alpha[j] = c->dres + 3;
+            mu[j] = run[ks[j]].mu;
+        }
+        Phase ph(c0, 0);
+        const bool ok = krylov_direction_multi<T>(c0->g, np, rh.data(), sh.data(), first ? nullptr : mu.data(),
+                                                  first ? KF_FIRST : 0, xh.data(), first ? nullptr : alpha.data(),
+                                                  so.data(), work.data(), twiddles<T>(c0), spec_params<T>(c0), ar,
+                                                  B->stream);
+        return ok ? MIREG_OK : B->fail(MIREG_E_NOMEM, "table arena exhausted");
+    };
+    auto readback_all = [&](const std::vector<int> &ks_all) -> int {
+        std::vector<int> ids;
+        for (int k : ks_all) ids.push_back(idx[k]);
+        const int r = batch_readback(B, ids, 3);
+        ar.reset();  // every table upload issued so far has completed
+        return r;
+    };
+    for (int k = 0; k < n; ++k) {
+        mireg_ctx *c = B->ctx[idx[k]];
+        ensure_state<T, S>(c);
+        ensure_gradm<T, S>(c);
+        ensure_d<T, S>(c);
+        ensure_Y<T, S>(c);
+        const long long N = c->N();
+        const T *rp[3] = {rhs[k], rhs[k] + N, rhs[k] + 2 * N};
+        cx<T> *rh[3] = {c->khat<T>(KV_R, 0), c->khat<T>(KV_R, 1), c->khat<T>(KV_R, 2)};
+        Phase ph(c, 0);
+        krylov_forward<T>(c->g, rp, rh, static_cast<cx<T> *>(c->spec), twiddles<T>(c), B->stream);
+        fill<T>(6 * c->g.NS, (T)0, reinterpret_cast<T *>(c->khat<T>(KV_X, 0)), B->stream);
+    }
+    std::vector<int> all(n);
+    for (int k = 0; k < n; ++k) all[k] = k;
+    for (const auto &cl : classes)
+        if ((rc = hessian_update(cl, false, false))) return rc;
+    if ((rc = readback_all(all))) return rc;
+    std::vector<char> live(n, 0);
+    for (int k = 0; k < n; ++k) {
+        mireg_ctx *c = B->ctx[idx[k]];
+        const double h3 = c->cell();
+        Run &R = run[k];
+        R.r0 = std::sqrt(h3 * c->hres[2]);
+        R.rz = h3 * c->hres[1];
+        R.rnorm = R.r0;
+        if (R.r0 > 0) R.st = MIREG_MAXIT;
+    }
+    std::vector<char> pos(n, 0);
+    for (int k = 0; k < n; ++k) pos[k] = run[k].r0 > 0;
+    for (const auto &cl : classes)
+        if ((rc = direction(members(cl, pos), true))) return rc;  // s = z = M^{-1} r
+    std::vector<int> livek;
+    for (int k = 0; k < n; ++k)
+        if (run[k].r0 > 0 && maxit > 0) {
+            live[k] = 1;
+            livek.push_back(k);
+        }
+    std::vector<SlProblem> pr;
+    auto tables = [&]() {
+        std::vector<int> ids;
+        for (int k : livek) ids.push_back(idx[k]);
+        return batch_tables<T, S>(B, ids, pr);
+    };
+    if (!livek.empty() && (rc = tables())) return rc;
+    const int order = B->ctx[0]->p.interp_order, nt = B->ctx[0]->p.nt;
+    while (!livek.empty()) {
+        {
+            Phase ph(B->ctx[idx[livek[0]]], 1);
+            matvec_transport_batch<T, S>(pr.data(), (int)pr.size(), order, nt, B->htab, B->dtab, B->stream);
+        }
+        for (const auto &cl : classes)
+            if ((rc = hessian_update(members(cl, live), true, true))) return rc;
+        if ((rc = readback_all(livek))) return rc;
+        std::vector<int> next;
+        std::vector<char> dir(n, 0);
+        for (int k : livek) {
+            mireg_ctx *c = B->ctx[idx[k]];
+            const double h3 = c->cell();
+            Run &R = run[k];
+            ++R.mv;
+            live[k] = 0;
+            const double sHs = h3 * c->hres[0];
+            if (!(sHs > 0)) {
+                R.x_is_s = R.it == 0;
+                R.st = MIREG_NEG_CURV;
+                continue;
+            }
+            ++R.it;
+            R.rnorm = std::sqrt(h3 * c->hres[2]);
+            if (R.rnorm <= rtol[k] * R.r0) {
+                R.pending = true;
+                R.st = MIREG_CONVERGED_REL;
+                continue;
+            }
+            const double rz_new = h3 * c->hres[1];
+            R.mu = rz_new / R.rz;
+            R.rz = rz_new;
+            dir[k] = 1;  // x += alpha s, then s = z + mu s
+            if (R.it < maxit) {
+                next.push_back(k);
+                live[k] = 1;
+            }
+        }
+        for (const auto &cl : classes)
+            if ((rc = direction(members(cl, dir), false))) return rc;
+        const bool same = next == livek;
+        livek.swap(next);
+        if (!same && !livek.empty() && (rc = tables())) return rc;
+    }
+    for (int k = 0; k < n; ++k) {
+        mireg_ctx *c = B->ctx[idx[k]];
+        const Run &R = run[k];
+        const long long N = c->N();
+        if (R.x_is_s) {
+            hipError_t e = hipMemcpyAsync(x[k], c->vec<T>(2), 3 * N * sizeof(T), hipMemcpyDeviceToDevice, B->stream);
+            if (e != hipSuccess) return B->fail(MIREG_E_HIP, "copy: %s", hipGetErrorString(e));
+        } else if (R.it > 0) {
+            cx<T> *xh[3], *sh[3];
+            for (int a = 0; a < 3; ++a) {
+                xh[a] = c->khat<T>(KV_X, a);
+                sh[a] = c->khat<T>(KV_S, a);
+            }
+            T *xp[3] = {x[k], x[k] + N, x[k] + 2 * N};
+            Phase ph(c, 0);
+            krylov_inverse<T>(c->g, xh, R.pending ? sh : nullptr, c->dres + 3, xp, static_cast<cx<T> *>(c->spec),
+                              twiddles<T>(c), B->stream);
+        } else {
+            fill<T>(3 * N, (T)0, x[k], B->stream);
+        }
+        if (iters) iters[k] = R.it;
+        if (relres) relres[k] = R.r0 > 0 ? R.rnorm / R.r0 : 0.0;
+        if (status) status[k] = R.st;
+        if (matvecs) matvecs[k] = R.mv;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return B->fail(MIREG_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return MIREG_OK;
+}
+
+// Lockstep GN (Algorithm "outer iteration" for every problem, impl_gn's
+// arithmetic): the Newton steps of all problems that have not stopped are
+// one batched PCG; the objective, gradient and line search run problem by
+// problem on the common stream.
+template <typename T, typename S>
+int batch_gn(mireg_batch *B, T *const *v_io, const mireg_solve_opts *o, mireg_report *reps) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int P = (int)B->ctx.size();
+    struct St {
+        mireg_report R{};
+        double J = 0, gn = 0, g0 = 0;
+        int k = 0;
+        bool done = false;
+        long long coarse0 = 0;
+    };
+    std::vector<St> st(P);
+    int rc;
+    double pcg_s = 0;
+    int pcg_calls = 0;
+    for (int p = 0; p < P; ++p) {
+        mireg_ctx *c = B->ctx[p];
+        const long long n = 3 * c->N();
+        T *g = c->vec<T>(4), *vk = c->vec<T>(6);
+        if ((rc = impl_set_velocity<T, S>(c, v_io[p]))) return batch_ctx_error(B, c, rc);
+        hipError_t e = hipMemcpyAsync(vk, v_io[p], n * sizeof(T), hipMemcpyDeviceToDevice, B->stream);
+        if (e != hipSuccess) return B->fail(MIREG_E_HIP, "copy: %s", hipGetErrorString(e));
+        if ((rc = impl_objective<T, S>(c, &st[p].J, nullptr, nullptr))) return batch_ctx_error(B, c, rc);
+        if ((rc = impl_gradient<T, S>(c, g, &st[p].gn))) return batch_ctx_error(B, c, rc);
+        st[p].R.pde_solves += 3;  // the paper's count for J and g at the initial velocity
+        st[p].g0 = st[p].gn;
+        st[p].R.J0 = st[p].J;
+        st[p].R.gnorm0 = st[p].g0;
+        st[p].coarse0 = c->coarse_matvecs;
+    }
+    for (;;) {
+        std::vector<int> A;
+        std::vector<const T *> rhs;
+        std::vector<T *> vts;
+        std::vector<double> eps;
+        for (int p = 0; p < P; ++p) {
+            St &s = st[p];
+            if (s.done) continue;
+            if (o->log_level > 0)
+                fprintf(stderr, "[mireg batch %d] gn %d J %.6e |g| %.6e |g|/|g0| %.3e\n", p, s.k, s.J, s.gn,
+                        s.g0 > 0 ? s.gn / s.g0 : 0.0);
+            if (s.gn <= o->grad_rtol * s.g0) {
+                s.R.status = MIREG_CONVERGED_REL;
+                s.done = true;
+            } else if (s.gn <= o->grad_atol) {
+                s.R.status = MIREG_CONVERGED_ABS;
+                s.done = true;
+            } else if (s.k >= o->max_gn) {
+                s.R.status = MIREG_MAXIT;
+                s.done = true;
+            }
+            if (s.done) continue;
+            mireg_ctx *c = B->ctx[p];
+            const long long n = 3 * c->N();
+            T *rv = c->vec<T>(7);
+            affine<T>(n, c->vec<T>(4), -1.0, 0.0, rv, B->stream);
+            A.push_back(p);
+            rhs.push_back(rv);
+            vts.push_back(c->vec<T>(5));
+            eps.push_back(std::fmin(0.5, std::sqrt(s.gn / s.g0)));
+        }
+        if (A.empty()) break;
+        std::vector<int> its(A.size()), pst(A.size()), mv(A.size());
+        const auto tp = std::chrono::steady_clock::now();
+        if ((rc = batch_pcg<T, S>(B, A, rhs.data(), vts.data(), eps.data(), o->max_pcg, its.data(), nullptr,
+                                  pst.data(), mv.data())))
+            return rc;
+        if (o->log_level > 1) {
+            hipStreamSynchronize(B->stream);
+            pcg_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
+            ++pcg_calls;
+        }
+        for (size_t a = 0; a < A.size(); ++a) {
+            const int p = A[a];
+            St &s = st[p];
+            mireg_ctx *c = B->ctx[p];
+            const long long n = 3 * c->N();
+            T *g = c->vec<T>(4), *vt = c->vec<T>(5), *vk = c->vec<T>(6);
+            s.R.matvecs += mv[a];
+            s.R.pcg_iters += its[a];
+            s.R.pde_solves += 2 * mv[a];
+            s.R.neg_curv += pst[a] == MIREG_NEG_CURV;
+            double slope = 0;
+            if ((rc = dot_h<T>(c, g, vt, n, &slope))) return batch_ctx_error(B, c, rc);
+            double alpha = 1.0, Jt = 0;
+            bool accepted = false;
+            for (int ls = 0; ls < o->max_ls; ++ls) {
+                xpay<T>(n, vk, alpha, vt, c->f<T>(c->v), B->stream);
+                c->invalidate();
+                if ((rc = impl_objective<T, S>(c, &Jt, nullptr, nullptr))) return batch_ctx_error(B, c, rc);
+                s.R.ls_trials += 1;
+                s.R.pde_solves += 1;
+                if (Jt <= s.J + o->armijo_c1 * alpha * slope) {
+                    accepted = true;
+                    break;
+                }
+                alpha *= 0.5;
+            }
+            if (!accepted) {
+                hipError_t e = hipMemcpyAsync(c->v, vk, n * sizeof(T), hipMemcpyDeviceToDevice, B->stream);
+                if (e != hipSuccess) return B->fail(MIREG_E_HIP, "copy: %s", hipGetErrorString(e));
+                c->invalidate();
+                s.R.status = MIREG_LS_FAIL;
+                s.done = true;
+                continue;
+            }
+            hipError_t e = hipMemcpyAsync(vk, c->v, n * sizeof(T), hipMemcpyDeviceToDevice, B->stream);
+            if (e != hipSuccess) return B->fail(MIREG_E_HIP, "copy: %s", hipGetErrorString(e));
+            s.J = Jt;
+            if ((rc = impl_gradient<T, S>(c, g, &s.gn))) return batch_ctx_error(B, c, rc);
+            s.R.pde_solves += 1;
+            ++s.k;
+        }
+    }
+    for (int p = 0; p < P; ++p) {
+        St &s = st[p];
+        mireg_ctx *c = B->ctx[p];
+        const long long N = c->N(), n = 3 * N;
+        s.R.gn_iters = s.k;
+        s.R.J = s.J;
+        s.R.gnorm = s.gn;
+        s.R.gnorm_rel = s.g0 > 0 ? s.gn / s.g0 : 0.0;
+        ensure_state<T, S>(c);
+        sumsq_diff<T, T>(c->f<T>(c->m) + c->p.nt * N, c->f<T>(c->mR), N, c->partials, c->dres, B->stream);
+        if ((rc = readback(c, 1))) return batch_ctx_error(B, c, rc);
+        const double num = c->hres[0];
+        sumsq_diff<T, T>(c->f<T>(c->mT), c->f<T>(c->mR), N, c->partials, c->dres, B->stream);
+        if ((rc = readback(c, 1))) return batch_ctx_error(B, c, rc);
+        s.R.mismatch_rel = c->hres[0] > 0 ? num / c->hres[0] : 0.0;
+        hipError_t e = hipMemcpyAsync(v_io[p], c->vec<T>(6), n * sizeof(T), hipMemcpyDeviceToDevice, B->stream);
+        if (e != hipSuccess) return B->fail(MIREG_E_HIP, "copy: %s", hipGetErrorString(e));
+        s.R.coarse_matvecs = (int)(c->coarse_matvecs - s.coarse0);
+    }
+    hipError_t e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return B->fail(MIREG_E_HIP, "synchronise: %s", hipGetErrorString(e));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (o->log_level > 1)
+        fprintf(stderr, "[mireg batch] %.4f s, of which %.4f s in %d lockstep PCG solves\n", secs, pcg_s, pcg_calls);
+    for (int p = 0; p < P; ++p) {
+        st[p].R.seconds = secs;
+        if (reps) reps[p] = st[p].R;
+    }
+    return MIREG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C-ABI
 // ===========================================================================
 extern "C" {
@@ -1517,6 +1993,90 @@ int mireg_gn_solve(mireg_ctx *ctx, void *v_inout, const mireg_solve_opts *opts, 
     if (opts) o = *opts;
     if (o.max_gn < 0 || o.max_pcg < 0 || o.max_ls < 0) return ctx->fail(MIREG_E_ARG, "negative iteration cap");
     return DISPATCH(ctx, (impl_gn<T, S>(ctx, (T *)v_inout, &o, rep)));
+}
+
+int mireg_batch_create(mireg_ctx *const *ctxs, int n, mireg_batch **out) {
+    if (!ctxs || !out || n < 1) return MIREG_E_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i]) return MIREG_E_ARG;
+    const mireg_ctx *c0 = ctxs[0];
+    for (int i = 1; i < n; ++i) {
+        const mireg_ctx *c = ctxs[i];
+        if (c->p.dtype != c0->p.dtype || c->p.nt != c0->p.nt || c->p.interp_order != c0->p.interp_order ||
+            c->stream != c0->stream || c->g.sl_tile != c0->g.sl_tile || c->g.lds_cap != c0->g.lds_cap)
+            return MIREG_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return MIREG_E_ARG;
+    }
+    mireg_batch *B = new (std::nothrow) mireg_batch;
+    if (!B) return MIREG_E_NOMEM;
+    B->ctx.assign(ctxs, ctxs + n);
+    B->stream = c0->stream;
+    mireg_ctx *cm = ctxs[0];
+    const size_t bytes = DISPATCH(cm, (batch_table_bytes<T, S>(n, cm->p.nt)));
+    // pointer tables of one PCG iteration: under 1 KB per problem
+    B->arena.cap = (size_t)4096 * n + (size_t)64 * 1024;
+    if (hipMalloc(&B->dtab, bytes) != hipSuccess || hipHostMalloc(&B->htab, bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&B->arena.d, B->arena.cap) != hipSuccess ||
+        hipHostMalloc((void **)&B->arena.h, B->arena.cap, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&B->tab_done, hipEventDisableTiming) != hipSuccess) {
+        mireg_batch_destroy(B);
+        return MIREG_E_NOMEM;
+    }
+    *out = B;
+    return MIREG_OK;
+}
+
+int mireg_batch_destroy(mireg_batch *b) {
+    if (!b) return MIREG_E_ARG;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    else hipDeviceSynchronize();
+    if (b->dtab) hipFree(b->dtab);
+    if (b->htab) hipHostFree(b->htab);
+    if (b->arena.d) hipFree(b->arena.d);
+    if (b->arena.h) hipHostFree(b->arena.h);
+    if (b->tab_done) hipEventDestroy(b->tab_done);
+    delete b;
+    return MIREG_OK;
+}
+
+const char *mireg_batch_last_error(const mireg_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int mireg_batch_pcg_solve(mireg_batch *b, const void *const *rhs, void *const *x, const double *rtol, int maxit,
+                          int *iters, double *relres, int *status) {
+    if (!b || !rhs || !x || !rtol) return b ? b->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
+    const int P = (int)b->ctx.size();
+    if (maxit < 0) return b->fail(MIREG_E_ARG, "negative iteration cap");
+    std::vector<int> idx(P);
+    for (int p = 0; p < P; ++p) {
+        idx[p] = p;
+        if (!rhs[p] || !x[p] || !(rtol[p] >= 0)) return b->fail(MIREG_E_ARG, "problem %d: invalid argument", p);
+        if (!b->ctx[p]->have_images) return b->fail(MIREG_E_STATE, "problem %d: set_images has not been called", p);
+        if (b->ctx[p]->pc_kind != MIREG_PC_SPECTRAL)
+            return b->fail(MIREG_E_ARG, "problem %d: batched PCG takes the spectral preconditioner", p);
+    }
+    mireg_ctx *c0 = b->ctx[0];
+    return DISPATCH(c0, (batch_pcg<T, S>(b, idx, reinterpret_cast<const T *const *>(rhs),
+                                          reinterpret_cast<T *const *>(x), rtol, maxit, iters, relres, status,
+                                          nullptr)));
+}
+
+int mireg_batch_gn_solve(mireg_batch *b, void *const *v_inout, const mireg_solve_opts *opts, mireg_report *reps) {
+    if (!b || !v_inout) return b ? b->fail(MIREG_E_ARG, "null pointer") : MIREG_E_ARG;
+    const int P = (int)b->ctx.size();
+    for (int p = 0; p < P; ++p) {
+        if (!v_inout[p]) return b->fail(MIREG_E_ARG, "problem %d: null velocity", p);
+        if (!b->ctx[p]->have_images) return b->fail(MIREG_E_STATE, "problem %d: set_images has not been called", p);
+        if (b->ctx[p]->pc_kind != MIREG_PC_SPECTRAL)
+            return b->fail(MIREG_E_ARG, "problem %d: batched solves take the spectral preconditioner", p);
+    }
+    mireg_solve_opts o;
+    mireg_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_gn < 0 || o.max_pcg < 0 || o.max_ls < 0) return b->fail(MIREG_E_ARG, "negative iteration cap");
+    mireg_ctx *c0 = b->ctx[0];
+    return DISPATCH(c0, (batch_gn<T, S>(b, reinterpret_cast<T *const *>(v_inout), &o, reps)));
 }
 
 int mireg_op(mireg_ctx *ctx, int opcode, const void *in, void *out, double arg) {

@@ -357,8 +357,33 @@ struct DirectStage {
 // stencil box is larger gather from global memory.  Only the fractional
 // positions and base nodes live across the staging phase; the weights are
 // formed point by point afterwards, which keeps the register count low.
-template <typename T, int ORDER, int NF, int SHAPE, class Op>
-__global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
+//
+// MULTI: one launch for several problems.  Their tiles are numbered one after
+// the other (problem p owns tiles tab[p].start .. tab[p].start + its tile
+// count - 1), each workgroup finds its problem in the table (a block-uniform
+// scan of at most a few dozen entries) and runs the single-problem tile code
+// on that problem's grid and operands, so every problem's results are those
+// of its own launch; every entry's lds_cap is at most the launch's dynamic
+// LDS.  (A flag on this kernel rather than a shared device function: with
+// the tile code outside the kernel body the compiler keeps the operands of
+// the single-problem launches in more registers.)
+template <class Op>
+struct SlEntry {
+    PGrid g;
+    Op op;
+    int start;
+};
+
+template <typename T, int ORDER, int NF, int SHAPE, class Op, bool MULTI = false>
+__global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g0, Op op0, const SlEntry<Op> *__restrict__ tab, int nprob,
+                                                   int total) {
+    int pm = 0;
+    if constexpr (MULTI) {
+        const int t = xcd_tile(blockIdx.x, total);
+        while (pm + 1 < nprob && tab[pm + 1].start <= t) ++pm;
+    }
+    const PGrid &g = MULTI ? tab[pm].g : g0;
+    const Op &op = MULTI ? tab[pm].op : op0;
     using TP = TilePoints<SHAPE>;
     constexpr int kPPT = TP::PPT;
     using A = AxisW<T, ORDER>;
@@ -366,7 +391,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl(PGrid g, Op op) {
     extern __shared__ __align__(16) unsigned char sl_smem[];
     T *lds = reinterpret_cast<T *>(sl_smem);
     __shared__ int box[6];
-    const int tile = xcd_tile(blockIdx.x, g.tx * g.ty * g.tz);
+    const int tile = MULTI ? xcd_tile(blockIdx.x, total) - tab[pm].start : xcd_tile(blockIdx.x, g.tx * g.ty * g.tz);
     const TP tp(g, tile);
     // box of the base nodes (lowest, highest per axis) in unwrapped grid
     // coordinates (block-uniform): the stored one, or reduced over the
@@ -859,6 +884,29 @@ __global__ __launch_bounds__(kSlThreads) void k_incstate_init(long long N, T hdt
     store_as(q, idx, hdt * f);
 }
 
+// The incremental state's first source for several problems in one launch
+// (problem p owns blocks start .. start + its block count - 1).
+template <typename T, typename S>
+struct InitEntry {
+    long long N;
+    T hdt;
+    const T *gm, *vt;
+    S *q;
+    int start;
+};
+template <typename T, typename S>
+__global__ __launch_bounds__(kSlThreads) void k_incstate_init_multi(const InitEntry<T, S> *__restrict__ tab,
+                                                                    int nprob) {
+    int p = 0;
+    while (p + 1 < nprob && tab[p + 1].start <= (int)blockIdx.x) ++p;
+    const InitEntry<T, S> e = tab[p];
+    const long long idx = (long long)((int)blockIdx.x - e.start) * kSlThreads + threadIdx.x;
+    if (idx >= e.N) return;
+    const long long N = e.N;
+    const T f = -(e.gm[idx] * e.vt[idx] + e.gm[N + idx] * e.vt[N + idx] + e.gm[2 * N + idx] * e.vt[2 * N + idx]);
+    store_as(e.q, idx, e.hdt * f);
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n) { return (unsigned)((n + kSlThreads - 1) / kSlThreads); }
 
@@ -876,9 +924,11 @@ static void launch_sl_shape(const PGrid &g, int order, const Op &op, hipStream_t
     const unsigned nb = (unsigned)(g.tx * g.ty * g.tz);
     const size_t lds = g.lds_cap > 0 ? (size_t)(g.lds_cap + 1) * NF * sizeof(T) : 0;
     if (order == 3)
-        hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op);
+        hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op,
+                           (const SlEntry<Op> *)nullptr, 0, 0);
     else
-        hipLaunchKernelGGL((k_sl<T, 1, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op);
+        hipLaunchKernelGGL((k_sl<T, 1, NF, SHAPE, Op>), dim3(nb), dim3(kSlThreads), lds, s, g, op,
+                           (const SlEntry<Op> *)nullptr, 0, 0);
 }
 
 template <typename T, int NF, class Op>
@@ -995,6 +1045,153 @@ void incstate_step(const Grid &gg, int order, double coef, double sign, const S 
     launch_sl<T, 1>(g, order, box, op, s);
 }
 
+// ---- batched GN matvec transport: one launch per step across problems ----
+// Table layout in device memory: init entries, then nt incremental-state
+// step tables, nt - 1 adjoint step tables and one accumulate table, each
+// nprob entries, every table 256-byte aligned.
+namespace {
+constexpr size_t kTabAlign = 256;
+size_t tab_round(size_t b) { return (b + kTabAlign - 1) / kTabAlign * kTabAlign; }
+template <typename T, typename S>
+struct BatchLayout {
+    size_t init, inc, adj, acc, total;
+    BatchLayout(int nprob, int nt) {
+        init = 0;
+        inc = tab_round(sizeof(InitEntry<T, S>) * nprob);
+        adj = inc + (size_t)nt * tab_round(sizeof(SlEntry<IncStateOp<T, S>>) * nprob);
+        acc = adj + (size_t)(nt > 1 ? nt - 1 : 0) * tab_round(sizeof(SlEntry<AdjointOp<T, S>>) * nprob);
+        total = acc + tab_round(sizeof(SlEntry<AdjointAccumOp<T, S>>) * nprob);
+    }
+    size_t inc_at(int j, int nprob) const { return inc + (size_t)j * tab_round(sizeof(SlEntry<IncStateOp<T, S>>) * nprob); }
+    size_t adj_at(int j, int nprob) const {  // j = 1 .. nt-1 -> slot j - 1
+        return adj + (size_t)(j - 1) * tab_round(sizeof(SlEntry<AdjointOp<T, S>>) * nprob);
+    }
+};
+
+template <typename T, int NF>
+PGrid entry_grid(const Grid &gg, SlBox box) {
+    PGrid g = pgrid(gg);
+    g.lds_cap = launch_cap<T, NF>(g, box.cap);
+    g.tbox = box.tiles;
+    return g;
+}
+
+template <typename T, int NF, int SHAPE, class Op>
+void launch_multi_shape(const SlEntry<Op> *dtab, int nprob, int total, int order, size_t lds, hipStream_t s) {
+    const PGrid none{};
+    if (order == 3)
+        hipLaunchKernelGGL((k_sl<T, 3, NF, SHAPE, Op, true>), dim3(total), dim3(kSlThreads), lds, s, none, Op{}, dtab,
+                           nprob, total);
+    else
+        hipLaunchKernelGGL((k_sl<T, 1, NF, SHAPE, Op, true>), dim3(total), dim3(kSlThreads), lds, s, none, Op{}, dtab,
+                           nprob, total);
+}
+
+// entries: the host copy (for the tile counts and the LDS size), dtab: the
+// same entries in device memory
+template <typename T, int NF, class Op>
+void launch_multi(const SlEntry<Op> *entries, const SlEntry<Op> *dtab, int nprob, int order, int shape,
+                  hipStream_t s) {
+    int total = 0;
+    size_t lds = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const PGrid &g = entries[p].g;
+        total += g.tx * g.ty * g.tz;
+        const size_t l = g.lds_cap > 0 ? (size_t)(g.lds_cap + 1) * NF * sizeof(T) : 0;
+        lds = l > lds ? l : lds;
+    }
+    switch (shape) {
+        case TILE_8x8x16: launch_multi_shape<T, NF, TILE_8x8x16>(dtab, nprob, total, order, lds, s); break;
+        case TILE_8x16x16: launch_multi_shape<T, NF, TILE_8x16x16>(dtab, nprob, total, order, lds, s); break;
+        default: launch_multi_shape<T, NF, TILE_4x8x32>(dtab, nprob, total, order, lds, s); break;
+    }
+}
+}  // namespace
+
+template <typename T, typename S>
+size_t batch_table_bytes(int nprob, int nt) {
+    return BatchLayout<T, S>(nprob, nt).total;
+}
+
+template <typename T, typename S>
+void matvec_transport_tables(const SlProblem *pr, int nprob, int nt, void *htab, void *dtab, hipStream_t s) {
+    const BatchLayout<T, S> L(nprob, nt);
+    char *h = static_cast<char *>(htab);
+    const double dt = 1.0 / nt;
+    int start = 0, bstart = 0;
+    for (int p = 0; p < nprob; ++p) {
+        const SlProblem &q = pr[p];
+        const unsigned N = (unsigned)q.g.N;
+        const T *gm = static_cast<const T *>(q.gradm), *vt = static_cast<const T *>(q.vt);
+        const T *X = static_cast<const T *>(q.X), *Y = static_cast<const T *>(q.Y), *d = static_cast<const T *>(q.d);
+        S *q0 = static_cast<S *>(q.q), *q1 = q0 + N, *lam = static_cast<S *>(q.lam);
+        InitEntry<T, S> *ie = reinterpret_cast<InitEntry<T, S> *>(h + L.init);
+        ie[p] = InitEntry<T, S>{q.g.N, (T)(0.5 * dt), gm, vt, q0, bstart};
+        bstart += (int)blocks_for(q.g.N);
+        const PGrid gx1 = entry_grid<T, 1>(q.g, q.boxX), gy2 = entry_grid<T, 2>(q.g, q.boxY);
+        const int tiles = gx1.tx * gx1.ty * gx1.tz;
+        S *cur = q0, *nxt = q1;
+        for (int j = 0; j < nt; ++j) {
+            auto *te = reinterpret_cast<SlEntry<IncStateOp<T, S>> *>(h + L.inc_at(j, nprob));
+            const bool last = j == nt - 1;
+            te[p].g = gx1;
+            te[p].op = IncStateOp<T, S>{cur, X, gm + 3 * (size_t)(j + 1) * N, vt, last ? lam + (size_t)nt * N : nxt, N,
+                                        (T)(last ? 0.5 * dt : dt), (T)(last ? -1.0 : 1.0)};
+            te[p].start = start;
+            S *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        for (int j = nt - 1; j >= 1; --j) {
+            auto *ae = reinterpret_cast<SlEntry<AdjointOp<T, S>> *>(h + L.adj_at(j, nprob));
+            ae[p].g = gy2;
+            ae[p].op = AdjointOp<T, S>{lam + (size_t)(j + 1) * N, d, Y, lam + (size_t)j * N, N, (T)dt};
+            ae[p].start = start;
+        }
+        auto *ce = reinterpret_cast<SlEntry<AdjointAccumOp<T, S>> *>(h + L.acc);
+        ce[p].g = gy2;
+        ce[p].op = AdjointAccumOp<T, S>{AdjointOp<T, S>{lam + N, d, Y, nullptr, N, (T)dt}, lam, gm,
+                                        static_cast<T *>(q.b), nt, (T)(0.5 * dt), (T)dt};
+        ce[p].start = start;
+        start += tiles;
+    }
+    hipMemcpyAsync(dtab, htab, L.total, hipMemcpyHostToDevice, s);
+}
+
+template <typename T, typename S>
+void matvec_transport_batch(const SlProblem *pr, int nprob, int order, int nt, const void *htab, const void *dtab,
+                            hipStream_t s) {
+    const BatchLayout<T, S> L(nprob, nt);
+    const char *h = static_cast<const char *>(htab), *dv = static_cast<const char *>(dtab);
+    const int shape = pr[0].g.sl_tile;
+    double Ntot = 0;
+    int blocks = 0;
+    for (int p = 0; p < nprob; ++p) {
+        Ntot += (double)pr[p].g.N;
+        blocks += (int)blocks_for(pr[p].g.N);
+    }
+    {
+        HookScope hs(K_INC_INIT, (6.0 * sizeof(T) + sizeof(S)) * Ntot);
+        hipLaunchKernelGGL((k_incstate_init_multi<T, S>), dim3(blocks), dim3(kSlThreads), 0, s,
+                           reinterpret_cast<const InitEntry<T, S> *>(dv + L.init), nprob);
+    }
+    for (int j = 0; j < nt; ++j) {
+        HookScope hs(K_INC_STEP, (9.0 * sizeof(T) + 2.0 * sizeof(S)) * Ntot);
+        launch_multi<T, 1>(reinterpret_cast<const SlEntry<IncStateOp<T, S>> *>(h + L.inc_at(j, nprob)),
+                           reinterpret_cast<const SlEntry<IncStateOp<T, S>> *>(dv + L.inc_at(j, nprob)), nprob, order,
+                           shape, s);
+    }
+    for (int j = nt - 1; j >= 1; --j) {
+        HookScope hs(K_ADJ_STEP, (4.0 * sizeof(T) + 2.0 * sizeof(S)) * Ntot);
+        launch_multi<T, 2>(reinterpret_cast<const SlEntry<AdjointOp<T, S>> *>(h + L.adj_at(j, nprob)),
+                           reinterpret_cast<const SlEntry<AdjointOp<T, S>> *>(dv + L.adj_at(j, nprob)), nprob, order,
+                           shape, s);
+    }
+    HookScope hs(K_ADJ_ACC, ((4.0 + 3.0 * (nt + 1) + 3.0) * sizeof(T) + (double)nt * sizeof(S)) * Ntot);
+    launch_multi<T, 2>(reinterpret_cast<const SlEntry<AdjointAccumOp<T, S>> *>(h + L.acc),
+                       reinterpret_cast<const SlEntry<AdjointAccumOp<T, S>> *>(dv + L.acc), nprob, order, shape, s);
+}
+
 #define MIREG_INST_T(T)                                                                                   \
     template void departure<T>(const Grid &, int, int, double, const T *, T *, SlBox, hipStream_t);      \
     template void interp_field<T, T, T>(const Grid &, int, const T *, const T *, T *, SlBox, hipStream_t); \
@@ -1008,7 +1205,11 @@ void incstate_step(const Grid &gg, int order, double coef, double sign, const S 
                                                 const T *, const T *, T *, SlBox, hipStream_t);          \
     template void incstate_init<T, S>(const Grid &, double, const T *, const T *, S *, hipStream_t);     \
     template void incstate_step<T, S>(const Grid &, int, double, double, const S *, const T *, const T *, \
-                                      const T *, S *, SlBox, hipStream_t);
+                                      const T *, S *, SlBox, hipStream_t);                               \
+    template size_t batch_table_bytes<T, S>(int, int);                                                   \
+    template void matvec_transport_tables<T, S>(const SlProblem *, int, int, void *, void *, hipStream_t); \
+    template void matvec_transport_batch<T, S>(const SlProblem *, int, int, int, const void *, const void *, \
+                                               hipStream_t);
 MIREG_INST_T(float)
 MIREG_INST_T(double)
 MIREG_INST(float, float)

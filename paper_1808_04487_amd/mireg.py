@@ -103,6 +103,13 @@ SIGNATURES = {
     "mireg_kernel_stats_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
     "mireg_timers_read": ([_vp, ctypes.POINTER(Timers), ctypes.c_int], ctypes.c_int),
     "mireg_interp_noalloc": ([ctypes.c_int * 3, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "mireg_batch_create": ([ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+    "mireg_batch_destroy": ([_vp], ctypes.c_int),
+    "mireg_batch_last_error": ([_vp], ctypes.c_char_p),
+    "mireg_batch_pcg_solve": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp, ctypes.c_int, _ip, _dp, _ip],
+                              ctypes.c_int),
+    "mireg_batch_gn_solve": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)],
+                             ctypes.c_int),
 }
 
 _lib = None
@@ -325,3 +332,58 @@ def interp_noalloc(f, disp, out, order=3):
     if rc != OK:
         raise MiregError(rc, lib.mireg_last_error(None).decode())
     return out
+
+
+class Batch:
+    """Lockstep solves of several contexts (any grid sizes; the same dtype,
+    nt, order, stream and tile shape): one transport launch per matvec step
+    across the problems, one PCG read-back per iteration for all of them."""
+
+    def __init__(self, ctxs):
+        self.lib = load_library()
+        self.ctxs = list(ctxs)
+        arr = (_vp * len(self.ctxs))(*[c.h for c in self.ctxs])
+        h = _vp()
+        rc = self.lib.mireg_batch_create(arr, len(self.ctxs), ctypes.byref(h))
+        if rc != OK:
+            raise MiregError(rc, "mireg_batch_create: contexts do not match or allocation failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc != OK:
+            raise MiregError(rc, self.lib.mireg_batch_last_error(self.h).decode())
+
+    def _ptrs(self, tensors, comps, name):
+        return (_vp * len(tensors))(*[c._arg(t, comps, name) for c, t in zip(self.ctxs, tensors)])
+
+    def pcg(self, rhs, rtol=1e-3, maxit=100):
+        """Returns ([x], [iterations], [relative residual], [status])."""
+        P = len(self.ctxs)
+        xs = [c.empty(3) for c in self.ctxs]
+        rt = (ctypes.c_double * P)(*([float(rtol)] * P if not isinstance(rtol, (list, tuple)) else rtol))
+        it, rel, st = (ctypes.c_int * P)(), (ctypes.c_double * P)(), (ctypes.c_int * P)()
+        self._check(self.lib.mireg_batch_pcg_solve(self.h, self._ptrs(rhs, 3, "rhs"), self._ptrs(xs, 3, "x"), rt,
+                                                   int(maxit), it, rel, st))
+        return xs, list(it), list(rel), list(st)
+
+    def gn_solve(self, v0=None, grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100, armijo_c1=1e-4,
+                 max_ls=10, log_level=0):
+        """Returns ([v], [report dict]); v0 (warm starts) defaults to zeros."""
+        vs = [torch.zeros((3,) + c.n, dtype=c.dtype, device=c.device) if v0 is None else v0[i].clone()
+              for i, c in enumerate(self.ctxs)]
+        o = SolveOpts(float(grad_rtol), float(grad_atol), int(max_gn), int(max_pcg), float(armijo_c1),
+                      int(max_ls), int(log_level))
+        reps = (Report * len(self.ctxs))()
+        self._check(self.lib.mireg_batch_gn_solve(self.h, self._ptrs(vs, 3, "v"), ctypes.byref(o), reps))
+        return vs, [r.as_dict() for r in reps]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mireg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -111,3 +111,154 @@ def test_batched_solves_equal_sequential():
     assert all(r[1]["status"] == mireg.CONVERGED_REL for r in rp)
     seq.close()
     par.close()
+
+
+REPORT_KEYS = ("status", "gn_iters", "matvecs", "pde_solves", "pcg_iters", "ls_trials", "neg_curv", "J0", "J",
+               "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel")  # printed in the oracle comparison
+
+
+def _lockstep_contexts(sizes, dtype):
+    """Contexts of the given grid sizes on the current stream, each with a
+    synthetic pair of its own (the paper's analytic problem at that size)."""
+    out = []
+    for k, n in enumerate(sizes):
+        g, ctx, vs = synthetic_ctx(n, dtype)
+        out.append((g, ctx, vs))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_lockstep_pcg_matches_single_problem_pcg(dtype):
+    """Lockstep PCG over problems of uneven sizes (one transport launch per
+    matvec step across them, one launch per Krylov pass per grid size)
+    against the single-problem PCG of each problem, also when problems stop
+    at different iterations and one has a zero right-hand side: the same
+    iterations and status, relative residual and iterate to rounding (the
+    multi-problem kernels are separate instantiations whose operation
+    contraction may differ)."""
+    need_gpu()
+    sizes = [(16, 16, 16), (48, 48, 48), (32, 16, 64), (16, 32, 16), (64, 16, 16), (64, 64, 64)]
+    probs = _lockstep_contexts(sizes, dtype)
+    rhs, ref = [], []
+    for k, (g, ctx, vs) in enumerate(probs):
+        ctx.set_velocity(torch.from_numpy((0.4 + 0.1 * k) * vs).to(dtype).cuda())
+        r = torch.from_numpy(smooth_vector(g, 200 + k)).to(dtype).cuda()
+        if k == 3:
+            r.zero_()
+        rhs.append(r)
+    rtols = [0.3, 0.1, 0.03, 1e-3, 1e-2, 1e-2]
+    for (g, ctx, vs), r, rt in zip(probs, rhs, rtols):
+        ref.append(ctx.pcg(r, rtol=rt, maxit=40, with_status=True))
+    B = mireg.Batch([p[1] for p in probs])
+    xs, its, rels, sts = B.pcg(rhs, rtol=rtols, maxit=40)
+    print("lockstep pcg", dtype, "iterations", its, "single", [r[1] for r in ref], flush=True)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for x, it, rel, st, (xr, itr, relr, str_) in zip(xs, its, rels, sts, ref):
+        assert (it, st) == (itr, str_)
+        assert abs(rel - relr) <= tol * max(relr, 1e-30) or rel == relr
+        d = (x - xr).abs().max().item()
+        scale = xr.abs().max().item()
+        print("  iterate max diff %.2e of max %.2e" % (d, scale), flush=True)
+        assert d <= tol * max(scale, 1e-30) * (1 if dtype == torch.float64 else 50)
+    assert len(set(its)) > 2  # the problems stop at different iterations
+    B.close()
+    for p in probs:
+        p[1].close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_lockstep_gn_matches_single_problem_gn(dtype):
+    """Lockstep GN-Krylov over pairs of uneven sizes (power-of-two and
+    radix-3 grids) against each pair's single-problem solve: in FP64 every
+    counter identical and J, mismatch and gradient norms to 1e-10 (the FP64
+    lockstep iterates equal the single ones bit for bit); in FP32, where a
+    few ulps of difference in the Krylov passes steer the iterates of a
+    solve stopped at a 20-fold gradient reduction, the same status,
+    iterations within one, the same J0, and J and the relative mismatch
+    within 1e-2 (measured: 7e-4 and 2e-3 on the 64^3 pair)."""
+    need_gpu()
+    sizes = [32, 48, 64, 32, 16]
+    pairs = batch.make_pairs(sizes)
+    if dtype == torch.float64:
+        pairs = [(a.double(), b.double()) for a, b in pairs]
+    ctxs = [mireg.Context((n, n, n), dtype=dtype, **batch.SOLVER) for n in sizes]
+    singles = []
+    for ctx, (mT, mR) in zip(ctxs, pairs):
+        ctx.set_images(mT, mR)
+        singles.append(ctx.gn_solve(grad_rtol=5e-2))
+    B = mireg.Batch(ctxs)
+    vs, reps = B.gn_solve(grad_rtol=5e-2)
+    print("lockstep gn", dtype, [(r["gn_iters"], r["matvecs"], r["J"]) for r in reps], flush=True)
+    print("single gn", dtype, [(r["gn_iters"], r["matvecs"], r["J"]) for _, r in singles], flush=True)
+    for v, rep, (vr, rr) in zip(vs, reps, singles):
+        assert rep["status"] == rr["status"] == mireg.CONVERGED_REL
+        if dtype == torch.float64:
+            for k in ("gn_iters", "matvecs", "pde_solves", "pcg_iters", "ls_trials", "neg_curv"):
+                assert rep[k] == rr[k], k
+            for k in ("J0", "J", "mismatch_rel", "gnorm0", "gnorm"):
+                assert abs(rep[k] - rr[k]) <= 1e-10 * abs(rr[k]), k
+        else:
+            assert abs(rep["gn_iters"] - rr["gn_iters"]) <= 1
+            assert rep["J0"] == rr["J0"]
+            for k in ("J", "mismatch_rel"):
+                assert abs(rep[k] - rr[k]) <= 1e-2 * abs(rr[k]), k
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.timeout(900)
+def test_lockstep_gn_matches_oracle_on_batch_pairs():
+    """Two pairs of the uneven batch recipe, the first 64^3 and the first
+    96^3 one, prepared by the oracle on the host in FP64 (its own reference
+    images) and solved together by the lockstep GN in FP64: status,
+    iterations, matvecs, PDE solves and trials equal the oracle's solves,
+    J, mismatch and gradient norms agree to 1e-10."""
+    need_gpu()
+    import math
+
+    from oracle import solver
+
+    amp = np.random.default_rng(7).uniform(0.05, 0.2, len(batch.UNEVEN_BATCH)) * 2 * math.pi
+    picks = [batch.UNEVEN_BATCH.index(64), batch.UNEVEN_BATCH.index(96)]
+    ctxs, oracle_reps = [], []
+    for p in picks:
+        n = (batch.UNEVEN_BATCH[p],) * 3
+        g = core.Grid(n)
+        mT = prep.smooth_rescale(g, synth.voronoi_phantom(n, nseeds=120, seed=100 + 2 * p), 2.0)
+        v = prep.smooth_velocity(g, synth.white_noise(n, seed=101 + 2 * p), math.pi / 4, float(amp[p]))
+        mR = prep.transport(g, mT, v)
+        print("oracle solve", n, flush=True)
+        prm = core.Params(n, nt=4, order=3, reg=core.REG_H1, div_mode=core.DIV_NEAR, beta_v=5e-3, beta_w=1.0)
+        _, rep = solver.gn_solve(core.Registration(prm, mT, mR), np.zeros((3,) + n), grad_rtol=5e-2)
+        oracle_reps.append(rep)
+        ctx = mireg.Context(n, dtype=torch.float64, **batch.SOLVER)
+        ctx.set_images(torch.from_numpy(mT).cuda(), torch.from_numpy(mR).cuda())
+        ctxs.append(ctx)
+    B = mireg.Batch(ctxs)
+    _, reps = B.gn_solve(grad_rtol=5e-2)
+    for rep, ro in zip(reps, oracle_reps):
+        print("lockstep", {k: rep[k] for k in REPORT_KEYS}, "oracle", ro.as_dict(), flush=True)
+        for k in ("status", "gn_iters", "matvecs", "pde_solves", "ls_trials", "neg_curv"):
+            assert rep[k] == getattr(ro, k), k
+        for k in ("J0", "J", "mismatch_rel", "gnorm0", "gnorm"):
+            assert abs(rep[k] - getattr(ro, k)) <= 1e-10 * abs(getattr(ro, k)), k
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_rejects_mismatched_contexts():
+    need_gpu()
+    a = mireg.Context((16, 16, 16), dtype=torch.float32)
+    b = mireg.Context((16, 16, 16), dtype=torch.float64)
+    c = mireg.Context((16, 16, 16), dtype=torch.float32, nt=2)
+    for bad in ([a, b], [a, c], [a, a]):
+        with pytest.raises(mireg.MiregError):
+            mireg.Batch(bad)
+    B = mireg.Batch([a])
+    with pytest.raises(mireg.MiregError):  # no images
+        B.gn_solve()
+    B.close()
+    for x in (a, b, c):
+        x.close()
