@@ -276,10 +276,18 @@ struct LayoutCols {
     static __device__ __forceinline__ int at(int c, int p) { return p * W + c; }
     static constexpr int size(int L) { return L * W; }
 };
+// Rows of power-of-two lines of 32 points and more carry one element of
+// padding after every 2^SH positions (SH = 4 from 128 points, else 3): the
+// first Stockham stage stores R consecutive positions per thread, at a
+// stride of R between the threads of a line, and a flat row would put those
+// threads on one bank; the skew spreads them, and the reads of consecutive
+// positions that follow stay spread too.  Shorter and 3/5-smooth lines keep
+// one element of padding per row.
 template <int W, int L>
 struct LayoutRows {
-    static constexpr int PITCH = L + 1;
-    static __device__ __forceinline__ int at(int c, int p) { return c * PITCH + p; }
+    static constexpr int SH = (is_pow2(L) && L >= 32) ? (L >= 128 ? 4 : 3) : 0;
+    static constexpr int PITCH = SH ? L + (L >> SH) : L + 1;
+    static __device__ __forceinline__ int at(int c, int p) { return c * PITCH + (SH ? p + (p >> SH) : p); }
     static constexpr int size(int) { return W * PITCH; }
 };
 

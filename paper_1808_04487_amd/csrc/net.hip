@@ -292,17 +292,165 @@ __global__ __launch_bounds__(kNetThreads) void k_wgrad(ConvGeom g, const __bf16 
     }
 }
 
+// Block-tiled weight gradient for grids of 32^3 and up: the same partial
+// sums as k_wgrad, reduced over the 4 x 4 x 16 voxel tiles of k_conv_tile.
+// Input channels go in slices of up to 32 (blockIdx.y selects the slice).
+// A workgroup walks a fixed set of tiles; per tile it stages
+// dz transposed ([co][voxel]) and the input tile with its one-voxel halo
+// transposed, in three copies shifted by 0, 1 and 2 voxels along x3
+// ([d3][ci][z][y][x], 16 x positions per row), so that every MFMA operand of
+// every tap is one aligned 16-byte LDS read and each staged value serves all
+// 27 taps.  The taps are split over the waves (tap t on wave t mod 8); a
+// wave's accumulators run over all tiles of its workgroup, which writes
+// them once.  Reduction chunks of 32 voxels are two 16-voxel rows of a
+// tile: lane group q = lane / 16 holds voxels 8 (q & 1) .. + 7 of row
+// 2 chunk + q / 2.
+template <int CIN, int COUT, bool UP>
+struct WgradTile {
+    static constexpr int CIH = CIN < 32 ? CIN : 32;     // input channels per workgroup
+    static constexpr int CINP = CIH < 16 ? 16 : CIH;    // staged (zero padded)
+    static constexpr int ZP = 256 + 8;       // dz row pitch (voxels)
+    static constexpr int CP = 36 * 16 + 8;   // one channel of one copy: 6 x 6 rows of 16
+    static constexpr int BYTES = 2 * (COUT * ZP + 3 * CINP * CP);
+};
+constexpr int kWgradThreads = 512;
+template <int CIN, int COUT, bool UP>
+__global__ __launch_bounds__(kWgradThreads) void k_wgrad_tile(ConvGeom g, const __bf16 *__restrict__ in,
+                                                             const __bf16 *__restrict__ dz,
+                                                             float *__restrict__ part) {
+    using TL = WgradTile<CIN, COUT, UP>;
+    constexpr int CIH = TL::CIH, CINP = TL::CINP, ZP = TL::ZP, CP = TL::CP;
+    constexpr int KPAD = conv_kpad<CIN>();
+    constexpr int NW = kWgradThreads / 64, TPW = (27 + NW - 1) / NW;
+    constexpr int NR = COUT / 16, NC = CINP / 16;
+    __shared__ __align__(16) __bf16 zs[COUT * ZP];
+    __shared__ __align__(16) __bf16 xs[3 * CINP * CP];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lg = g.lg, lgi = g.lg_in, m = (1 << lg) - 1;
+    const int tx3 = 1 << (lg - 4), tx2 = 1 << (lg - 2);
+    const int ntiles = (int)(g.V >> 8);
+    const int c0 = (int)blockIdx.y * CIH;  // first input channel of the slice
+    // padded input channels stay zero in every copy
+    if constexpr (CIH < CINP) {
+        for (int q = tid; q < 3 * (CINP - CIH) * CP; q += kWgradThreads) {
+            const int d = q / ((CINP - CIH) * CP), r = q % ((CINP - CIH) * CP);
+            xs[(d * CINP + CIH) * CP + r] = (__bf16)0.f;
+        }
+    }
+    f32x4 acc[TPW][NR][NC];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[i][r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tile = (int)blockIdx.x; tile < ntiles; tile += (int)gridDim.x) {
+        const int o3 = (tile % tx3) << 4, o2 = ((tile / tx3) % tx2) << 2, o1 = (tile / (tx3 * tx2)) << 2;
+        __syncthreads();  // the previous tile's LDS reads are done
+        // 1. dz of the tile's voxel v = (z 4 + y) 16 + x, channel-major
+        for (int q = tid; q < 256 * (COUT / 8); q += kWgradThreads) {
+            const int v = q / (COUT / 8), cg = q % (COUT / 8);
+            const unsigned src = ((unsigned)(o1 + (v >> 6)) << (2 * lg)) | ((unsigned)(o2 + ((v >> 4) & 3)) << lg) |
+                                 (unsigned)(o3 + (v & 15));
+            const bf16x8 val = *reinterpret_cast<const bf16x8 *>(dz + (size_t)src * COUT + 8 * cg);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) zs[(8 * cg + k) * ZP + v] = val[k];
+        }
+        // 2. halo voxel (z, y, x), x < 18, is input voxel (o1, o2, o3) + (z, y, x) - 1
+        //    (wrapped; its coarse parent when upsampled); copy d holds it at x - d
+        for (int q = tid; q < 648 * (CIH / 8); q += kWgradThreads) {
+            const int vox = q / (CIH / 8), cg = q % (CIH / 8);
+            const int z = vox / 108, y = (vox / 18) % 6, x = vox % 18;
+            int f1 = (o1 - 1 + z) & m, f2 = (o2 - 1 + y) & m, f3 = (o3 - 1 + x) & m;
+            if (UP) {
+                f1 >>= 1;
+                f2 >>= 1;
+                f3 >>= 1;
+            }
+            const unsigned src = ((unsigned)f1 << (2 * lgi)) | ((unsigned)f2 << lgi) | (unsigned)f3;
+            const bf16x8 val = *reinterpret_cast<const bf16x8 *>(in + (size_t)src * CIN + c0 + 8 * cg);
+            const int row = (z * 6 + y) * 16;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int xd = x - d;
+                if (xd >= 0 && xd < 16) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) xs[(d * CINP + 8 * cg + k) * CP + row + xd] = val[k];
+                }
+            }
+        }
+        __syncthreads();
+        // 3. per reduction chunk: the A fragments (dz) once, then every tap of the wave
+        const int q4 = lane >> 4, l16 = lane & 15;
+#pragma unroll 2
+        for (int ch = 0; ch < 8; ++ch) {
+            const int r = 2 * ch + (q4 >> 1), z = r >> 2, y = r & 3, xh = 8 * (q4 & 1);
+            bf16x8 a[NR];
+#pragma unroll
+            for (int tr = 0; tr < NR; ++tr)
+                a[tr] = *reinterpret_cast<const bf16x8 *>(zs + (16 * tr + l16) * ZP + 32 * ch + 8 * q4);
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+                const int t = wave + NW * i;
+                if (t < 27) {  // uniform per wave
+                    const int d1 = t / 9, d2 = (t / 3) % 3, d3 = t % 3;
+                    const __bf16 *xb = xs + (d3 * CINP + l16) * CP + ((z + d1) * 6 + (y + d2)) * 16 + xh;
+#pragma unroll
+                    for (int tc = 0; tc < NC; ++tc) {
+                        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(xb + 16 * tc * CP);
+#pragma unroll
+                        for (int tr = 0; tr < NR; ++tr) acc[i][tr][tc] = mfma16(a[tr], b, acc[i][tr][tc]);
+                    }
+                }
+            }
+        }
+    }
+    // 4. partials of this workgroup: D row 4 (lane / 16) + k is co, column lane % 16 is ci
+    float *out = part + (size_t)blockIdx.x * COUT * KPAD;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + NW * i;
+        if (t < 27) {
+#pragma unroll
+            for (int tr = 0; tr < NR; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NC; ++tc) {
+                    const int ci = 16 * tc + (lane & 15);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int co = 16 * tr + 4 * (lane >> 4) + k;
+                        if (ci < CIH) out[(size_t)co * KPAD + t * CIN + c0 + ci] = acc[i][tr][tc][k];
+                    }
+                }
+        }
+    }
+}
+
 // grad[co][tap][ci] (flat, ci < cin_f) += sum_b part[b][co][tap cin_k + ci]
-__global__ void k_wgrad_finish(int nblk, int cin_k, int cin_f, int cout, int kpad, const float *__restrict__ part,
-                               float *__restrict__ grad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// A workgroup takes 32 outputs; its 8 thread rows sum consecutive eighths
+// of the partials, which are then added in row order.
+__global__ __launch_bounds__(kNetThreads) void k_wgrad_finish(int nblk, int cin_k, int cin_f, int cout, int kpad,
+                                                              const float *__restrict__ part,
+                                                              float *__restrict__ grad) {
+    __shared__ float red[kNetThreads];
+    const int o = (int)threadIdx.x & 31, seg = (int)threadIdx.x >> 5;
+    const int j = (int)blockIdx.x * 32 + o;
     const int per = 27 * cin_f;
-    if (j >= cout * per) return;
-    const int co = j / per, r = j % per, tap = r / cin_f, ci = r % cin_f;
-    const size_t src = (size_t)co * kpad + tap * cin_k + ci;
+    const int len = (nblk + 7) / 8, b0 = seg * len, b1 = b0 + len < nblk ? b0 + len : nblk;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * cout * kpad + src];
-    grad[j] += s;
+    if (j < cout * per) {
+        const int co = j / per, r = j % per, tap = r / cin_f, ci = r % cin_f;
+        const size_t src = (size_t)co * kpad + tap * cin_k + ci;
+        for (int b = b0; b < b1; ++b) s += part[(size_t)b * cout * kpad + src];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (seg == 0 && j < cout * per) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += red[32 * q + o];
+        grad[j] += t;
+    }
 }
 
 // Packed MFMA weights from the flat FP32 vector: W[co][tap cin_k + ci] (zero
@@ -418,12 +566,22 @@ __global__ __launch_bounds__(kNetThreads) void k_mask(unsigned total, int C, flo
 }
 
 // grad[c] += sum_b part[b][c]
-__global__ void k_rows_finish(int nblk, int C, const float *__restrict__ part, float *__restrict__ grad) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+// One workgroup per column c (kNetThreads threads): thread t sums rows
+// t, t + 256, ..., then a fixed-order tree over the threads.
+__global__ __launch_bounds__(kNetThreads) void k_rows_finish(int nblk, int C, const float *__restrict__ part,
+                                                             float *__restrict__ grad) {
+    __shared__ float red[kNetThreads];
+    const int c = (int)blockIdx.x, t = (int)threadIdx.x;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * C + c];
-    grad[c] += s;
+    for (int b = t; b < nblk; b += kNetThreads) s += part[(size_t)b * C + c];
+    red[t] = s;
+    __syncthreads();
+#pragma unroll
+    for (int h = kNetThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) grad[c] += red[0];
 }
 
 // Pointwise head: out[c][v] = sum_k W[c][k] in[v][k] + b[c]   (3 outputs, FP32 weights)
@@ -460,19 +618,43 @@ __global__ void k_head_bwd(unsigned V, int C, const float *__restrict__ dy, cons
 
 // Head weight gradient, per block over a voxel range: part[blk][p] for
 // p < 3C: sum_v dy[p / C][v] in[v][p % C]; p = 3C + c: sum_v dy[c][v].
-__global__ void k_head_wgrad(unsigned V, int C, unsigned vpb, const float *__restrict__ dy,
-                             const __bf16 *__restrict__ in, float *__restrict__ part) {
+// Thread tid owns channel k = tid % C and the voxels v0 + tid / C + j (256 / C)
+// of its workgroup's range; a fixed-order sum over the voxel lanes follows.
+__global__ __launch_bounds__(kNetThreads) void k_head_wgrad(unsigned V, int C, unsigned vpb,
+                                                            const float *__restrict__ dy,
+                                                            const __bf16 *__restrict__ in,
+                                                            float *__restrict__ part) {
+    __shared__ float red[6][kNetThreads];
+    const int tid = (int)threadIdx.x, k = tid % C, lanes = kNetThreads / C, vs = tid / C;
     const unsigned v0 = blockIdx.x * vpb, v1 = v0 + vpb < V ? v0 + vpb : V;
-    for (int p = threadIdx.x; p < 3 * C + 3; p += blockDim.x) {
-        float s = 0.f;
-        if (p < 3 * C) {
-            const int c = p / C, k = p % C;
-            for (unsigned v = v0; v < v1; ++v) s += dy[(size_t)c * V + v] * (float)in[(size_t)v * C + k];
-        } else {
-            const int c = p - 3 * C;
-            for (unsigned v = v0; v < v1; ++v) s += dy[(size_t)c * V + v];
+    float w0 = 0.f, w1 = 0.f, w2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    if (vs < lanes) {
+        for (unsigned v = v0 + (unsigned)vs; v < v1; v += (unsigned)lanes) {
+            const float a = (float)in[(size_t)v * C + k];
+            const float y0 = dy[v], y1 = dy[(size_t)V + v], y2 = dy[2 * (size_t)V + v];
+            w0 += y0 * a;
+            w1 += y1 * a;
+            w2 += y2 * a;
+            b0 += y0;
+            b1 += y1;
+            b2 += y2;
         }
-        part[(size_t)blockIdx.x * (3 * C + 3) + p] = s;
+    }
+    red[0][tid] = w0;
+    red[1][tid] = w1;
+    red[2][tid] = w2;
+    red[3][tid] = b0;
+    red[4][tid] = b1;
+    red[5][tid] = b2;
+    __syncthreads();
+    float *out = part + (size_t)blockIdx.x * (3 * C + 3);
+    for (int p = tid; p < 3 * C + 3; p += kNetThreads) {
+        // weights: (c, k) summed over the voxel lanes of channel k; biases:
+        // output c summed over the voxel lanes of channel 0
+        const int q = p < 3 * C ? p / C : 3 + (p - 3 * C), kk = p < 3 * C ? p % C : 0;
+        float sum = 0.f;
+        for (int l = 0; l < lanes; ++l) sum += red[q][l * C + kk];
+        out[p] = sum;
     }
 }
 
@@ -612,31 +794,48 @@ inline void wgrad_blocks(unsigned V, int *nblk, unsigned *vpb) {
     *vpb = per * kWgradVB;
     *nblk = (int)((V + *vpb - 1) / *vpb);
 }
+// The block-tiled weight gradient on grids of 32^3 and up whose staging fits
+// the LDS; k_wgrad otherwise, or always with MIREG_WGRAD_TILE=0 in the
+// environment.  *nb: the number of partial rows written (the tiled kernel
+// uses at most one row per tile).
+inline bool wgrad_tile_enabled() {
+    const char *e = getenv("MIREG_WGRAD_TILE");
+    return !(e && e[0] == '0');
+}
 template <int CIN, int COUT, bool UP>
-void wgrad_go(ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s) {
-    int nb;
+void wgrad_go(ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s, int *nb) {
     unsigned vpb;
-    wgrad_blocks(g.V, &nb, &vpb);
-    hipLaunchKernelGGL((k_wgrad<CIN, COUT, UP>), dim3(nb), dim3(kNetThreads), 0, s, g, in, dz, vpb, part);
+    wgrad_blocks(g.V, nb, &vpb);
+    using TL = WgradTile<CIN, COUT, UP>;
+    if constexpr (CIN % 8 == 0 && TL::BYTES <= 160 * 1024) {
+        const unsigned tiles = g.V >> 8;
+        if (g.lg >= 5 && wgrad_tile_enabled()) {
+            if (tiles < (unsigned)*nb) *nb = (int)tiles;
+            hipLaunchKernelGGL((k_wgrad_tile<CIN, COUT, UP>), dim3(*nb, CIN / TL::CIH), dim3(kWgradThreads), 0, s, g,
+                               in, dz, part);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT, UP>), dim3(*nb), dim3(kNetThreads), 0, s, g, in, dz, vpb, part);
 }
 template <int CIN, bool UP>
-bool wgrad_co(int cout, ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s) {
+bool wgrad_co(int cout, ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s, int *nb) {
     switch (cout) {
-        case 16: wgrad_go<CIN, 16, UP>(g, in, dz, part, s); return true;
-        case 32: wgrad_go<CIN, 32, UP>(g, in, dz, part, s); return true;
-        case 64: wgrad_go<CIN, 64, UP>(g, in, dz, part, s); return true;
-        case 128: wgrad_go<CIN, 128, UP>(g, in, dz, part, s); return true;
+        case 16: wgrad_go<CIN, 16, UP>(g, in, dz, part, s, nb); return true;
+        case 32: wgrad_go<CIN, 32, UP>(g, in, dz, part, s, nb); return true;
+        case 64: wgrad_go<CIN, 64, UP>(g, in, dz, part, s, nb); return true;
+        case 128: wgrad_go<CIN, 128, UP>(g, in, dz, part, s, nb); return true;
         default: return false;
     }
 }
 template <bool UP>
-bool wgrad(int cin, int cout, ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s) {
+bool wgrad(int cin, int cout, ConvGeom g, const __bf16 *in, const __bf16 *dz, float *part, hipStream_t s, int *nb) {
     switch (cin) {
-        case 8: return wgrad_co<8, UP>(cout, g, in, dz, part, s);
-        case 16: return wgrad_co<16, UP>(cout, g, in, dz, part, s);
-        case 32: return wgrad_co<32, UP>(cout, g, in, dz, part, s);
-        case 64: return wgrad_co<64, UP>(cout, g, in, dz, part, s);
-        case 128: return wgrad_co<128, UP>(cout, g, in, dz, part, s);
+        case 8: return wgrad_co<8, UP>(cout, g, in, dz, part, s, nb);
+        case 16: return wgrad_co<16, UP>(cout, g, in, dz, part, s, nb);
+        case 32: return wgrad_co<32, UP>(cout, g, in, dz, part, s, nb);
+        case 64: return wgrad_co<64, UP>(cout, g, in, dz, part, s, nb);
+        case 128: return wgrad_co<128, UP>(cout, g, in, dz, part, s, nb);
         default: return false;
     }
 }
@@ -786,22 +985,20 @@ int mask(mireg_net *net, int level, int C, float *g, const __bf16 *act, float *b
     if (nb > 1024) nb = 1024;
     // the bias partials reuse the weight-gradient partial buffer
     hipLaunchKernelGGL(k_mask, dim3(nb), dim3(kNetThreads), 0, net->stream, total, C, g, act, net->dz16, net->part);
-    hipLaunchKernelGGL(k_rows_finish, dim3(1), dim3(128), 0, net->stream, (int)nb, C, net->part, bgrad);
+    hipLaunchKernelGGL(k_rows_finish, dim3(C), dim3(kNetThreads), 0, net->stream, (int)nb, C, net->part, bgrad);
     return MIREG_OK;
 }
 
 int conv_wgrad(mireg_net *net, int l, int level, bool up, const __bf16 *in) {
     const NetConv &c = net->L[l];
     const ConvGeom g = net->geom(level, up);
-    const bool ok = up ? wgrad<true>(c.cin_k, c.cout, g, in, net->dz16, net->part, net->stream)
-                       : wgrad<false>(c.cin_k, c.cout, g, in, net->dz16, net->part, net->stream);
+    int nb = 0;
+    const bool ok = up ? wgrad<true>(c.cin_k, c.cout, g, in, net->dz16, net->part, net->stream, &nb)
+                       : wgrad<false>(c.cin_k, c.cout, g, in, net->dz16, net->part, net->stream, &nb);
     if (!ok) return net->fail(MIREG_E_ARG, "unsupported channels %d -> %d", c.cin_k, c.cout);
-    int nb;
-    unsigned vpb;
-    wgrad_blocks(g.V, &nb, &vpb);
     const int n = c.cout * 27 * c.cin_f;
-    hipLaunchKernelGGL(k_wgrad_finish, dim3(nblocks(n)), dim3(kNetThreads), 0, net->stream, nb, c.cin_k, c.cin_f,
-                       c.cout, c.kpad, net->part, net->G + c.woff);
+    hipLaunchKernelGGL(k_wgrad_finish, dim3((unsigned)(n + 31) / 32), dim3(kNetThreads), 0, net->stream, nb, c.cin_k,
+                       c.cin_f, c.cout, c.kpad, net->part, net->G + c.woff);
     return MIREG_OK;
 }
 
@@ -816,11 +1013,11 @@ int conv_bwd_data(mireg_net *net, int l, int level) {
 int head_backward(mireg_net *net, unsigned V, int C, const float *dy, const __bf16 *in, size_t off, float *dx) {
     hipStream_t s = net->stream;
     hipLaunchKernelGGL(k_head_bwd, dim3(nblocks((size_t)V * C)), dim3(kNetThreads), 0, s, V, C, dy, net->P + off, dx);
-    unsigned nb = V < 256 ? V : 256;
+    unsigned nb = V / 64 < 1024 ? (V / 64 > 0 ? V / 64 : 1) : 1024;
     const unsigned vpb = (V + nb - 1) / nb;
     nb = (V + vpb - 1) / vpb;
     hipLaunchKernelGGL(k_head_wgrad, dim3(nb), dim3(kNetThreads), 0, s, V, C, vpb, dy, in, net->part);
-    hipLaunchKernelGGL(k_rows_finish, dim3(nblocks(3 * C + 3)), dim3(kNetThreads), 0, s, (int)nb, 3 * C + 3, net->part,
+    hipLaunchKernelGGL(k_rows_finish, dim3(3 * C + 3), dim3(kNetThreads), 0, s, (int)nb, 3 * C + 3, net->part,
                        net->G + off);
     return MIREG_OK;
 }
@@ -973,7 +1170,7 @@ int mireg_net_create(const mireg_net_config *cfg, void *stream, mireg_net **out)
         part = part > (size_t)nb * L.cout * L.kpad ? part : (size_t)nb * L.cout * L.kpad;
     }
     part = part > (size_t)1024 * 128 ? part : (size_t)1024 * 128;
-    part = part > (size_t)256 * (3 * 128 + 3) ? part : (size_t)256 * (3 * 128 + 3);
+    part = part > (size_t)1024 * (3 * 128 + 3) ? part : (size_t)1024 * (3 * 128 + 3);
     if (!rc) rc = net_alloc(net, &net->du, du);
     if (!rc) rc = net_alloc(net, &net->dz16, dz);
     if (!rc) rc = net_alloc(net, &net->part, part);

@@ -87,6 +87,60 @@ def test_tiled_convolutions_equal_the_gather_kernel(monkeypatch):
     assert l1 == l0 and np.array_equal(g1, np.asarray(g0))
 
 
+def test_tiled_weight_gradient_matches_the_chunked_kernel(monkeypatch):
+    """At 64^3 the weight gradients of the 64^3 and 32^3 levels (enc0, dec0,
+    enc1, dec1; dec1 in two input-channel slices) run the block-tiled
+    kernel; with MIREG_WGRAD_TILE=0 they run the per-tap chunked kernel.  The
+    two sum the same products in other voxel orders (FP32 accumulation), so
+    those layers agree to rounding and every other layer is identical."""
+    need_gpu()
+    n, ch = 64, (16, 32, 64, 128)
+    net, theta, _, (mT_t, mR_t, vt_t) = setup(n, ch, seed=8)
+    l1, g1 = net.loss_grad(mT_t, mR_t, vt_t)
+    g1 = np.array(g1, copy=True)
+    monkeypatch.setenv("MIREG_WGRAD_TILE", "0")
+    l0, g0 = net.loss_grad(mT_t, mR_t, vt_t)
+    g0 = np.asarray(g0)
+    assert l1 == l0
+    o = 0
+    for name, ci, co, t in onet.layers(ch):
+        size = co * t * ci
+        e = rel_l2(g1[o:o + size], g0[o:o + size].astype(np.float64))
+        print("  wgrad %-6s tiled vs chunked %.2e" % (name, e), flush=True)
+        if name in ("enc0", "dec0", "enc1", "dec1"):
+            assert 0 < e < 1e-4, (name, e)
+        else:
+            assert np.array_equal(g1[o:o + size], g0[o:o + size]), name
+        o += size + co
+
+
+def test_gradient_matches_oracle_at_full_size():
+    """128^3 with the production channels against the oracle's BF16 storage
+    model, layer by layer: block-tiled convolutions on the 128^3 and 64^3
+    levels, block-tiled weight gradients on the 128^3, 64^3 and 32^3 levels
+    (input channels in slices of 32 above 32), the chunked kernel at 16^3."""
+    need_gpu()
+    n, ch = 128, (16, 32, 64, 128)
+    net, theta, (mT, mR, vt), (mT_t, mR_t, vt_t) = setup(n, ch, seed=4)
+    loss, g = net.loss_grad(mT_t, mR_t, vt_t)
+    g = np.array(g, copy=True)
+    O = onet.Net(n, ch, 2.0)
+    print("oracle forward/backward at 128^3 ...", flush=True)
+    v16 = O.forward(theta.astype(np.float64), mT, mR, bf16=True)
+    g16 = O.backward(v16, vt, bf16=True)
+    lo = O.loss(v16, vt)
+    print("loss %.6e vs %.6e" % (loss, lo), flush=True)
+    assert abs(loss - lo) < 2e-3 * lo
+    o = 0
+    for name, ci, co, t in onet.layers(ch):
+        for part, size in (("W", co * t * ci), ("b", co)):
+            e = rel_l2(g[o:o + size], g16[o:o + size])
+            print("  grad %-6s %s %.2e" % (name, part, e), flush=True)
+            assert e < 1e-2, (name, part, e)
+            o += size
+    assert o == theta.size
+
+
 def test_adam_step_and_training_reduce_the_loss():
     """First Adam step moves each parameter by about lr sign(g); a few
     steps on one pair reduce its loss."""
