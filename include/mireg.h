@@ -201,6 +201,19 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
 int mireg_set_graphs(mireg_ctx *ctx, int on);
 int mireg_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape);
 
+/* Per-iteration log of mireg_gn_solve (the paper's solver reports, Sec. 4,
+ * list #iter, #matvecs, #PDE, mismatch and gradient norms per solve; this
+ * adds one record per GN iteration).  path (host string) is opened for
+ * appending; NULL or "" closes the log.  Each GN iteration appends one JSON
+ * object on its own line, after its line search: {"event": "gn", "iter",
+ * "J", "gnorm", "gnorm_rel" (at the iterate the step starts from), "eps_h",
+ * "pcg_iters", "pcg_status", "pcg_matvecs", "slope" (<g, step>), "alpha"
+ * (last step length tried), "accepted", "J_trial", and the running totals
+ * "matvecs", "pde_solves", "ls_trials", "seconds"}; the solve ends with
+ * {"event": "done", ...} carrying the fields of mireg_report.  The lockstep
+ * batch solve writes no log.  MIREG_E_ARG if the file cannot be opened. */
+int mireg_set_log_jsonl(mireg_ctx *ctx, const char *path);
+
 /* PCG (Algorithm "inner iteration") for H x = rhs at the current v, x0 = 0;
  * stops when ||r|| <= rtol ||rhs|| (*status = MIREG_CONVERGED_REL, also for
  * rhs = 0), after maxit iterations (MIREG_MAXIT), or on non-positive

@@ -151,6 +151,8 @@ struct mireg_ctx {
     long long vel_version = 0, coarse_vel_version = -1;
     bool coarse_images = false;
     long long coarse_matvecs = 0;
+    // JSON-lines log of the GN iterations (mireg_set_log_jsonl), or null
+    FILE *jlog = nullptr;
     // PCG's matvec replayed from a captured graph (per velocity and buffers)
     bool use_graphs = false;
     hipStream_t cap_stream = nullptr;
@@ -1066,10 +1068,11 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
         R.neg_curv += pst == MIREG_NEG_CURV;
         double slope = 0;
         if ((rc = dot_h<T>(ctx, g, vt, n, &slope))) return rc;
-        double alpha = 1.0, Jt = 0;
+        double alpha = 1.0, Jt = 0, alpha_tried = 0;
         bool accepted = false;
         for (int ls = 0; ls < o->max_ls; ++ls) {
             // trial velocity v = vk + alpha vt, written into the context velocity
+            alpha_tried = alpha;
             xpay<T>(n, vk, alpha, vt, ctx->f<T>(ctx->v), ctx->stream);
             ctx->invalidate();
             if ((rc = impl_objective<T, S>(ctx, &Jt, nullptr, nullptr))) return rc;
@@ -1081,6 +1084,15 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
             }
             alpha *= 0.5;
         }
+        if (ctx->jlog)
+            fprintf(ctx->jlog,
+                    "{\"event\": \"gn\", \"iter\": %d, \"J\": %.17g, \"gnorm\": %.17g, \"gnorm_rel\": %.17g, "
+                    "\"eps_h\": %.17g, \"pcg_iters\": %d, \"pcg_status\": %d, \"pcg_matvecs\": %d, "
+                    "\"slope\": %.17g, \"alpha\": %.17g, \"accepted\": %s, \"J_trial\": %.17g, "
+                    "\"matvecs\": %d, \"pde_solves\": %d, \"ls_trials\": %d, \"seconds\": %.6f}\n",
+                    k, J, gn, g0 > 0 ? gn / g0 : 0.0, eps_h, its, pst, mv, slope, alpha_tried, accepted ? "true" : "false",
+                    Jt, R.matvecs, R.pde_solves, R.ls_trials,
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
         if (!accepted) {
             HIP_OK(hipMemcpyAsync(ctx->v, vk, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
             ctx->invalidate();
@@ -1112,6 +1124,16 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     R.coarse_matvecs = (int)(ctx->coarse_matvecs - coarse0);
     (void)h3;
+    if (ctx->jlog) {
+        fprintf(ctx->jlog,
+                "{\"event\": \"done\", \"status\": %d, \"gn_iters\": %d, \"pcg_iters\": %d, \"matvecs\": %d, "
+                "\"coarse_matvecs\": %d, \"pde_solves\": %d, \"ls_trials\": %d, \"neg_curv\": %d, \"J0\": %.17g, "
+                "\"J\": %.17g, \"gnorm0\": %.17g, \"gnorm\": %.17g, \"gnorm_rel\": %.17g, "
+                "\"mismatch_rel\": %.17g, \"seconds\": %.6f}\n",
+                R.status, R.gn_iters, R.pcg_iters, R.matvecs, R.coarse_matvecs, R.pde_solves, R.ls_trials, R.neg_curv,
+                R.J0, R.J, R.gnorm0, R.gnorm, R.gnorm_rel, R.mismatch_rel, R.seconds);
+        fflush(ctx->jlog);
+    }
     if (rep) *rep = R;
     return check_launch(ctx);
 }
@@ -1886,6 +1908,7 @@ int mireg_destroy(mireg_ctx *ctx) {
     if (ctx->hres) hipHostFree(ctx->hres);
     if (ctx->ev0) hipEventDestroy(ctx->ev0);
     if (ctx->ev1) hipEventDestroy(ctx->ev1);
+    if (ctx->jlog) fclose(ctx->jlog);
     delete ctx;
     return MIREG_OK;
 }
@@ -1931,6 +1954,19 @@ int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
     if (ctx->pc_kind == MIREG_PC_TWO_LEVEL && !ctx->have_images)
         return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     return DISPATCH(ctx, (apply_precond<T, S>(ctx, (const T *)r, (T *)z, 1.0)));
+}
+
+int mireg_set_log_jsonl(mireg_ctx *ctx, const char *path) {
+    if (!ctx) return MIREG_E_ARG;
+    if (ctx->jlog) {
+        fclose(ctx->jlog);
+        ctx->jlog = nullptr;
+    }
+    if (path && path[0]) {
+        ctx->jlog = fopen(path, "a");
+        if (!ctx->jlog) return ctx->fail(MIREG_E_ARG, "cannot open %s for appending", path);
+    }
+    return MIREG_OK;
 }
 
 int mireg_set_graphs(mireg_ctx *ctx, int on) {

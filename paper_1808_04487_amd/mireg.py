@@ -97,6 +97,7 @@ SIGNATURES = {
     "mireg_op": ([_vp, ctypes.c_int, _vp, _vp, ctypes.c_double], ctypes.c_int),
     "mireg_set_precond": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "mireg_set_graphs": ([_vp, ctypes.c_int], ctypes.c_int),
+    "mireg_set_log_jsonl": ([_vp, ctypes.c_char_p], ctypes.c_int),
     "mireg_autotune": ([_vp, ctypes.c_int, _dp, _ip], ctypes.c_int),
     "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -244,6 +245,11 @@ class Context:
 
     def set_graphs(self, on=True):
         self._check(self.lib.mireg_set_graphs(self.h, int(bool(on))))
+
+    def set_log_jsonl(self, path=None):
+        """Append one JSON line per GN iteration of gn_solve to `path`
+        (None closes the log)."""
+        self._check(self.lib.mireg_set_log_jsonl(self.h, path.encode() if path else None))
 
     def autotune(self, reps=3):
         """Pick the fastest transport tile shape; returns (shape, ms per shape)."""
