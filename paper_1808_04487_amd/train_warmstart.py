@@ -10,6 +10,14 @@ and --steps 0 only the held-out evaluation of those weights runs:
 
   python -m paper_1808_04487_amd.train_warmstart --init paper_1808_04487_amd/weights/warmstart_128.npz \
       --pairs 0 --steps 0 --eval 256 --report eval.json
+
+With --sizes (a comma list of training-set sizes) the pairs are generated
+once, for the largest size, and a fresh network is trained on the first
+`size` of them for each size (same steps, learning rate and seed) and
+evaluated on the same held-out pairs; no weights are saved:
+
+  python -m paper_1808_04487_amd.train_warmstart --sizes 256,1024,3072 --steps 6000 --eval 128 \
+      --report sizes.json
 """
 import argparse
 import json
@@ -71,6 +79,44 @@ def summary(rows):
             "fallbacks": int(sum(not r["used"] for r in rows))}
 
 
+def train(net, pairs, steps, batch, lr0, seed):
+    t0 = last = time.perf_counter()
+    rng = np.random.default_rng(seed)
+    loss = float("nan")
+    for s in range(steps):
+        lr = lr0 * 0.5 * (1.0 + np.cos(np.pi * s / steps))  # cosine decay
+        idx = rng.choice(len(pairs), size=batch, replace=False)
+        loss = net.train_step([pairs[i] for i in idx], lr)
+        if time.perf_counter() - last > 10 or s == steps - 1:
+            last = time.perf_counter()
+            log("step %d/%d loss %.4e lr %.2e (%.1f s)" % (s + 1, steps, loss, lr, last - t0))
+    return loss, time.perf_counter() - t0
+
+
+def size_study(args, ctx):
+    sizes = sorted(int(x) for x in args.sizes.split(","))
+    net = warmstart.WarmStartNet(args.n)
+    t0 = time.perf_counter()
+    pairs = generate(net, ctx, range(sizes[-1]))
+    t_gen = time.perf_counter() - t0
+    out = {"args": vars(args), "generate_s": t_gen, "sizes": []}
+    for size in sizes:
+        net.set_params(warmstart.init_params(warmstart.CHANNELS, args.seed))
+        log("training on %d pairs" % size)
+        loss, t_train = train(net, pairs[:size], args.steps, args.batch, args.lr, args.seed)
+        rows = evaluate(net, ctx, range(HELD_OUT_SEED, HELD_OUT_SEED + args.eval))
+        summ = summary(rows)
+        summ.update({"train_pairs": size, "final_train_loss": loss, "train_s": t_train,
+                     "gn_ratio": summ["plain_gn_mean"] / summ["warm_gn_mean"],
+                     "matvec_ratio": summ["plain_matvecs_mean"] / summ["warm_matvecs_mean"],
+                     "time_ratio": summ["plain_s_mean"] / summ["warm_s_mean"]})
+        log("size %d: %s" % (size, json.dumps(summ)))
+        out["sizes"].append(summ)
+    if args.report:
+        json.dump(out, open(args.report, "w"), indent=1)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--n", type=int, default=128)
@@ -83,8 +129,12 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(warmstart.WEIGHTS_DIR, "warmstart_128.npz"))
     ap.add_argument("--report", default=None, help="JSON file for the evaluation")
     ap.add_argument("--init", default=None, help="start from these weights (with --steps 0: evaluate them only)")
+    ap.add_argument("--sizes", default=None, help="comma list of training-set sizes to compare (no weights saved)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if args.sizes:
+        ctx = warmstart.registration_context(args.n)
+        return size_study(args, ctx)
     if args.init:
         net = warmstart.WarmStartNet.load(args.init)
         if net.n != args.n:
@@ -95,16 +145,8 @@ def main(argv=None):
     ctx = warmstart.registration_context(args.n)
     log("network %d parameters, n = %d" % (net.param_count, args.n))
     pairs = generate(net, ctx, range(args.pairs))
-    t0 = time.perf_counter()
-    rng = np.random.default_rng(args.seed)
-    last = t0
-    for s in range(args.steps):
-        lr = args.lr * 0.5 * (1.0 + np.cos(np.pi * s / args.steps))  # cosine decay
-        idx = rng.choice(len(pairs), size=args.batch, replace=False)
-        loss = net.train_step([pairs[i] for i in idx], lr)
-        if time.perf_counter() - last > 10 or s == args.steps - 1:
-            last = time.perf_counter()
-            log("step %d/%d loss %.4e lr %.2e (%.1f s)" % (s + 1, args.steps, loss, lr, last - t0))
+    if args.steps > 0:
+        train(net, pairs, args.steps, args.batch, args.lr, args.seed)
     if args.steps > 0:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         net.save(args.out)
