@@ -272,7 +272,8 @@ def precision_variant(args, torch, mireg, n, mT, mR, v_true, probe, plain):
 
 def batched_eval(args, torch, mireg):
     """Uneven batch: sequential (one stream, eager) vs batched (4 streams,
-    graphs, autotuner) vs lockstep (all pairs in one batch: one launch per
+    graphs, autotuner) vs hybrid (the same, with the 64^3 pairs in lockstep
+    groups of 8) vs lockstep (all pairs in one batch: one launch per
     transport step across them); each configuration runs once untimed first."""
     from paper_1808_04487_amd import batch
 
@@ -282,7 +283,8 @@ def batched_eval(args, torch, mireg):
                        "amplitude U[0.05, 0.2] 2 pi; H1-div beta_v=5e-3, eps_g=5e-2", "pairs": len(sizes),
            "points": int(sum(n ** 3 for n in sizes))}
     for key, kw in (("sequential", dict(workers=1, graphs=False, autotune=False)),
-                    ("batched", dict(workers=4, graphs=True, autotune=True))):
+                    ("batched", dict(workers=4, graphs=True, autotune=True)),
+                    ("hybrid", dict(workers=4, graphs=True, autotune=True, lockstep={64: 8}))):
         bs = batch.BatchSolver(**kw)
         bs.solve(pairs, grad_rtol=5e-2)
         res, wall = bs.solve(pairs, grad_rtol=5e-2)
@@ -293,6 +295,7 @@ def batched_eval(args, torch, mireg):
                                                                    for r, p in zip(res, pairs)) / wall, 1)}
         log(args, "%s: %.3f s for %d pairs" % (key, wall, len(sizes)))
     out["speedup"] = round(out["sequential"]["wall_s"] / out["batched"]["wall_s"], 3)
+    out["hybrid"]["speedup"] = round(out["sequential"]["wall_s"] / out["hybrid"]["wall_s"], 3)
     # lockstep: one context per pair on one stream; each transport step of the
     # Hessian matvec is one launch across all running pairs, each Krylov pass
     # one launch per grid size, one PCG read-back per iteration for all

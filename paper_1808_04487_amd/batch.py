@@ -9,6 +9,17 @@ captured HIP graph and picks its transport tile shape with the autotuner
 after its first solve; neither changes a result bit, so a batched solve
 returns exactly what solving the pairs one by one returns.
 
+With `lockstep={n: g}` the pairs of grid n are solved in groups of g by
+the lockstep batch (`mireg.Batch`: one transport launch per step and one
+Krylov pass per grid size for the whole group), each group as one job of
+a worker; other sizes keep one pair per job.  Small grids gain (a 64^3
+launch is latency-bound, and a group of 8 still fits the 256 MB
+last-level cache step by step); large ones lose, as every lockstep kernel
+then streams the fields of all members and the next kernel finds none of
+them cached.  Lockstep FP32 results agree with the single-pair ones to
+rounding, not bit for bit, and the contexts of a group keep the default
+transport tile shape (the autotuner runs only on single-pair jobs).
+
 The uneven batch: 16 pairs at 64^3, 16 at 96^3, 12 at 128^3 and 4 at 160^3,
 in that order.  Pair p has its phantom from seed 100 + 2p (periodic Voronoi,
 120 seeds, Gaussian of 2 cells, rescaled to [0, 1]) and its velocity from
@@ -53,14 +64,18 @@ def make_pairs(sizes, device=None):
 
 
 class BatchSolver:
-    """Solve lists of (mT, mR) pairs with `workers` concurrent streams."""
+    """Solve lists of (mT, mR) pairs with `workers` concurrent streams;
+    `lockstep` ({grid points per axis: group size}) groups pairs of those
+    sizes into lockstep batches."""
 
-    def __init__(self, workers=4, graphs=True, autotune=True, device=None, **solver):
+    def __init__(self, workers=4, graphs=True, autotune=True, device=None, lockstep=None, **solver):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workers, self.graphs, self.tune = int(workers), bool(graphs), bool(autotune)
+        self.lockstep = {int(k): int(v) for k, v in (lockstep or {}).items() if int(v) > 1}
         self.solver = dict(SOLVER, **solver)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.workers)]
         self.ctxs = [dict() for _ in range(self.workers)]
+        self.groups = [dict() for _ in range(self.workers)]
         self.tuned = {}
 
     def _context(self, w, n):
@@ -73,21 +88,49 @@ class BatchSolver:
             self.ctxs[w][n] = c
         return c
 
+    def _group(self, w, n, g):
+        """Worker w's lockstep batch of g contexts for grid n (its stream)."""
+        key = (n, g)
+        b = self.groups[w].get(key)
+        if b is None:
+            with torch.cuda.device(self.device), torch.cuda.stream(self.streams[w]):
+                cs = [mireg.Context(n, dtype=torch.float32, device=self.device, **self.solver) for _ in range(g)]
+            b = (cs, mireg.Batch(cs))
+            self.groups[w][key] = b
+        return b
+
+    def _jobs(self, pairs):
+        """Lists of pair indices, largest work first: same-size groups for
+        the lockstep sizes, single pairs otherwise."""
+        by_n = {}
+        for i, p in enumerate(pairs):
+            by_n.setdefault(tuple(p[0].shape), []).append(i)
+        jobs = []
+        for n, idx in by_n.items():
+            g = self.lockstep.get(n[0], 1) if n[0] == n[1] == n[2] else 1
+            jobs += [idx[k:k + g] for k in range(0, len(idx), g)]
+        jobs.sort(key=lambda j: -sum(pairs[i][0].numel() for i in j))
+        return jobs
+
     def solve(self, pairs, **gn_opts):
         """Returns [(v, report)] in the order of `pairs` and the wall time."""
         results = [None] * len(pairs)
-        order = sorted(range(len(pairs)), key=lambda i: -pairs[i][0].numel())
+        jobs = self._jobs(pairs)
         todo = queue.Queue()
-        for i in order:
-            todo.put(i)
+        for j in jobs:
+            todo.put(j)
         errors = []
         producer = torch.cuda.current_stream(self.device)
         # Every context exists before the workers start: creating one (device
         # allocations, uploads) while another worker captures its matvec graph
         # could invalidate that capture.
-        for n in sorted({tuple(p[0].shape) for p in pairs}):
+        for j in jobs:
+            n = tuple(pairs[j[0]][0].shape)
             for w in range(self.workers):
-                self._context(w, n)
+                if len(j) > 1:
+                    self._group(w, n, len(j))
+                else:
+                    self._context(w, n)
 
         def work(w):
             try:
@@ -96,11 +139,20 @@ class BatchSolver:
                 with torch.cuda.device(self.device), torch.cuda.stream(s):
                     while True:
                         try:
-                            i = todo.get_nowait()
+                            j = todo.get_nowait()
                         except queue.Empty:
                             return
+                        n = tuple(pairs[j[0]][0].shape)
+                        if len(j) > 1:
+                            cs, B = self.groups[w][(n, len(j))]
+                            for c, i in zip(cs, j):
+                                c.set_images(*pairs[i])
+                            vs, reps = B.gn_solve(**gn_opts)
+                            for i, v, rep in zip(j, vs, reps):
+                                results[i] = (v, rep)
+                            continue
+                        i = j[0]
                         mT, mR = pairs[i]
-                        n = tuple(mT.shape)
                         ctx = self.ctxs[w][n]
                         ctx.set_images(mT, mR)
                         v, rep = ctx.gn_solve(**gn_opts)
@@ -124,7 +176,13 @@ class BatchSolver:
         return results, wall
 
     def close(self):
+        for d in self.groups:
+            for cs, B in d.values():
+                B.close()
+                for c in cs:
+                    c.close()
         for d in self.ctxs:
             for c in d.values():
                 c.close()
         self.ctxs = [dict() for _ in range(self.workers)]
+        self.groups = [dict() for _ in range(self.workers)]

@@ -117,6 +117,34 @@ REPORT_KEYS = ("status", "gn_iters", "matvecs", "pde_solves", "pcg_iters", "ls_t
                "mismatch_rel", "gnorm0", "gnorm", "gnorm_rel")  # printed in the oracle comparison
 
 
+def test_hybrid_batch_matches_single_solves():
+    """Worker streams with same-size pairs grouped into lockstep batches
+    (here the 32^3 pairs in groups of 3, the rest one pair per job) against
+    the pairs solved one by one: single-pair jobs bit for bit, grouped pairs
+    to the FP32 lockstep bounds (same status and J0, iterations within one,
+    J and relative mismatch within 1e-2)."""
+    need_gpu()
+    sizes = [32, 48, 32, 32, 16, 32, 32, 32]
+    pairs = batch.make_pairs(sizes)
+    seq = batch.BatchSolver(workers=1, graphs=False, autotune=False)
+    ref, _ = seq.solve(pairs, grad_rtol=5e-2)
+    seq.close()
+    hyb = batch.BatchSolver(workers=2, graphs=True, autotune=False, lockstep={32: 3})
+    assert sorted(len(j) for j in hyb._jobs(pairs)) == [1, 1, 3, 3]
+    got, _ = hyb.solve(pairs, grad_rtol=5e-2)
+    hyb.close()
+    for n, (v, rep), (vr, rr) in zip(sizes, got, ref):
+        print("hybrid", n, rep["gn_iters"], rep["J"], "single", rr["gn_iters"], rr["J"], flush=True)
+        assert rep["status"] == rr["status"] == mireg.CONVERGED_REL
+        if n != 32:
+            assert torch.equal(v, vr) and rep["J"] == rr["J"] and rep["matvecs"] == rr["matvecs"]
+        else:
+            assert abs(rep["gn_iters"] - rr["gn_iters"]) <= 1
+            assert rep["J0"] == rr["J0"]
+            for k in ("J", "mismatch_rel"):
+                assert abs(rep[k] - rr[k]) <= 1e-2 * abs(rr[k]), k
+
+
 def _lockstep_contexts(sizes, dtype):
     """Contexts of the given grid sizes on the current stream, each with a
     synthetic pair of its own (the paper's analytic problem at that size)."""
