@@ -193,13 +193,25 @@ int mireg_set_precond(mireg_ctx *ctx, int kind, double kappa, int max_inner);
  *   stream: with graphs on in one thread, other threads must keep their
  *   work off the null stream (mireg_create with a null stream uses it), or
  *   the capturing call fails with MIREG_E_HIP.
- * mireg_autotune: times `reps` matvecs at the current velocity with each
- *   tile shape of the transport kernels (0: 4x8x32, 1: 8x8x16, 2: 8x16x16
- *   points in x1 x x2 x x3) and keeps the fastest; ms (host, 3 values, may
- *   be NULL) receives the mean times, *shape (may be NULL) the choice.  The
- *   shapes compute identical bits.  Needs set_images; synchronises. */
+ * mireg_autotune: times `reps` PCG iterations (right-hand side: the current
+ *   velocity; setup and final transform included) with each tile shape of
+ *   the transport kernels (0: 4x8x32, 1: 8x8x16, 2: 8x16x16 points in x1 x
+ *   x2 x x3) and, for FP32 grids with 256 points along x1, each workgroup
+ *   width of the Krylov x1 passes (32 or 16 columns), and keeps the fastest
+ *   pair; ms (host, 3 values, may be NULL) receives the mean time per
+ *   iteration of each shape (its best width), *shape (may be NULL) the
+ *   chosen shape.  The shapes compute identical bits; the widths group the
+ *   FP64 partial sums of <s, H s> differently.  Needs set_images;
+ *   synchronises.
+ * mireg_get_tuning / mireg_set_tuning: the context's tile shape (0..2) and
+ *   Krylov x1 width (1: 16 columns; forced to 0 where there is only one),
+ *   e.g. to give the contexts of a lockstep batch one tuned shape; get takes
+ *   host ints (either may be NULL); set re-measures the stencil boxes of the
+ *   cached departure points; MIREG_E_ARG for values out of range. */
 int mireg_set_graphs(mireg_ctx *ctx, int on);
 int mireg_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape);
+int mireg_get_tuning(const mireg_ctx *ctx, int *tile_shape, int *x1_narrow);
+int mireg_set_tuning(mireg_ctx *ctx, int tile_shape, int x1_narrow);
 
 /* Per-iteration log of mireg_gn_solve (the paper's solver reports, Sec. 4,
  * list #iter, #matvecs, #PDE, mismatch and gradient norms per solve; this

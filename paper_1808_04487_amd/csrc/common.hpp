@@ -74,6 +74,7 @@ struct Grid {
     long long NS;    // n1 n2 k3 (complex entries of one half spectrum)
     int lds_cap;     // largest stencil box (points) staged in LDS; 0: gather from global memory
     int sl_tile;     // tile shape of the semi-Lagrangian kernels (0, 1, 2)
+    int x1_narrow;   // Krylov x1 passes on FP32 256-point lines: 16-column workgroups instead of 32
 };
 
 }  // namespace mireg

@@ -448,9 +448,9 @@ __device__ __forceinline__ T ainv_sqrt_symbol(const Mode<T> &m, const OpConst<T>
 // rows, still over a thousand workgroups per component) for FP32 lines of
 // 256 points, where they fit 128 registers without spilling; the column
 // default otherwise.
-template <typename T, int L>
+template <typename T, int L, bool NARROW = false>
 constexpr int krylov_threads() {
-    return (sizeof(T) == 4 && L == 256) ? 1024 : col_threads<T, L, 1>();
+    return (sizeof(T) == 4 && L == 256 && !NARROW) ? 1024 : col_threads<T, L, 1>();
 }
 // Launch bound: at least that of the other column passes, so the other
 // instantiations keep their register budget.
@@ -460,7 +460,8 @@ constexpr int krylov_bound() {
 }
 // SA: element type of the spectral operand a_in of KP_HESS (an FP64
 // spectrum read by an FP32 pass is rounded at the load)
-template <typename T, int L, int PASS, typename SA = T, bool TAB = false>
+// NARROW: the 16-column workgroups (Grid::x1_narrow) where 32 is the default
+template <typename T, int L, int PASS, typename SA = T, bool TAB = false, bool NARROW = false>
 __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs farg, long long Q, OpConst<T> oc,
                                                                       T mu_arg, int flags,
                                                                       const cx<T> *__restrict__ tw,
@@ -473,7 +474,7 @@ __global__ __launch_bounds__((krylov_bound<T, L>())) void k_x1_krylov(KrylovPtrs
     const bool xupd = flags & KF_XUPD;
     const T alpha = xupd ? (T)*f.alpha : (T)0;
     constexpr int V = 1;
-    constexpr int NT = krylov_threads<T, L>();
+    constexpr int NT = krylov_threads<T, L, NARROW>();
     using S = FftShape<T, L, V, NT>;
     constexpr int EPT = S::EPT, TPC = S::TPC, W = S::W;
     using Lay = LayoutCols<W>;
@@ -939,6 +940,17 @@ static void launch_x1_krylov(const Grid &g, const KrylovPtrs &f, const OpConst<T
         else                                                                                             \
             hipLaunchKernelGGL((k_x1_krylov<T, L, PASS, SA>), grid, dim3(NT), 0, s, f, Q, oc, mu, flags, tw, \
                                tab);                                                                     \
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (g.x1_narrow && g.n1 == 256 && !tab) {
+            constexpr int NT = krylov_threads<T, 256, true>();
+            constexpr int W = FftShape<T, 256, 1, NT>::W;
+            dim3 grid((unsigned)((Q + W - 1) / W), PASS == KP_HESS ? 1 : 3, np);
+            if (blocks) *blocks = (int)grid.x;
+            hipLaunchKernelGGL((k_x1_krylov<T, 256, PASS, SA, false, true>), grid, dim3(NT), 0, s, f, Q, oc, mu,
+                               flags, tw, tab);
+            return;
+        }
     }
     MIREG_SWITCH_COL(g.n1, MIREG_L)
 #undef MIREG_L

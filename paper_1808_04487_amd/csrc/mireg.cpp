@@ -779,45 +779,14 @@ void set_tile(mireg_ctx *ctx, int shape) {
     }
 }
 
-// Autotuner: mean time of `reps` matvecs at the current velocity per tile
-// shape; keeps the fastest (every shape gives the same bits).
-template <typename T, typename S = T>
-int impl_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape) {
-    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
-    ensure_state<T, S>(ctx);
-    ensure_gradm<T, S>(ctx);
-    ensure_d<T, S>(ctx);
-    ensure_Y<T, S>(ctx);
-    const long long n = 3 * ctx->N();
-    T *in = ctx->vec<T>(2), *out = ctx->vec<T>(3);
-    HIP_OK(hipMemcpyAsync(in, ctx->v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    double best = 1e300;
-    int best_shape = ctx->g.sl_tile, rc = MIREG_OK;
-    for (int sh = 0; sh < 3 && !rc; ++sh) {
-        set_tile<T, S>(ctx, sh);
-        rc = impl_matvec<T, S>(ctx, in, out);  // warm-up
-        hipEventRecord(e0, ctx->stream);
-        for (int r = 0; r < reps && !rc; ++r) rc = impl_matvec<T, S>(ctx, in, out);
-        hipEventRecord(e1, ctx->stream);
-        hipEventSynchronize(e1);
-        float t = 0;
-        hipEventElapsedTime(&t, e0, e1);
-        const double m = (double)t / reps;
-        if (ms) ms[sh] = m;
-        if (m < best) {
-            best = m;
-            best_shape = sh;
-        }
+// Krylov x1 workgroup width (16 or 32 columns on FP32 256-point lines); a
+// captured matvec holds the launches of the old width.
+void set_x1_narrow(mireg_ctx *ctx, int narrow) {
+    ctx->g.x1_narrow = narrow;
+    if (ctx->mv_exec) {
+        hipGraphExecDestroy(ctx->mv_exec);
+        ctx->mv_exec = nullptr;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (rc) return rc;
-    set_tile<T, S>(ctx, best_shape);
-    if (shape) *shape = best_shape;
-    return check_launch(ctx);
 }
 
 // The preconditioner PCG uses, with the PCG's relative tolerance eps_h.
@@ -1011,6 +980,61 @@ template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres,
              int *status = nullptr, int *matvecs = nullptr) {
     return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres, status, matvecs);
+}
+
+// Autotuner: mean time of a PCG iteration (`reps` iterations from the
+// current velocity as right-hand side, the setup and final transform
+// included) per transport tile shape and, where both exist, per Krylov x1
+// workgroup width; keeps the fastest pair.  ms[shape]: the best time of that
+// shape over the widths.  Tile shapes give identical bits; the widths group
+// the FP64 partial sums of <s, Hs> differently.
+template <typename T, typename S = T>
+int impl_autotune(mireg_ctx *ctx, int reps, double *ms, int *shape) {
+    if (!ctx->have_images) return ctx->fail(MIREG_E_STATE, "set_images has not been called");
+    ensure_state<T, S>(ctx);
+    ensure_gradm<T, S>(ctx);
+    ensure_d<T, S>(ctx);
+    ensure_Y<T, S>(ctx);
+    const long long n = 3 * ctx->N();
+    // right-hand side and iterate outside PCG's own vectors (0..3)
+    T *in = ctx->vec<T>(4), *out = ctx->vec<T>(5);
+    HIP_OK(hipMemcpyAsync(in, ctx->v, n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_shape = ctx->g.sl_tile, best_narrow = ctx->g.x1_narrow, rc = MIREG_OK;
+    const int widths = (sizeof(T) == 4 && ctx->g.n1 == 256) ? 2 : 1;
+    for (int sh = 0; sh < 3 && !rc; ++sh) {
+        set_tile<T, S>(ctx, sh);
+        double best_sh = 1e300;
+        for (int w = 0; w < widths && !rc; ++w) {
+            set_x1_narrow(ctx, w);
+            int its = 0;
+            rc = impl_pcg<T, S>(ctx, in, out, 0.0, 1, &its, nullptr);  // warm-up (and graph capture)
+            hipEventRecord(e0, ctx->stream);
+            if (!rc) rc = impl_pcg<T, S>(ctx, in, out, 0.0, reps, &its, nullptr);
+            hipEventRecord(e1, ctx->stream);
+            hipEventSynchronize(e1);
+            float t = 0;
+            hipEventElapsedTime(&t, e0, e1);
+            const double m = (double)t / (its > 0 ? its : 1);
+            if (m < best_sh) best_sh = m;
+            if (m < best) {
+                best = m;
+                best_shape = sh;
+                best_narrow = w;
+            }
+        }
+        if (ms) ms[sh] = best_sh;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    set_tile<T, S>(ctx, best_shape);
+    set_x1_narrow(ctx, best_narrow);
+    if (shape) *shape = best_shape;
+    return check_launch(ctx);
 }
 
 template <typename T, typename S = T>
@@ -1954,6 +1978,23 @@ int mireg_precond_apply(mireg_ctx *ctx, const void *r, void *z) {
     if (ctx->pc_kind == MIREG_PC_TWO_LEVEL && !ctx->have_images)
         return ctx->fail(MIREG_E_STATE, "set_images has not been called");
     return DISPATCH(ctx, (apply_precond<T, S>(ctx, (const T *)r, (T *)z, 1.0)));
+}
+
+int mireg_set_tuning(mireg_ctx *ctx, int tile_shape, int x1_narrow) {
+    if (!ctx) return MIREG_E_ARG;
+    if (tile_shape < 0 || tile_shape > 2 || (x1_narrow != 0 && x1_narrow != 1))
+        return ctx->fail(MIREG_E_ARG, "tile shape must be 0, 1 or 2 and the x1 width 0 or 1");
+    // only FP32 grids with 256-point x1 lines have a second Krylov width
+    if (ctx->p.dtype == MIREG_F64 || ctx->g.n1 != 256) x1_narrow = 0;
+    set_x1_narrow(ctx, x1_narrow);
+    return DISPATCH(ctx, (set_tile<T, S>(ctx, tile_shape), MIREG_OK));
+}
+
+int mireg_get_tuning(const mireg_ctx *ctx, int *tile_shape, int *x1_narrow) {
+    if (!ctx) return MIREG_E_ARG;
+    if (tile_shape) *tile_shape = ctx->g.sl_tile;
+    if (x1_narrow) *x1_narrow = ctx->g.x1_narrow;
+    return MIREG_OK;
 }
 
 int mireg_set_log_jsonl(mireg_ctx *ctx, const char *path) {

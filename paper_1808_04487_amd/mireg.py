@@ -98,6 +98,8 @@ SIGNATURES = {
     "mireg_set_precond": ([_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "mireg_set_graphs": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_set_log_jsonl": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "mireg_get_tuning": ([_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "mireg_set_tuning": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "mireg_autotune": ([_vp, ctypes.c_int, _dp, _ip], ctypes.c_int),
     "mireg_timers_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mireg_kernel_stats_enable": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -252,11 +254,21 @@ class Context:
         self._check(self.lib.mireg_set_log_jsonl(self.h, path.encode() if path else None))
 
     def autotune(self, reps=3):
-        """Pick the fastest transport tile shape; returns (shape, ms per shape)."""
+        """Pick the fastest transport tile shape (and Krylov x1 width where
+        there are two); returns (shape, ms per PCG iteration per shape)."""
         ms = (ctypes.c_double * 3)()
         sh = ctypes.c_int()
         self._check(self.lib.mireg_autotune(self.h, int(reps), ms, ctypes.byref(sh)))
         return sh.value, list(ms)
+
+    def tuning(self):
+        """(transport tile shape, Krylov x1 width: 1 for 16 columns)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.mireg_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_tuning(self, shape, narrow=0):
+        self._check(self.lib.mireg_set_tuning(self.h, int(shape), int(narrow)))
 
     def set_precond(self, kind, kappa=0.1, max_inner=50):
         """PC_SPECTRAL or PC_TWO_LEVEL (coarse CG to kappa times the PCG tolerance)."""

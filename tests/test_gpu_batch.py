@@ -95,6 +95,40 @@ def test_autotune_keeps_results():
     assert torch.equal(ctx.hessian_matvec(probe), before)
 
 
+def test_autotune_krylov_width_at_256():
+    """FP32 256^3: the Krylov x1 passes in 16-column workgroups give the
+    same PCG as the default 32 (same iterations; the FP64 partial sums of
+    <s, Hs> are grouped differently, so the iterates agree to rounding), the
+    matvec entry point is bit for bit the same, and the autotuner, which
+    times both widths with every tile shape, leaves the matvec unchanged."""
+    need_gpu()
+    n = 256
+    (mT, mR), = batch.make_pairs([n])
+    ctx = mireg.Context((n, n, n), dtype=torch.float32, **batch.SOLVER)
+    ctx.set_images(mT, mR)
+    noise = torch.randn((3, n, n, n), generator=torch.Generator().manual_seed(5)).cuda()
+    sm = torch.stack([ctx.op("gauss", noise[c].contiguous(), n / 8.0) for c in range(3)]).contiguous()
+    ctx.set_velocity(ctx.op("scale_maxnorm", ctx.op("leray", sm), 0.5))
+    probe = ctx.op("leray", torch.stack([ctx.op("gauss", noise[c].flip(0).contiguous(), 16.0) for c in range(3)]))
+    assert ctx.tuning() == (1, 0)
+    before = ctx.hessian_matvec(probe).clone()
+    xw, itw, _ = ctx.pcg(probe, rtol=1e-3, maxit=40)
+    ctx.set_tuning(1, 1)
+    assert ctx.tuning() == (1, 1)
+    assert torch.equal(ctx.hessian_matvec(probe), before)
+    xn, itn, _ = ctx.pcg(probe, rtol=1e-3, maxit=40)
+    e = ((xn - xw).norm() / xw.norm()).item()
+    print("pcg 32 vs 16 columns: iterations %d / %d, rel diff %.2e" % (itw, itn, e), flush=True)
+    assert itw == itn and e < 1e-5
+    shape, ms = ctx.autotune(reps=2)
+    print("autotune", shape, ms, ctx.tuning(), flush=True)
+    assert ctx.tuning()[0] == shape and ms[shape] == min(ms)
+    assert torch.equal(ctx.hessian_matvec(probe), before)
+    with pytest.raises(mireg.MiregError):
+        ctx.set_tuning(3, 0)
+    ctx.close()
+
+
 def test_batched_solves_equal_sequential():
     need_gpu()
     sizes = [32, 96, 48, 64, 48, 32, 16]  # power-of-two and radix-3 grids
