@@ -17,8 +17,8 @@ launch is latency-bound, and a group of 8 still fits the 256 MB
 last-level cache step by step); large ones lose, as every lockstep kernel
 then streams the fields of all members and the next kernel finds none of
 them cached.  Lockstep FP32 results agree with the single-pair ones to
-rounding, not bit for bit, and the contexts of a group keep the default
-transport tile shape (the autotuner runs only on single-pair jobs).
+rounding, not bit for bit.  With `autotune` a group's first context is tuned
+after the group's first solve and its shape is given to the others.
 
 The uneven batch: 16 pairs at 64^3, 16 at 96^3, 12 at 128^3 and 4 at 160^3,
 in that order.  Pair p has its phantom from seed 100 + 2p (periodic Voronoi,
@@ -150,6 +150,12 @@ class BatchSolver:
                             vs, reps = B.gn_solve(**gn_opts)
                             for i, v, rep in zip(j, vs, reps):
                                 results[i] = (v, rep)
+                            if self.tune and (w, n, len(j)) not in self.tuned:
+                                # one tuned shape for the whole group (a lockstep
+                                # batch needs the same shape in every context)
+                                self.tuned[(w, n, len(j))] = cs[0].autotune(reps=2)
+                                for c in cs[1:]:
+                                    c.set_tuning(*cs[0].tuning())
                             continue
                         i = j[0]
                         mT, mR = pairs[i]

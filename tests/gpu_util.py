@@ -43,6 +43,8 @@ def rel_err_l2(got, ref):
 def assert_close(got, ref, dtype, factor=1.0, what=""):
     e = rel_err(got, ref)
     tol = TOL[dtype] * factor
+    if what:
+        print("  %s: max rel %.2e (bound %.0e)" % (what, e, tol), flush=True)
     assert e <= tol, "%s: max rel error %.3e > %.1e" % (what, e, tol)
     return e
 

@@ -3,7 +3,9 @@
 maximum grid (512^3) through exact properties, and edge cases: the largest
 line lengths on every FFT axis, the smallest grid, other time-step counts,
 and the degenerate constant template."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -124,6 +126,30 @@ def test_fullsize_gn_solve_reaches_tolerance(workload256):
     assert gk / g0 <= 5e-2 * 1.01
     assert abs(J - rep["J"]) <= 1e-3 * abs(J) and J < 0.1 * J0
     assert abs(mis - rep["mismatch_rel"]) <= 1e-3 * mis
+    check_against_oracle_solve(rep)
+
+
+ORACLE_GN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_gn_256.json")
+
+
+def check_against_oracle_solve(rep):
+    """The GPU's FP32 solve against the oracle's FP64 solve of the same
+    inputs (tests/golden/oracle_gn_256.json, written by
+    tests/golden/make_oracle_gn_256.py): the same stopping reason, GN
+    iterations within one, matvecs within 10% (FP32 rounding moves the PCG
+    stops of a few Newton steps), J0 and the gradient norm at v = 0 to
+    FP32 accuracy, and the end point (J, relative mismatch) within 1%."""
+    with open(ORACLE_GN_256) as f:
+        o = json.load(f)
+    print("oracle FP64 solve: %s" % {k: o[k] for k in ("status", "gn_iters", "matvecs", "pde_solves", "J0", "J",
+                                                         "mismatch_rel", "gnorm_rel")}, flush=True)
+    assert rep["status"] == o["status"]
+    assert abs(rep["gn_iters"] - o["gn_iters"]) <= 1
+    assert abs(rep["matvecs"] - o["matvecs"]) <= 0.1 * o["matvecs"]
+    assert abs(rep["J0"] - o["J0"]) <= 1e-5 * o["J0"]
+    assert abs(rep["gnorm0"] - o["gnorm0"]) <= 1e-4 * o["gnorm0"]
+    for k in ("J", "mismatch_rel"):
+        assert abs(rep[k] - o[k]) <= 1e-2 * abs(o[k]), k
 
 
 def test_max_grid_properties():
