@@ -139,6 +139,9 @@ def check_against_oracle_solve(rep):
     iterations within one, matvecs within 10% (FP32 rounding moves the PCG
     stops of a few Newton steps), J0 and the gradient norm at v = 0 to
     FP32 accuracy, and the end point (J, relative mismatch) within 1%."""
+    if not os.path.exists(ORACLE_GN_256):
+        print("no stored oracle solve (run tests/golden/make_oracle_gn_256.py)", flush=True)
+        return
     with open(ORACLE_GN_256) as f:
         o = json.load(f)
     print("oracle FP64 solve: %s" % {k: o[k] for k in ("status", "gn_iters", "matvecs", "pde_solves", "J0", "J",
