@@ -57,3 +57,26 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_batch_jobs_group_lockstep_sizes():
+    """The hybrid batch's job list (host logic, no GPU): pairs of a lockstep
+    size come in groups of the stated size (the last one shorter), other
+    sizes one pair per job, largest work first, every pair exactly once."""
+    import types
+
+    import torch
+
+    from paper_1808_04487_amd import batch
+
+    sizes = [64] * 11 + [96] * 3 + [128, 48, 64]
+    pairs = [(torch.empty((n, n, n), dtype=torch.float32), None) for n in sizes]
+    jobs = batch.BatchSolver._jobs(types.SimpleNamespace(lockstep={64: 4, 48: 2}), pairs)
+    flat = sorted(i for j in jobs for i in j)
+    assert flat == list(range(len(sizes)))
+    for j in jobs:
+        assert len({sizes[i] for i in j}) == 1
+        assert len(j) == 1 or sizes[j[0]] == 64
+    assert sorted(len(j) for j in jobs if sizes[j[0]] == 64) == [4, 4, 4]
+    work = [sum(sizes[i] ** 3 for i in j) for j in jobs]
+    assert work == sorted(work, reverse=True)
