@@ -93,7 +93,7 @@ def test_fullsize_transport_gradient_matvec(workload256):
 
 
 @pytest.mark.timeout(900)
-def test_fullsize_gn_solve_reaches_tolerance(workload256):
+def test_fullsize_gn_solve_reaches_tolerance(workload256, tmp_path):
     """The benchmark's solve (256^3 FP32 from v = 0, relative gradient
     5e-2): the oracle, evaluated at the velocity the GPU returns, confirms
     the gradient reduction, the reported mismatch and the objective."""
@@ -104,8 +104,13 @@ def test_fullsize_gn_solve_reaches_tolerance(workload256):
     mR_t, mR = as_input(mR0, dt)
     ctx = mireg.Context(g.n, reg=mireg.H1, div=mireg.DIV_NEAR, beta_v=5e-3, beta_w=1.0, dtype=dt)
     ctx.set_images(mT_t, mR_t)
+    log = tmp_path / "gn256.jsonl"
+    ctx.set_log_jsonl(str(log))
     v_t, rep = ctx.gn_solve(grad_rtol=5e-2, grad_atol=1e-6, max_gn=50, max_pcg=100)
+    ctx.set_log_jsonl(None)
     ctx.close()
+    hist = [json.loads(line) for line in log.read_text().splitlines()]
+    hist = [r for r in hist if r["event"] == "gn"]
     print("256^3 solve", rep, flush=True)
     assert rep["status"] == 1 and rep["gnorm_rel"] <= 5e-2
     R = core.Registration(workload_params(g), mT, mR)
@@ -126,19 +131,21 @@ def test_fullsize_gn_solve_reaches_tolerance(workload256):
     assert gk / g0 <= 5e-2 * 1.01
     assert abs(J - rep["J"]) <= 1e-3 * abs(J) and J < 0.1 * J0
     assert abs(mis - rep["mismatch_rel"]) <= 1e-3 * mis
-    check_against_oracle_solve(rep)
+    check_against_oracle_solve(rep, hist)
 
 
 ORACLE_GN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_gn_256.json")
 
 
-def check_against_oracle_solve(rep):
+def check_against_oracle_solve(rep, hist):
     """The GPU's FP32 solve against the oracle's FP64 solve of the same
     inputs (tests/golden/oracle_gn_256.json, written by
-    tests/golden/make_oracle_gn_256.py): the same stopping reason, GN
-    iterations within one, matvecs within 10% (FP32 rounding moves the PCG
-    stops of a few Newton steps), J0 and the gradient norm at v = 0 to
-    FP32 accuracy, and the end point (J, relative mismatch) within 1%."""
+    tests/golden/make_oracle_gn_256.py, about an hour on 8 host cores): the
+    same stopping reason and the same GN iterations, PDE-solve count and
+    line-search trials; matvecs within 2% (FP32 rounding could move the
+    stop of a PCG solve by an iteration; measured: identical, 162); J and
+    the gradient norm at every GN iterate to 1e-3 relative (measured
+    within 2e-4), and the end point (J, relative mismatch) to 1e-3."""
     if not os.path.exists(ORACLE_GN_256):
         print("no stored oracle solve (run tests/golden/make_oracle_gn_256.py)", flush=True)
         return
@@ -147,12 +154,22 @@ def check_against_oracle_solve(rep):
     print("oracle FP64 solve: %s" % {k: o[k] for k in ("status", "gn_iters", "matvecs", "pde_solves", "J0", "J",
                                                          "mismatch_rel", "gnorm_rel")}, flush=True)
     assert rep["status"] == o["status"]
-    assert abs(rep["gn_iters"] - o["gn_iters"]) <= 1
-    assert abs(rep["matvecs"] - o["matvecs"]) <= 0.1 * o["matvecs"]
+    for k in ("gn_iters", "ls_trials", "pde_solves"):
+        assert rep[k] == o[k], k
+    assert abs(rep["matvecs"] - o["matvecs"]) <= 0.02 * o["matvecs"]
     assert abs(rep["J0"] - o["J0"]) <= 1e-5 * o["J0"]
     assert abs(rep["gnorm0"] - o["gnorm0"]) <= 1e-4 * o["gnorm0"]
+    assert len(hist) == rep["gn_iters"]
+    worst = 0.0
+    for r, h in zip(hist, o["history"]):
+        for k in ("J", "gnorm"):
+            e = abs(r[k] - h[k]) / abs(h[k])
+            worst = max(worst, e)
+            assert e <= 1e-3, (r["iter"], k, r[k], h[k])
+    print("GN path against the oracle's: worst relative difference %.2e over %d iterates" % (worst, len(hist)),
+          flush=True)
     for k in ("J", "mismatch_rel"):
-        assert abs(rep[k] - o[k]) <= 1e-2 * abs(o[k]), k
+        assert abs(rep[k] - o[k]) <= 1e-3 * abs(o[k]), k
 
 
 def test_max_grid_properties():
