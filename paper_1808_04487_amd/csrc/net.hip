@@ -741,18 +741,25 @@ __global__ void k_voronoi(int lg, int ns, const float *__restrict__ seeds, const
 inline unsigned nblocks(size_t n, int t = kNetThreads) { return (unsigned)((n + t - 1) / t); }
 
 // ---- template dispatch over channel counts ----
-// The block-tiled kernel on cubic grids of 64^3 and up (at least 1024 tiles)
-// whose staged input fits 64 KB of LDS; k_conv otherwise, or always with
+// The block-tiled kernel on cubic grids of 32^3 and up whose staged input
+// fits 64 KB of LDS (taking the 32^3 level too, 128 tiles, moved the 128^3
+// forward pass from 0.756 to 0.737 ms, identical bits); k_conv otherwise, or always with
 // MIREG_CONV_TILE=0 in the environment (the two give identical results).
 inline bool conv_tile_enabled() {
     const char *e = getenv("MIREG_CONV_TILE");
     return !(e && e[0] == '0');
 }
+// Smallest grid (log2 of points per axis) that takes the block-tiled
+// convolution; MIREG_CONV_TILE_MIN_LG overrides it (for measurements).
+inline int conv_tile_min_lg() {
+    const char *e = getenv("MIREG_CONV_TILE_MIN_LG");
+    return e ? atoi(e) : 5;
+}
 template <int CIN, int COUT, bool UP, typename OT>
 void conv_go(ConvGeom g, const __bf16 *in, const __bf16 *W, const float *b, const __bf16 *res, int relu, OT *out,
              hipStream_t s) {
     if constexpr (ConvTile<CIN, UP>::BYTES <= 65536) {
-        if (g.lg >= 6 && conv_tile_enabled()) {
+        if (g.lg >= conv_tile_min_lg() && g.lg >= 4 && conv_tile_enabled()) {
             const unsigned ntiles = g.V / 256u;
             hipLaunchKernelGGL((k_conv_tile<CIN, COUT, UP, OT>), dim3(ntiles), dim3(kNetThreads), 0, s, g, in, W, b,
                                res, relu, out);
