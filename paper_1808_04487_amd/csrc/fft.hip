@@ -204,6 +204,7 @@ __device__ __forceinline__ T scalar_symbol(const Mode<T> &m, const OpConst<T> &o
             return ksq(m) == (T)0 ? (T)1 : (T)1 / s;  // zero singular value set to one
         }
         case SYM_LAP: return -ksq(m);
+        case SYM_GRADSQ: return m.t1 * m.t1 + m.t2 * m.t2 + m.t3 * m.t3;
         case SYM_GAUSS:
             return exp(-(oc.gs1 * m.k1 * m.k1 + oc.gs2 * m.k2 * m.k2 + oc.gs3 * m.k3 * m.k3));
         case SYM_AINV_SQRT: {

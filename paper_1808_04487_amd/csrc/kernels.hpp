@@ -46,7 +46,12 @@ enum SpecKind {
 // SYM_AINV_SQRT: (alpha a(k))^(-1/2), 1 at k = 0; SYM_HIGHPASS: 0 on the modes
 // a grid of half the size resolves below its Nyquist (|k_a| < n_a / 4 on every
 // axis), 1 elsewhere.
-enum SymKind { SYM_ID = 0, SYM_A = 1, SYM_AINV = 2, SYM_LAP = 3, SYM_GAUSS = 4, SYM_AINV_SQRT = 5, SYM_HIGHPASS = 6 };
+// SYM_GRADSQ: |kt|^2 with the odd-symbol wavenumbers of the spectral
+// gradient, so <u, SYM_GRADSQ u> = ||grad u||^2 by Parseval.
+enum SymKind {
+    SYM_ID = 0, SYM_A = 1, SYM_AINV = 2, SYM_LAP = 3, SYM_GAUSS = 4, SYM_AINV_SQRT = 5, SYM_HIGHPASS = 6,
+    SYM_GRADSQ = 7
+};
 
 struct SpecParams {
     int sym;        // SymKind for SPEC_SCALE

@@ -140,6 +140,8 @@ struct mireg_ctx {
 
     bool have_images = false;
     bool have_X = false, have_Y = false, have_state = false, have_gradm = false, have_d = false;
+    // grad m^0 = grad mT does not depend on the velocity: kept until the images change
+    bool have_gradm0 = false;
     SlBox box_X, box_Y;                    // stencil boxes of X and Y (largest, per tile)
     int *tbox_X = nullptr, *tbox_Y = nullptr;  // per-tile box storage of X and Y
     bool tile_boxes = true;  // hand the per-tile boxes to the transport kernels
@@ -393,9 +395,9 @@ void ensure_gradm(mireg_ctx *ctx) {
     if (ctx->have_gradm) return;
     ensure_state<T, S>(ctx);
     const long long N = ctx->N();
-    for (int j = 0; j <= ctx->p.nt; ++j)
+    for (int j = ctx->have_gradm0 ? 1 : 0; j <= ctx->p.nt; ++j)
         op_grad<T, S>(ctx, ctx->f<T>(ctx->m) + j * N, ctx->f<T>(ctx->gradm) + 3 * j * N);
-    ctx->have_gradm = true;
+    ctx->have_gradm = ctx->have_gradm0 = true;
 }
 template <typename T, typename S = T>
 void ensure_d(mireg_ctx *ctx) {
@@ -459,13 +461,27 @@ int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
     const double vAv = ctx->cell() * ctx->hres[0];
     double r = 0.5 * ctx->p.beta_v * vAv;
     if (ctx->p.div == MIREG_DIV_NEAR) {
-        // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2)
+        // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2), ||grad w||^2
+        // taken by Parseval from the spectrum of w with the spectral
+        // gradient's wavenumbers (one scalar pass instead of a gradient)
         ensure_d<T, S>(ctx);
-        T *gw = ctx->vec<T>(7);
-        op_grad<T, S>(ctx, ctx->f<T>(ctx->d), gw);
-        double a = 0, c = 0;
-        if ((rc = dot_h<T>(ctx, gw, gw, 3 * N, &a))) return rc;
-        if ((rc = dot_h<T>(ctx, ctx->f<T>(ctx->d), ctx->f<T>(ctx->d), N, &c))) return rc;
+        const T *d = ctx->f<T>(ctx->d);
+        T *tmp = ctx->vec<T>(7);
+        {
+            const void *in[1] = {d};
+            T *o[1] = {tmp};
+            SpecParams sp = spec_params<T>(ctx);
+            sp.sym = SYM_GRADSQ;
+            sp.nf = 1;
+            sp.alpha = 1.0;
+            sp.red = ctx->xpart;
+            sp.red_out = ctx->dres;
+            spec<T, S>(ctx, SPEC_SCALE, 1, 1, in, o, sp);
+        }
+        if ((rc = readback(ctx, 1))) return rc;
+        const double a = ctx->cell() * ctx->hres[0];
+        double c = 0;
+        if ((rc = dot_h<T>(ctx, d, d, N, &c))) return rc;
         r += 0.5 * ctx->p.beta_w * (a + c);
     }
     if (J) *J = mis + r;
@@ -715,7 +731,7 @@ void coarse_sync(mireg_ctx *ctx) {
         resample3<T>(ctx, c, ctx->f<T>(ctx->mT), c->f<T>(c->mT), 1);
         resample3<T>(ctx, c, ctx->f<T>(ctx->mR), c->f<T>(c->mR), 1);
         c->have_images = true;
-        c->have_state = c->have_gradm = false;
+        c->have_state = c->have_gradm = c->have_gradm0 = false;
         ctx->coarse_images = true;
     }
     if (ctx->coarse_vel_version != ctx->vel_version) {
@@ -1180,7 +1196,7 @@ int impl_set_images(mireg_ctx *ctx, const T *mT, const T *mR) {
     HIP_OK(hipMemcpyAsync(ctx->mT, mT, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->mR, mR, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     ctx->have_images = true;
-    ctx->have_state = ctx->have_gradm = false;
+    ctx->have_state = ctx->have_gradm = ctx->have_gradm0 = false;
     ctx->coarse_images = false;
     return MIREG_OK;
 }
