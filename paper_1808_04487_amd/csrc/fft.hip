@@ -337,6 +337,36 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
         }
         fft_line<T, L, V, +1, Lay>(acc, t, c, tw, 1, lds);
         store(0, acc);
+    } else if constexpr (KIND == SPEC_REG) {
+        // Regulariser of v by Parseval, nothing transformed back: per mode
+        // beta_v/2 a(k) sum_a |v_a|^2 and, for the near-incompressible model
+        // (w = div v = i kt . v eliminated), beta_w/2 (|kt|^2 + 1) |w|^2.
+        cx<T> w[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) w[e] = make_cx<T>(0, 0);
+        double pv = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            load(a, reg);
+            fft_line<T, L, V, -1, Lay>(reg, t, c, tw, 1, lds);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const Mode<T> m = mode(e);
+                const T ka = a == 0 ? m.t1 : (a == 1 ? m.t2 : m.t3);
+                pv += (double)reg_symbol(m, oc.reg) * ((double)reg[e].re * reg[e].re + (double)reg[e].im * reg[e].im);
+                w[e] = w[e] + scale(mul_i(reg[e]), ka);
+            }
+        }
+        double pw = 0;
+        if (oc.div == 1) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const Mode<T> m = mode(e);
+                const double kts = (double)m.t1 * m.t1 + (double)m.t2 * m.t2 + (double)m.t3 * m.t3;
+                pw += (kts + 1.0) * ((double)w[e].re * w[e].re + (double)w[e].im * w[e].im);
+            }
+        }
+        if (ok) dacc = wk3 * (double)oc.norm * (0.5 * (double)oc.beta_v * pv + 0.5 * (double)oc.beta_w * pw);
     } else {
         // SPEC_PROJ: K u for u in slots 0..2.
         // SPEC_TAIL: alpha A u + K b, u in slots 0..2, b in slots 3..5.
@@ -371,7 +401,7 @@ __global__ __launch_bounds__(kColThreads) void k_x1_op(FieldPtrs f, long long Q,
             store(a, reg);
         }
     }
-    if constexpr (KIND == SPEC_SCALE || KIND == SPEC_TAIL) {
+    if constexpr (KIND == SPEC_SCALE || KIND == SPEC_TAIL || KIND == SPEC_REG) {
         if (oc.red) {
             __shared__ double red_sh[NT / 64];
 #pragma unroll
@@ -827,7 +857,7 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
     oc.gs2 = (T)(0.5 * (two_pi * sp.sigma / g.n2) * (two_pi * sp.sigma / g.n2));
     oc.gs3 = (T)(0.5 * (two_pi * sp.sigma / g.n3) * (two_pi * sp.sigma / g.n3));
     oc.norm = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
-    oc.red = (kind == SPEC_SCALE || kind == SPEC_TAIL) ? sp.red : nullptr;
+    oc.red = (kind == SPEC_SCALE || kind == SPEC_TAIL || kind == SPEC_REG) ? sp.red : nullptr;
 
     launch_r2c<T>(g, fin, fspec, nin, tw.t[2], s);
     launch_x2<T, -1>(g, fspec, nin, tw.t[1], s);
@@ -837,14 +867,17 @@ void spectral_apply(const Grid &g, int kind, int nin, int nout, const void *cons
         case SPEC_GRAD: launch_x1<T, SPEC_GRAD>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         case SPEC_DIV: launch_x1<T, SPEC_DIV>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         case SPEC_PROJ: launch_x1<T, SPEC_PROJ>(g, fspec, nin, nout, oc, tw.t[0], s); break;
+        case SPEC_REG: blocks = launch_x1<T, SPEC_REG>(g, fspec, nin, nout, oc, tw.t[0], s); break;
         default: blocks = launch_x1<T, SPEC_TAIL>(g, fspec, nin, nout, oc, tw.t[0], s); break;
     }
     if (oc.red) {
         HookScope hs(K_REDUCE, 8.0 * blocks);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, blocks, oc.red, sp.red_out, nullptr);
     }
-    launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
-    launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
+    if (nout > 0) {
+        launch_x2<T, +1>(g, fspec, nout, tw.t[1], s);
+        launch_c2r<T>(g, fspec, fout, nout, tw.t[2], s);
+    }
 }
 
 // Destination half spectrum from the source one (both x1, x2, x3

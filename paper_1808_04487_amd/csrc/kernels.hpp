@@ -41,7 +41,8 @@ enum SpecKind {
     SPEC_GRAD = 1,   // 1 -> 3
     SPEC_DIV = 2,    // 3 -> 1
     SPEC_PROJ = 3,   // 3 -> 3, K
-    SPEC_TAIL = 4    // 6 -> 3, alpha A u + K b (u in slots 0..2, b in 3..5)
+    SPEC_TAIL = 4,   // 6 -> 3, alpha A u + K b (u in slots 0..2, b in 3..5)
+    SPEC_REG = 5     // 3 -> 0, only the reduction: the regulariser of v
 };
 // SYM_AINV_SQRT: (alpha a(k))^(-1/2), 1 at k = 0; SYM_HIGHPASS: 0 on the modes
 // a grid of half the size resolves below its Nyquist (|k_a| < n_a / 4 on every

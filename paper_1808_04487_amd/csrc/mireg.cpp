@@ -443,47 +443,20 @@ int impl_objective(mireg_ctx *ctx, double *J, double *mism, double *reg) {
     int rc = readback(ctx, 1);
     if (rc) return rc;
     const double mis = 0.5 * ctx->cell() * ctx->hres[0];
-    // beta_v/2 <A v, v>, the product taken from the spectra of the A pass
-    T *Av = ctx->vec<T>(7);
+    // the regulariser beta_v/2 <A v, v> (+ beta_w/2 (||grad w||^2 + ||w||^2)
+    // for the near-incompressible model, w = div v eliminated), by Parseval
+    // from one forward transform of v (nothing transformed back)
     {
         const T *v = ctx->f<T>(ctx->v);
         const void *in[3] = {v, v + N, v + 2 * N};
-        T *o[3] = {Av, Av + N, Av + 2 * N};
+        T *o[1] = {nullptr};
         SpecParams sp = spec_params<T>(ctx);
-        sp.sym = SYM_A;
-        sp.nf = 3;
-        sp.alpha = 1.0;
         sp.red = ctx->xpart;
         sp.red_out = ctx->dres;
-        spec<T, S>(ctx, SPEC_SCALE, 3, 3, in, o, sp);
+        spec<T, S>(ctx, SPEC_REG, 3, 0, in, o, sp);
     }
     if ((rc = readback(ctx, 1))) return rc;
-    const double vAv = ctx->cell() * ctx->hres[0];
-    double r = 0.5 * ctx->p.beta_v * vAv;
-    if (ctx->p.div == MIREG_DIV_NEAR) {
-        // w = div v eliminated: beta_w/2 (||grad w||^2 + ||w||^2), ||grad w||^2
-        // taken by Parseval from the spectrum of w with the spectral
-        // gradient's wavenumbers (one scalar pass instead of a gradient)
-        ensure_d<T, S>(ctx);
-        const T *d = ctx->f<T>(ctx->d);
-        T *tmp = ctx->vec<T>(7);
-        {
-            const void *in[1] = {d};
-            T *o[1] = {tmp};
-            SpecParams sp = spec_params<T>(ctx);
-            sp.sym = SYM_GRADSQ;
-            sp.nf = 1;
-            sp.alpha = 1.0;
-            sp.red = ctx->xpart;
-            sp.red_out = ctx->dres;
-            spec<T, S>(ctx, SPEC_SCALE, 1, 1, in, o, sp);
-        }
-        if ((rc = readback(ctx, 1))) return rc;
-        const double a = ctx->cell() * ctx->hres[0];
-        double c = 0;
-        if ((rc = dot_h<T>(ctx, d, d, N, &c))) return rc;
-        r += 0.5 * ctx->p.beta_w * (a + c);
-    }
+    const double r = ctx->cell() * ctx->hres[0];
     if (J) *J = mis + r;
     if (mism) *mism = mis;
     if (reg) *reg = r;
