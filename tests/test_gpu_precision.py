@@ -14,7 +14,7 @@ from gpu_util import as_input, need_gpu, rel_err, rel_err_l2, smooth_vector
 
 pytestmark = pytest.mark.gpu
 
-# spec bound on reduced-precision storage paths (relative, L2)
+# bound on the reduced-precision storage paths (relative, L2)
 TOL16 = 1e-3
 
 
