@@ -872,7 +872,7 @@ int two_level_spectral(mireg_ctx *ctx, double eps_h, double *rz) {
 // (the transport needs it on the grid).  Inner products come from Parseval.
 template <typename T, typename S = T>
 int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres,
-                      int *status, int *matvecs) {
+                      int *status, int *matvecs, bool rhs_is_minus_h = false) {
     const long long N = ctx->N();
     const double h3 = ctx->cell();
     T *s = ctx->vec<T>(2);
@@ -896,7 +896,11 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
     int rc;
     {
         Phase ph(ctx, 0);
-        krylov_forward<T>(ctx->g, rp, rh, work, tw, ctx->stream);  // r = rhs, x = 0
+        if (rhs_is_minus_h)  // rhs = -g and KV_H still holds the spectrum of g (the gradient's tail)
+            affine<T>(6 * ctx->g.NS, reinterpret_cast<const T *>(hh[0]), -1.0, 0.0, reinterpret_cast<T *>(rh[0]),
+                      ctx->stream);
+        else
+            krylov_forward<T>(ctx->g, rp, rh, work, tw, ctx->stream);  // r = rhs, x = 0
         fill<T>(6 * ctx->g.NS, (T)0, reinterpret_cast<T *>(xh[0]), ctx->stream);
         krylov_update<T>(ctx->g, false, 1, ctx->dres, rh, hh, sp, ctx->partials, ctx->stream);
     }
@@ -967,8 +971,8 @@ int impl_pcg_spectral(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit
 
 template <typename T, typename S = T>
 int impl_pcg(mireg_ctx *ctx, const T *rhs, T *x, double rtol, int maxit, int *iters, double *relres,
-             int *status = nullptr, int *matvecs = nullptr) {
-    return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres, status, matvecs);
+             int *status = nullptr, int *matvecs = nullptr, bool rhs_is_minus_h = false) {
+    return impl_pcg_spectral<T, S>(ctx, rhs, x, rtol, maxit, iters, relres, status, matvecs, rhs_is_minus_h);
 }
 
 // Autotuner: mean time of a PCG iteration (`reps` iterations from the
@@ -1074,7 +1078,10 @@ int impl_gn(mireg_ctx *ctx, T *v_io, const mireg_solve_opts *o, mireg_report *re
         T *rhs = ctx->vec<T>(7);
         affine<T>(n, g, -1.0, 0.0, rhs, ctx->stream);
         int its = 0, pst = 0, mv = 0;
-        if ((rc = impl_pcg<T, S>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr, &pst, &mv))) return rc;
+        // in FP32 contexts the gradient's tail leaves the spectrum of g in KV_H
+        // (untouched since): PCG starts from it instead of transforming -g again
+        constexpr bool ghat = std::is_same<T, float>::value;
+        if ((rc = impl_pcg<T, S>(ctx, rhs, vt, eps_h, o->max_pcg, &its, nullptr, &pst, &mv, ghat))) return rc;
         R.matvecs += mv;
         R.pcg_iters += its;
         R.pde_solves += 2 * mv;
